@@ -1,0 +1,219 @@
+/*
+ * tns.h - C ABI of the MI355X (gfx950) two-site effective-Hamiltonian library.
+ *
+ * The library applies sigma = H_eff psi, the matrix-vector product inside the
+ * Davidson diagonalisation of the paper's DMRG method (Section III.A.2,
+ * Eq. (2)): every term of the Hamiltonian, after the two single-site factors
+ * are reduced to scalars, adds alpha * L_i A R_i^T into one output sector of
+ * the wavefunction, A being an input sector, L_i a left-block operator block,
+ * R_i a right-block operator block and alpha a precalculated scalar.  The
+ * library builds the sector and task tables of the paper's four-level
+ * hierarchy (Section III.A.1, levels 1-2) on the device, executes them with
+ * hand-written MFMA kernels (level 3), and offers the Davidson iteration and
+ * a backward pass on top.
+ *
+ * Conventions shared with the callers
+ * -----------------------------------
+ * - Quantum numbers are (N, 2Sz) pairs; sector tables are sorted ascending.
+ * - Site states: 0 = empty, 1 = up, 2 = down, 3 = up-down, with (N, 2Sz) =
+ *   (0,0), (1,1), (1,-1), (2,0).  Site monomials have id 4*u + d, u and d in
+ *   {0: 1, 1: n, 2: c+, 3: c}, the up factor to the left; within a site the
+ *   up mode precedes the down mode in Jordan-Wigner order.
+ * - The product state |l, sa, sb, r> = C_l C_a C_b C_r |0>; a term
+ *   c * O_L O_a O_b O_R carries the sign
+ *   (-1)^(pa*Nl + pb*(Nl+Na) + pR*(Nl+Na+Nb)) with the operator parities p and
+ *   the particle numbers N of the *input* state.
+ * - Wavefunction sectors (iL, sa, sb, iR) are listed in ascending
+ *   (iL, sa, sb) order; sector s is a dimL[iL] x dimR[iR] row-major matrix at
+ *   element offset psi_off[s].  sigma has the same layout.
+ * - Operator blocks are row-major matrices (rows = dimension of the output
+ *   sector, cols = dimension of the input sector) at element offset blk_off
+ *   with leading dimension blk_ld (>= cols) in one value array.  An operator
+ *   has at most one block per input sector, mapping in -> in + shift.
+ * - Terms are (op_L, mono_a, mono_b, op_R, coef); op id -1 is the identity.
+ *
+ * Ownership and errors
+ * --------------------
+ * The library allocates no memory: every device buffer, including the
+ * workspaces whose sizes the *_workspace_bytes queries return, belongs to the
+ * caller and must outlive the calls that use it.  No exception crosses the
+ * ABI; every entry point returns a tns_status.  Host-side validation happens
+ * before any launch, so an error status means that nothing was enqueued,
+ * except for TNS_ERR_HIP (a HIP call failed; the stream state is unknown).
+ * Calls are asynchronous on the given stream unless stated otherwise.
+ */
+#ifndef TNS_H
+#define TNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TNS_OK = 0,
+  TNS_ERR_ARG = -1,           /* null pointer, negative count, bad enum       */
+  TNS_ERR_SHAPE = -2,         /* inconsistent dimensions or offsets           */
+  TNS_ERR_QN = -3,            /* quantum numbers not conserved                */
+  TNS_ERR_WORKSPACE = -4,     /* workspace smaller than required              */
+  TNS_ERR_HIP = -5,           /* a HIP runtime call failed                    */
+  TNS_ERR_NUMERIC = -6,       /* non-finite value detected (Davidson)         */
+  TNS_ERR_NOT_CONVERGED = -7  /* Davidson hit max_iter                        */
+} tns_status;
+
+typedef enum {
+  TNS_F64 = 0,     /* FP64 operands, FP64 MFMA, FP64 accumulation                     */
+  TNS_F32 = 1,     /* FP32 operands, FP32 MFMA, FP32 accumulation per output tile     */
+  TNS_BF16X3 = 2   /* split BF16 operands (hi + lo), three BF16 MFMA products          */
+                   /* (lo*hi + hi*lo + hi*hi) with FP32 accumulation                  */
+} tns_prec;
+
+/* One two-site problem.  All pointers are HOST pointers to small index tables
+ * (read only during tns_build_tasklist, which validates them and copies them
+ * into the device workspace).  Operator values are passed separately, as
+ * device pointers, to the compute calls. */
+typedef struct {
+  int32_t nL, nR;            /* left / right block sector counts                    */
+  int32_t nS;                /* wavefunction sector count                           */
+  int32_t nOps, nBlk, nTerms;
+  int32_t target_N, target_2Sz;
+  int64_t n_vals;            /* length (elements) of the operator value array       */
+  const int32_t *qL;         /* [nL][2] (N, 2Sz)                                     */
+  const int32_t *dimL;       /* [nL]                                                 */
+  const int32_t *qR;         /* [nR][2]                                              */
+  const int32_t *dimR;       /* [nR]                                                 */
+  const int32_t *psi_sec;    /* [nS][4] (iL, sa, sb, iR), ascending (iL, sa, sb)     */
+  const int64_t *psi_off;    /* [nS+1]                                               */
+  const int32_t *op_side;    /* [nOps] 0 = left block, 1 = right block               */
+  const int32_t *op_dN;      /* [nOps] shift of N                                    */
+  const int32_t *op_d2Sz;    /* [nOps] shift of 2Sz                                  */
+  const int32_t *blk_op;     /* [nBlk] owning operator                               */
+  const int32_t *blk_in;     /* [nBlk] input sector                                  */
+  const int32_t *blk_out;    /* [nBlk] output sector (= in + shift)                  */
+  const int32_t *blk_rows;   /* [nBlk] = dim(out)                                    */
+  const int32_t *blk_cols;   /* [nBlk] = dim(in)                                     */
+  const int32_t *blk_ld;     /* [nBlk] >= cols                                       */
+  const int64_t *blk_off;    /* [nBlk] element offset into the value array           */
+  const int32_t *term_L;     /* [nTerms] left operator or -1                         */
+  const int32_t *term_ma;    /* [nTerms] site-a monomial 0..15                       */
+  const int32_t *term_mb;    /* [nTerms] site-b monomial 0..15                       */
+  const int32_t *term_R;     /* [nTerms] right operator or -1                        */
+  const double  *term_coef;  /* [nTerms]                                             */
+} tns_problem;
+
+/* One task of the task table (Section III.A.1, level 2): 40 bytes.
+ * alpha = ((coef * a) * b) * sign in FP64 (a, b = site matrix elements).
+ * cost  = flops of the cheaper evaluation order of the chain L A R^T
+ * (Section III.B): 2qn(m+r) for (L A) R^T, 2mr(n+q) for L (A R^T), with q, m
+ * the output / input left dimensions and r, n the output / input right
+ * dimensions; order = 1 only if the second is strictly cheaper.  An identity
+ * side drops its product (2mnr or 2qmn; 2mn if both are identities).  The
+ * table is sorted by output sector, keeping term order inside a sector. */
+typedef struct {
+  int32_t out, in, term, lblk, rblk, order;
+  double alpha;
+  int64_t cost;
+} tns_task;
+
+/* Result of tns_build_tasklist.  Counts are host values; tasks and out_ptr are
+ * device views into the build workspace; `opaque` holds the library's
+ * schedule (device pointers into the same workspace). */
+typedef struct {
+  int64_t ntasks;         /* number of tasks                                        */
+  int64_t nitems;         /* work items of the persistent kernel                    */
+  int64_t nslots;         /* partial-result slots                                   */
+  int64_t partial_elems;  /* elements of the partial buffer                         */
+  int64_t total_flops;    /* sum of task costs (algorithmic flops per application)  */
+  int64_t psi_dim;        /* elements of psi / sigma                                */
+  const tns_task *tasks;  /* device [ntasks]                                        */
+  const int32_t *out_ptr; /* device [nS+1] CSR over output sectors                  */
+  uint8_t opaque[2048];
+} tns_tasklist;
+
+/* Bytes of device workspace tns_build_tasklist needs for this problem (host
+ * only, no device call except a query of the device's compute-unit count).
+ * Returns 0 when the problem fails host validation. */
+size_t tns_tasklist_workspace_bytes(const tns_problem *prob);
+
+/* Levels 1-2 of Section III.A.1 on the device: validates the problem on the
+ * host (shapes, ranges, quantum-number conservation of every block and every
+ * term), copies the tables into `ws`, enumerates every (term, input sector)
+ * pair that yields a contribution, sorts them by output sector (term order
+ * inside a sector), and builds the work schedules of the persistent kernels
+ * (output row panels x task chunks, longest first) for the forward product
+ * and for its backward.  Synchronises the stream twice to read counts.
+ * `ws` must stay untouched while `out` is in use. */
+tns_status tns_build_tasklist(const tns_problem *prob, void *ws, size_t ws_bytes,
+                              tns_tasklist *out, hipStream_t stream);
+
+/* Device workspace bytes of tns_apply_heff for a precision. */
+size_t tns_apply_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
+
+/* Convert FP64 operator values (device, n elements) into the operand format of
+ * `prec`: TNS_F64 copies, TNS_F32 rounds to float (`out` = float[n]),
+ * TNS_BF16X3 writes hi = bf16(x) then lo = bf16(x - hi) (round to nearest
+ * even each), `out` = uint16[2n] (n hi values followed by n lo values). */
+tns_status tns_prepare_operands(tns_prec prec, const double *vals64, int64_t n, void *out,
+                                hipStream_t stream);
+
+/* Level 3, Eq. (2): sigma := beta * sigma + H_eff psi for beta in {0, 1}
+ * (beta = 1 is the accumulate form B := B + alpha sum L_i A R_i^T).
+ * op_vals: operands from tns_prepare_operands (device).  psi, sigma: device,
+ * psi_dim elements of double (TNS_F64) or float (TNS_F32, TNS_BF16X3).
+ * Deterministic: every output element is summed in a fixed order. */
+tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
+                          const void *psi, void *sigma, double beta, void *ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Backward of tns_apply_heff for a loss with G = d loss / d sigma:
+ * grad_psi   = sum_tasks alpha L^T G_out R            (psi layout; nullable)
+ * grad_ops   = sum_tasks alpha G_out R A^T into L,    (operator-value layout,
+ *              alpha G_out^T L A into R                 padding untouched; nullable)
+ * Both outputs are overwritten (not accumulated).  FP32 and FP64 only. */
+size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
+tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
+                                   const void *psi, const void *grad_sigma, void *grad_psi,
+                                   void *grad_ops, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Davidson iteration for the lowest eigenpair (Section III: the effective
+ * Hamiltonian is diagonalised with Davidson's method).  Vectors, projections,
+ * Rayleigh-Ritz, residuals and the diagonal preconditioner are FP64 on the
+ * device; the matrix-vector products run in `inner` precision.  With
+ * refine != 0 and inner != TNS_F64, each inner convergence is followed by an
+ * FP64 product w = H x, theta = <x, w>, r = w - theta x, and the inner
+ * iteration restarts from (x, w) until |r| <= tol_res.  The reported energy
+ * is the FP64 Rayleigh quotient. */
+typedef struct {
+  int32_t max_sub;     /* subspace size before restart (<= 64)   */
+  int32_t keep;        /* Ritz vectors kept at restart           */
+  int32_t max_iter;    /* total products in inner precision      */
+  int32_t refine;      /* FP64 residual-correction rounds        */
+  double tol_res;      /* residual 2-norm                         */
+  double tol_e;        /* energy change between iterations       */
+  tns_prec inner;
+} tns_davidson_opts;
+
+typedef struct {
+  int32_t iters, matvecs_lo, matvecs_f64;
+  double res_norm;     /* final FP64 residual norm                */
+  double e_lo;         /* last inner-precision Ritz value         */
+} tns_davidson_info;
+
+size_t tns_davidson_workspace_bytes(const tns_tasklist *tl, const tns_davidson_opts *opts);
+/* op_vals_lo: operands for opts->inner; op_vals_f64: FP64 values (may equal
+ * op_vals_lo when inner == TNS_F64).  psi_inout: FP64 start vector (device),
+ * overwritten by the eigenvector.  energy: host.  One scalar readback per
+ * iteration synchronises the stream. */
+tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_opts *opts, const void *op_vals_lo,
+                        const double *op_vals_f64, double *psi_inout, double *energy,
+                        tns_davidson_info *info, void *ws, size_t ws_bytes, hipStream_t stream);
+
+const char *tns_status_string(tns_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNS_H */

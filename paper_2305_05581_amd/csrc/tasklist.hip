@@ -1,0 +1,705 @@
+// Levels 1-2 of the four-level hierarchy (Section III.A.1) on the device:
+// sector lookups, the task table of Eq. (2) in canonical order, and the work
+// schedule of the persistent H_eff kernel.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <vector>
+
+#include "tns_internal.hpp"
+
+namespace tns {
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Exclusive scan of n int64 values into out[0..n] (out[n] = total); one
+// workgroup of 1024 threads walks the array in tiles.
+__global__ __launch_bounds__(1024) void k_scan_i64(const int64_t *__restrict__ in, int64_t *__restrict__ out,
+                                                   int64_t n) {
+  __shared__ int64_t sh[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += 1024) {
+    int64_t i = base + threadIdx.x;
+    int64_t v = (i < n) ? in[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int64_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < n) out[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+tns_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, in, out, n);
+  return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// lookups
+// ---------------------------------------------------------------------------
+
+__global__ void k_psi_index(Plan p) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.nS) return;
+  const int32_t *e = p.psi_sec + 4 * s;
+  p.psi_index[(e[0] * 4 + e[1]) * 4 + e[2]] = s;
+}
+
+__global__ void k_blk_of_out(Plan p) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= p.nBlk) return;
+  p.blk_of_out[(int64_t)p.blk_op[b] * p.nmax + p.blk_out[b]] = b;
+}
+
+// ---------------------------------------------------------------------------
+// task table: one wave per output sector, lanes over terms.  For an output
+// sector and a term there is at most one input sector (each operator block
+// and each monomial maps inputs to outputs injectively), so gathering per
+// output sector in term order yields the canonical order directly.
+// ---------------------------------------------------------------------------
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_tasks(Plan p) {
+  const int lane = threadIdx.x & 63;
+  const int so = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (so >= p.nS) return;
+  const int jL = p.psi_sec[4 * so + 0], ta = p.psi_sec[4 * so + 1];
+  const int tb = p.psi_sec[4 * so + 2], jR = p.psi_sec[4 * so + 3];
+  int64_t base = FILL ? p.out_ptr[so] : 0;
+  int count = 0;
+  for (int k0 = 0; k0 < p.nTerms; k0 += 64) {
+    const int k = k0 + lane;
+    bool ok = false;
+    int iL = 0, iR = 0, sa = 0, sb = 0, lb = -1, rb = -1, va = 0, vb = 0, si = -1;
+    int oL = -1, oR = -1, ma = 0, mb = 0;
+    if (k < p.nTerms) {
+      oL = p.term_L[k]; oR = p.term_R[k]; ma = p.term_ma[k]; mb = p.term_mb[k];
+      ok = true;
+      if (oL >= 0) {
+        lb = p.blk_of_out[(int64_t)oL * p.nmax + jL];
+        if (lb < 0) ok = false; else iL = p.blk_in[lb];
+      } else {
+        iL = jL;
+      }
+      if (ok) {
+        sa = -1;
+        for (int s = 0; s < 4; ++s) { int v; if (mono_apply(ma, s, &v) == ta) { sa = s; va = v; } }
+        sb = -1;
+        for (int s = 0; s < 4; ++s) { int v; if (mono_apply(mb, s, &v) == tb) { sb = s; vb = v; } }
+        if (sa < 0 || sb < 0) ok = false;
+      }
+      if (ok) {
+        if (oR >= 0) {
+          rb = p.blk_of_out[(int64_t)oR * p.nmax + jR];
+          if (rb < 0) ok = false; else iR = p.blk_in[rb];
+        } else {
+          iR = jR;
+        }
+      }
+      if (ok) {
+        si = p.psi_index[(iL * 4 + sa) * 4 + sb];
+        if (si < 0 || p.psi_sec[4 * si + 3] != iR) ok = false;
+      }
+    }
+    const uint64_t bal = __ballot(ok);
+    if (FILL && ok) {
+      const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+      tns_task t;
+      t.out = so; t.in = si; t.term = k; t.lblk = lb; t.rblk = rb;
+      const int Nl = p.qL[2 * iL], Na = site_N(sa), Nb = site_N(sb);
+      const int pa = mono_parity(ma), pb = mono_parity(mb);
+      const int pR = (oR >= 0) ? (abs(p.op_dN[oR]) & 1) : 0;
+      const int e = pa * Nl + pb * (Nl + Na) + pR * (Nl + Na + Nb);
+      const double sgn = (e & 1) ? -1.0 : 1.0;
+      const double c = p.term_coef[k];
+      t.alpha = ((c * (double)va) * (double)vb) * sgn;
+      const int64_t q = p.dimL[jL], m = p.dimL[iL], n = p.dimR[iR], r = p.dimR[jR];
+      if (oL >= 0 && oR >= 0) {
+        const int64_t c0 = 2 * q * n * (m + r), c1 = 2 * m * r * (n + q);
+        if (c1 < c0) { t.order = 1; t.cost = c1; } else { t.order = 0; t.cost = c0; }
+      } else if (oL >= 0) {
+        t.order = 0; t.cost = 2 * q * m * n;
+      } else if (oR >= 0) {
+        t.order = 0; t.cost = 2 * m * n * r;
+      } else {
+        t.order = 0; t.cost = 2 * m * n;
+      }
+      p.tasks[base + count + rank] = t;
+    }
+    count += __popcll(bal);
+  }
+  if (!FILL && lane == 0) p.scan_tmp[so] = count;
+}
+
+// Forward groups: per output sector, class-0 tasks then class-1 tasks
+// (canonical order kept inside each class).  Group 2s + c holds class c of
+// sector s; its output is sigma_s (c = 0) or sigma_s^T (c = 1).
+__global__ __launch_bounds__(256) void k_fwd_groups(Plan p, Sched S) {
+  const int lane = threadIdx.x & 63;
+  const int so = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (so >= p.nS) return;
+  const int t0 = p.out_ptr[so], t1 = p.out_ptr[so + 1];
+  int n0 = 0;
+  for (int b = t0; b < t1; b += 64) {
+    const int t = b + lane;
+    const int ord = (t < t1) ? p.tasks[t].order : -1;
+    const uint64_t bal = __ballot(ord == 0);
+    if (ord == 0) S.idx[t0 + n0 + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+    n0 += __popcll(bal);
+  }
+  int n1 = 0;
+  for (int b = t0; b < t1; b += 64) {
+    const int t = b + lane;
+    const int ord = (t < t1) ? p.tasks[t].order : -1;
+    const uint64_t bal = __ballot(ord == 1);
+    if (ord == 1) S.idx[t0 + n0 + n1 + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+    n1 += __popcll(bal);
+  }
+  if (lane == 0) {
+    const int q = p.dimL[p.psi_sec[4 * so]], r = p.dimR[p.psi_sec[4 * so + 3]];
+    S.grp_begin[2 * so] = t0;
+    S.grp_n[2 * so] = n0;
+    S.grp_rows[2 * so] = q;
+    S.grp_cols[2 * so] = r;
+    S.grp_out[2 * so] = so;
+    S.grp_mode[2 * so] = M_FWD0;
+    S.grp_begin[2 * so + 1] = t0 + n0;
+    S.grp_n[2 * so + 1] = n1;
+    S.grp_rows[2 * so + 1] = r;
+    S.grp_cols[2 * so + 1] = q;
+    S.grp_out[2 * so + 1] = so;
+    S.grp_mode[2 * so + 1] = M_FWD1;
+  }
+}
+
+// Flops of one task evaluated in a mode (used for load balance).
+__device__ inline int64_t mode_cost(const Plan &p, const tns_task &t, int mode) {
+  if (mode <= M_FWD1) return t.cost;
+  const int64_t q = p.dimL[p.psi_sec[4 * t.out]], r = p.dimR[p.psi_sec[4 * t.out + 3]];
+  const int64_t m = p.dimL[p.psi_sec[4 * t.in]], n = p.dimR[p.psi_sec[4 * t.in + 3]];
+  if (mode == M_DPSI) return 2 * m * q * r + 2 * m * r * n;
+  if (mode == M_DL) return 2 * q * r * n + 2 * q * n * m;
+  return 2 * r * q * m + 2 * r * m * n;
+}
+
+// Summed cost per group (one wave per group) and the schedule total.
+__global__ __launch_bounds__(256) void k_group_cost(Plan p, Sched S) {
+  const int lane = threadIdx.x & 63;
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= S.ngroups) return;
+  const int b = S.grp_begin[g], n = S.grp_n[g], mode = S.grp_mode[g];
+  int64_t c = 0;
+  for (int i = lane; i < n; i += 64) c += mode_cost(p, p.tasks[S.idx[b + i]], mode);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane == 0) {
+    S.grp_cost[g] = c;
+    atomicAdd((unsigned long long *)&S.scalars[0], (unsigned long long)c);
+  }
+}
+
+// Greedy task chunks per group: a chunk closes before the task that would
+// push it over cap = target_item_cost * panels (each chunk is then cut into
+// row panels of TQ rows, so items cost about target_item_cost each).
+template <bool FILL>
+__global__ void k_chunks(Plan p, Sched S) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= S.ngroups) return;
+  const int n = S.grp_n[g];
+  int nc = 0;
+  if (n > 0) {
+    const int64_t total = S.scalars[0];
+    const int64_t target = total / ((int64_t)ITEMS_PER_CU * p.n_cu) + 1;
+    const int npan = (S.grp_rows[g] + TQ - 1) / TQ;
+    const int64_t cap = target * npan;
+    const int b = S.grp_begin[g], mode = S.grp_mode[g];
+    int64_t cur = 0;
+    int start = b;
+    const int64_t cb = FILL ? S.grp_chunk_base[g] : 0;
+    for (int i = b; i < b + n; ++i) {
+      const int64_t c = mode_cost(p, p.tasks[S.idx[i]], mode);
+      if (i > start && cur + c > cap) {
+        if (FILL) { Chunk ch{g, start, i, 0, cur}; S.chunks[cb + nc] = ch; }
+        ++nc;
+        start = i;
+        cur = 0;
+      }
+      cur += c;
+    }
+    if (FILL) { Chunk ch{g, start, b + n, 0, cur}; S.chunks[cb + nc] = ch; }
+    ++nc;
+  }
+  if (!FILL) S.scratch[g] = nc;
+}
+
+// Per chunk: partial-slot size (rows * cols of its output) and item count.
+__global__ void k_chunk_sizes(Sched S, int64_t *slot_sz, int64_t *item_n) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= S.chunks_cap) return;
+  const int64_t nch = S.grp_chunk_base[S.ngroups];
+  if (c >= nch) { slot_sz[c] = 0; item_n[c] = 0; return; }
+  const int g = S.chunks[c].grp;
+  slot_sz[c] = (int64_t)S.grp_rows[g] * S.grp_cols[g];
+  item_n[c] = (S.grp_rows[g] + TQ - 1) / TQ;
+}
+
+__global__ void k_items(Sched S) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nch = S.grp_chunk_base[S.ngroups];
+  if (c >= nch) return;
+  const Chunk ch = S.chunks[c];
+  const int rows = S.grp_rows[ch.grp];
+  const int npan = (rows + TQ - 1) / TQ;
+  const int64_t ib = S.chunk_item_base[c];
+  for (int k = 0; k < npan; ++k) {
+    Item it;
+    it.grp = ch.grp;
+    it.mode = S.grp_mode[ch.grp];
+    it.p0 = k * TQ;
+    it.np = min(TQ, rows - k * TQ);
+    it.tb = ch.tb;
+    it.te = ch.te;
+    it.slot = (int32_t)c;
+    it.out = S.grp_out[ch.grp];
+    it.cost = ch.cost * it.np / rows;
+    S.items_unsorted[ib + k] = it;
+  }
+}
+
+__global__ void k_sort_keys(Sched S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.items_cap) return;
+  const int64_t nit = S.chunk_item_base[S.grp_chunk_base[S.ngroups]];
+  // ascending key = descending cost; padding entries sort last
+  S.keys_in[i] = (i < nit) ? (~(uint64_t)S.items_unsorted[i].cost - 1ull) : ~0ull;
+  S.vals_in[i] = (int32_t)i;
+}
+
+__global__ void k_gather_items(Sched S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nit = S.chunk_item_base[S.grp_chunk_base[S.ngroups]];
+  if (i >= nit) return;
+  S.items[i] = S.items_unsorted[S.vals_out[i]];
+}
+
+__global__ void k_sched_totals(Sched S) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t nch = S.grp_chunk_base[S.ngroups];
+  S.scalars[1] = nch;
+  S.scalars[2] = S.chunk_item_base[nch];
+  S.scalars[3] = S.slot_off[nch];
+}
+
+// Backward grouping: three (key, task) entries per task -- input sector,
+// left block, right block (keys offset by nS); absent entries get INT_MAX.
+__global__ void k_bwd_keys(Plan p, int64_t ntasks) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  const tns_task tk = p.tasks[t];
+  p.bkeys_in[3 * t + 0] = tk.in;
+  p.bkeys_in[3 * t + 1] = tk.lblk >= 0 ? p.nS + tk.lblk : 0x7fffffff;
+  p.bkeys_in[3 * t + 2] = tk.rblk >= 0 ? p.nS + tk.rblk : 0x7fffffff;
+  p.bvals_in[3 * t + 0] = (int32_t)t;
+  p.bvals_in[3 * t + 1] = (int32_t)t;
+  p.bvals_in[3 * t + 2] = (int32_t)t;
+}
+
+__global__ void k_bwd_count(Plan p, Sched S, int64_t nent) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nent) return;
+  const int k = p.bkeys_out[e];
+  if (k != 0x7fffffff) atomicAdd((unsigned long long *)&S.scratch[k], 1ull);
+}
+
+__global__ void k_bwd_groups(Plan p, Sched S) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= S.ngroups) return;
+  S.grp_begin[g] = (int32_t)S.grp_chunk_base[g];  // scan of counts (reused buffer)
+  S.grp_n[g] = (int32_t)(S.grp_chunk_base[g + 1] - S.grp_chunk_base[g]);
+  if (g < p.nS) {
+    S.grp_rows[g] = p.dimL[p.psi_sec[4 * g]];
+    S.grp_cols[g] = p.dimR[p.psi_sec[4 * g + 3]];
+    S.grp_out[g] = g;
+    S.grp_mode[g] = M_DPSI;
+  } else {
+    const int b = g - p.nS;
+    S.grp_rows[g] = p.blk_rows[b];
+    S.grp_cols[g] = p.blk_cols[b];
+    S.grp_out[g] = b;
+    S.grp_mode[g] = p.op_side[p.blk_op[b]] ? M_DR : M_DL;
+  }
+}
+
+__global__ void k_copy_i32(const int32_t *a, int32_t *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void k_i32_to_i64(const int32_t *a, int64_t *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+__global__ void k_i64_to_i32(const int64_t *a, int32_t *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+static tns_status validate(const tns_problem *P, int32_t *nmax_out, int32_t *maxdim_out) {
+  if (!P) return TNS_ERR_ARG;
+  if (P->nL <= 0 || P->nR <= 0 || P->nS < 0 || P->nOps < 0 || P->nBlk < 0 || P->nTerms < 0 || P->n_vals < 0)
+    return TNS_ERR_ARG;
+  if (!P->qL || !P->dimL || !P->qR || !P->dimR || !P->psi_off) return TNS_ERR_ARG;
+  if (P->nS > 0 && !P->psi_sec) return TNS_ERR_ARG;
+  if (P->nOps > 0 && (!P->op_side || !P->op_dN || !P->op_d2Sz)) return TNS_ERR_ARG;
+  if (P->nBlk > 0 && (!P->blk_op || !P->blk_in || !P->blk_out || !P->blk_rows || !P->blk_cols || !P->blk_ld ||
+                      !P->blk_off))
+    return TNS_ERR_ARG;
+  if (P->nTerms > 0 && (!P->term_L || !P->term_ma || !P->term_mb || !P->term_R || !P->term_coef))
+    return TNS_ERR_ARG;
+  int32_t maxdim = 1;
+  for (int i = 0; i < P->nL; ++i) { if (P->dimL[i] <= 0) return TNS_ERR_SHAPE; maxdim = std::max(maxdim, P->dimL[i]); }
+  for (int i = 0; i < P->nR; ++i) { if (P->dimR[i] <= 0) return TNS_ERR_SHAPE; maxdim = std::max(maxdim, P->dimR[i]); }
+  for (int i = 1; i < P->nL; ++i)
+    if (P->qL[2 * i] < P->qL[2 * i - 2] || (P->qL[2 * i] == P->qL[2 * i - 2] && P->qL[2 * i + 1] <= P->qL[2 * i - 1]))
+      return TNS_ERR_QN;
+  for (int i = 1; i < P->nR; ++i)
+    if (P->qR[2 * i] < P->qR[2 * i - 2] || (P->qR[2 * i] == P->qR[2 * i - 2] && P->qR[2 * i + 1] <= P->qR[2 * i - 1]))
+      return TNS_ERR_QN;
+  // wavefunction sectors: valid, conserving, strictly ascending, packed
+  if (P->psi_off[0] != 0) return TNS_ERR_SHAPE;
+  for (int s = 0; s < P->nS; ++s) {
+    const int32_t *e = P->psi_sec + 4 * s;
+    if (e[0] < 0 || e[0] >= P->nL || e[1] < 0 || e[1] > 3 || e[2] < 0 || e[2] > 3 || e[3] < 0 || e[3] >= P->nR)
+      return TNS_ERR_SHAPE;
+    const int N = P->qL[2 * e[0]] + site_N(e[1]) + site_N(e[2]) + P->qR[2 * e[3]];
+    const int S = P->qL[2 * e[0] + 1] + site_2Sz(e[1]) + site_2Sz(e[2]) + P->qR[2 * e[3] + 1];
+    if (N != P->target_N || S != P->target_2Sz) return TNS_ERR_QN;
+    if (s > 0) {
+      const int32_t *f = e - 4;
+      const int64_t ka = ((int64_t)f[0] * 4 + f[1]) * 4 + f[2], kb = ((int64_t)e[0] * 4 + e[1]) * 4 + e[2];
+      if (kb <= ka) return TNS_ERR_SHAPE;
+    }
+    if (P->psi_off[s + 1] - P->psi_off[s] != (int64_t)P->dimL[e[0]] * P->dimR[e[3]]) return TNS_ERR_SHAPE;
+  }
+  // operators and blocks
+  for (int o = 0; o < P->nOps; ++o)
+    if (P->op_side[o] != 0 && P->op_side[o] != 1) return TNS_ERR_ARG;
+  std::vector<int> seen;  // (op, in) uniqueness
+  const int nmax = std::max(P->nL, P->nR);
+  seen.assign((size_t)P->nOps * nmax, 0);
+  for (int b = 0; b < P->nBlk; ++b) {
+    const int o = P->blk_op[b];
+    if (o < 0 || o >= P->nOps) return TNS_ERR_SHAPE;
+    const int side = P->op_side[o];
+    const int ns = side ? P->nR : P->nL;
+    const int32_t *q = side ? P->qR : P->qL;
+    const int32_t *dim = side ? P->dimR : P->dimL;
+    const int i = P->blk_in[b], j = P->blk_out[b];
+    if (i < 0 || i >= ns || j < 0 || j >= ns) return TNS_ERR_SHAPE;
+    if (q[2 * j] != q[2 * i] + P->op_dN[o] || q[2 * j + 1] != q[2 * i + 1] + P->op_d2Sz[o]) return TNS_ERR_QN;
+    if (P->blk_rows[b] != dim[j] || P->blk_cols[b] != dim[i] || P->blk_ld[b] < P->blk_cols[b]) return TNS_ERR_SHAPE;
+    if (P->blk_off[b] < 0 || P->blk_off[b] + (int64_t)(P->blk_rows[b] - 1) * P->blk_ld[b] + P->blk_cols[b] > P->n_vals)
+      return TNS_ERR_SHAPE;
+    if (seen[(size_t)o * nmax + i]++) return TNS_ERR_SHAPE;
+  }
+  // terms conserve (N, 2Sz)
+  for (int k = 0; k < P->nTerms; ++k) {
+    const int oL = P->term_L[k], oR = P->term_R[k], ma = P->term_ma[k], mb = P->term_mb[k];
+    if (ma < 0 || ma > 15 || mb < 0 || mb > 15) return TNS_ERR_ARG;
+    if (oL < -1 || oL >= P->nOps || oR < -1 || oR >= P->nOps) return TNS_ERR_ARG;
+    if ((oL >= 0 && P->op_side[oL] != 0) || (oR >= 0 && P->op_side[oR] != 1)) return TNS_ERR_ARG;
+    int dN = 0, dS = 0, a, c;
+    mono_shift(ma, &a, &c); dN += a; dS += c;
+    mono_shift(mb, &a, &c); dN += a; dS += c;
+    if (oL >= 0) { dN += P->op_dN[oL]; dS += P->op_d2Sz[oL]; }
+    if (oR >= 0) { dN += P->op_dN[oR]; dS += P->op_d2Sz[oR]; }
+    if (dN != 0 || dS != 0) return TNS_ERR_QN;
+  }
+  *nmax_out = nmax;
+  *maxdim_out = maxdim;
+  return TNS_OK;
+}
+
+static int device_cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+static size_t radix_tmp_u64(int64_t n) {
+  size_t tmp = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                           (const int32_t *)nullptr, (int32_t *)nullptr, (int)n);
+  return tmp;
+}
+static size_t radix_tmp_i32(int64_t n) {
+  size_t tmp = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                           (const int32_t *)nullptr, (int32_t *)nullptr, (int)n);
+  return tmp;
+}
+
+// Carves one schedule's arrays; `idx` may be supplied by the caller.
+static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, int64_t chunks_cap, int npmax,
+                         bool own_idx) {
+  S.ngroups = ngroups;
+  S.ntcap = ntcap;
+  S.chunks_cap = chunks_cap;
+  S.items_cap = chunks_cap * npmax;
+  if (own_idx) S.idx = cv.take<int32_t>(ntcap);
+  const size_t ng = std::max(1, ngroups);
+  S.grp_begin = cv.take<int32_t>(ng); S.grp_n = cv.take<int32_t>(ng);
+  S.grp_rows = cv.take<int32_t>(ng); S.grp_cols = cv.take<int32_t>(ng);
+  S.grp_out = cv.take<int32_t>(ng); S.grp_mode = cv.take<int32_t>(ng);
+  S.grp_cost = cv.take<int64_t>(ng); S.grp_chunk_base = cv.take<int64_t>(ng + 1);
+  S.chunks = cv.take<Chunk>(chunks_cap);
+  S.slot_off = cv.take<int64_t>(chunks_cap + 1);
+  S.chunk_item_base = cv.take<int64_t>(chunks_cap + 1);
+  S.items_unsorted = cv.take<Item>(S.items_cap);
+  S.items = cv.take<Item>(S.items_cap);
+  S.keys_in = cv.take<uint64_t>(S.items_cap); S.keys_out = cv.take<uint64_t>(S.items_cap);
+  S.vals_in = cv.take<int32_t>(S.items_cap); S.vals_out = cv.take<int32_t>(S.items_cap);
+  S.sort_tmp_bytes = radix_tmp_u64(S.items_cap);
+  S.sort_tmp = cv.take<char>(S.sort_tmp_bytes + 256);
+  S.scratch = cv.take<int64_t>(std::max<int64_t>(ng, chunks_cap) + 1);
+  S.scalars = cv.take<int64_t>(8);
+}
+
+// Lays out (or, with base == nullptr, sizes) the build workspace.
+static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_cu, char *base, Plan *pl) {
+  Carve cv{base, 0, 0};
+  Plan p;
+  memset(&p, 0, sizeof(p));
+  p.nL = P->nL; p.nR = P->nR; p.nS = P->nS; p.nOps = P->nOps; p.nBlk = P->nBlk; p.nTerms = P->nTerms;
+  p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals;
+  p.psi_dim = P->psi_off[P->nS];
+  const int64_t ntcap = std::max<int64_t>(1, (int64_t)P->nTerms * P->nS);
+  const int npmax = (maxdim + TQ - 1) / TQ;
+  p.qL = cv.take<int32_t>(2 * P->nL); p.dimL = cv.take<int32_t>(P->nL);
+  p.qR = cv.take<int32_t>(2 * P->nR); p.dimR = cv.take<int32_t>(P->nR);
+  p.psi_sec = cv.take<int32_t>(4 * (size_t)std::max(1, P->nS)); p.psi_off = cv.take<int64_t>(P->nS + 1);
+  const size_t no = std::max(1, P->nOps), nb = std::max(1, P->nBlk), nt = std::max(1, P->nTerms);
+  p.op_side = cv.take<int32_t>(no); p.op_dN = cv.take<int32_t>(no); p.op_d2Sz = cv.take<int32_t>(no);
+  p.blk_op = cv.take<int32_t>(nb); p.blk_in = cv.take<int32_t>(nb); p.blk_out = cv.take<int32_t>(nb);
+  p.blk_rows = cv.take<int32_t>(nb); p.blk_cols = cv.take<int32_t>(nb); p.blk_ld = cv.take<int32_t>(nb);
+  p.blk_off = cv.take<int64_t>(nb);
+  p.term_L = cv.take<int32_t>(nt); p.term_ma = cv.take<int32_t>(nt); p.term_mb = cv.take<int32_t>(nt);
+  p.term_R = cv.take<int32_t>(nt); p.term_coef = cv.take<double>(nt);
+  p.psi_index = cv.take<int32_t>((size_t)P->nL * 16);
+  p.blk_of_out = cv.take<int32_t>(no * nmax);
+  p.tasks = cv.take<tns_task>(ntcap);
+  p.out_ptr = cv.take<int32_t>(P->nS + 1);
+  p.scan_tmp = cv.take<int64_t>(P->nS + 1);
+  p.scalars = cv.take<int64_t>(8);
+  // forward schedule: 2 groups per sector
+  const int64_t fchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 4 * (int64_t)P->nS + 16;
+  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, npmax, true);
+  // backward schedule: one group per sector (d psi) and one per block (d L / d R)
+  const int64_t bent = 3 * ntcap;
+  p.bkeys_in = cv.take<int32_t>(bent); p.bkeys_out = cv.take<int32_t>(bent); p.bvals_in = cv.take<int32_t>(bent);
+  p.bwd.idx = cv.take<int32_t>(bent);
+  p.bsort_tmp_bytes = radix_tmp_i32(bent);
+  p.bsort_tmp = cv.take<char>(p.bsort_tmp_bytes + 256);
+  const int32_t bgroups = P->nS + P->nBlk;
+  const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
+  layout_sched(cv, p.bwd, bgroups, bent, bchunks, npmax, false);
+  if (pl) *pl = p;
+  return cv.off + 256;
+}
+
+template <class T>
+static hipError_t up(T *dst, const T *src, size_t n, hipStream_t st) {
+  if (n == 0 || !src) return hipSuccess;
+  return hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+// Chunks, partial slots, work items and the longest-first order of a
+// schedule whose groups (begin, n, rows, cols, out, mode) are set.
+static tns_status finish_sched(const Plan &p, Sched &S, hipStream_t st) {
+  const int B = 256;
+  const int ng = S.ngroups;
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(8), 0, st, S.scalars, (int64_t)8, (int64_t)0);
+  if (ng > 0) {
+    hipLaunchKernelGGL(k_group_cost, dim3(nblk(ng, 4)), dim3(256), 0, st, p, S);
+    hipLaunchKernelGGL(k_chunks<false>, dim3(nblk(ng, B)), dim3(B), 0, st, p, S);
+    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, S.scratch, S.grp_chunk_base, (int64_t)ng);
+    hipLaunchKernelGGL(k_chunks<true>, dim3(nblk(ng, B)), dim3(B), 0, st, p, S);
+  } else {
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(1), 0, st, S.grp_chunk_base, (int64_t)1, (int64_t)0);
+  }
+  int64_t *slot_sz = S.scratch;
+  int64_t *item_n = reinterpret_cast<int64_t *>(S.keys_out);  // items_cap >= chunks_cap
+  hipLaunchKernelGGL(k_chunk_sizes, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S, slot_sz, item_n);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, slot_sz, S.slot_off, S.chunks_cap);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, item_n, S.chunk_item_base, S.chunks_cap);
+  hipLaunchKernelGGL(k_items, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S);
+  hipLaunchKernelGGL(k_sort_keys, dim3(nblk(S.items_cap, B)), dim3(B), 0, st, S);
+  TNS_HIP(hipGetLastError());
+  size_t tmp = S.sort_tmp_bytes;
+  TNS_HIP(hipcub::DeviceRadixSort::SortPairs(S.sort_tmp, tmp, S.keys_in, S.keys_out, S.vals_in, S.vals_out,
+                                             (int)S.items_cap, 0, 64, st));
+  hipLaunchKernelGGL(k_gather_items, dim3(nblk(S.items_cap, B)), dim3(B), 0, st, S);
+  hipLaunchKernelGGL(k_sched_totals, dim3(1), dim3(1), 0, st, S);
+  TNS_HIP(hipGetLastError());
+  return TNS_OK;
+}
+
+static void read_sched(Sched &S, const int64_t *h) {
+  S.total_cost = h[0];
+  S.nchunks = h[1];
+  S.nitems = h[2];
+  S.partial_elems = h[3];
+}
+
+}  // namespace tns
+
+using namespace tns;
+
+extern "C" size_t tns_tasklist_workspace_bytes(const tns_problem *prob) {
+  int32_t nmax = 0, maxdim = 0;
+  if (validate(prob, &nmax, &maxdim) != TNS_OK) return 0;
+  return layout(prob, nmax, maxdim, device_cu_count(), nullptr, nullptr);
+}
+
+extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t ws_bytes, tns_tasklist *out,
+                                         hipStream_t st) {
+  if (!out || !ws) return TNS_ERR_ARG;
+  int32_t nmax = 0, maxdim = 0;
+  tns_status s = validate(P, &nmax, &maxdim);
+  if (s != TNS_OK) return s;
+  const int n_cu = device_cu_count();
+  const size_t need = layout(P, nmax, maxdim, n_cu, nullptr, nullptr);
+  if (ws_bytes < need) return TNS_ERR_WORKSPACE;
+  Plan p;
+  layout(P, nmax, maxdim, n_cu, (char *)ws, &p);
+  TNS_HIP(up(p.qL, P->qL, 2 * (size_t)P->nL, st));
+  TNS_HIP(up(p.dimL, P->dimL, P->nL, st));
+  TNS_HIP(up(p.qR, P->qR, 2 * (size_t)P->nR, st));
+  TNS_HIP(up(p.dimR, P->dimR, P->nR, st));
+  TNS_HIP(up(p.psi_sec, P->psi_sec, 4 * (size_t)P->nS, st));
+  TNS_HIP(up(p.psi_off, P->psi_off, (size_t)P->nS + 1, st));
+  TNS_HIP(up(p.op_side, P->op_side, P->nOps, st));
+  TNS_HIP(up(p.op_dN, P->op_dN, P->nOps, st));
+  TNS_HIP(up(p.op_d2Sz, P->op_d2Sz, P->nOps, st));
+  TNS_HIP(up(p.blk_op, P->blk_op, P->nBlk, st));
+  TNS_HIP(up(p.blk_in, P->blk_in, P->nBlk, st));
+  TNS_HIP(up(p.blk_out, P->blk_out, P->nBlk, st));
+  TNS_HIP(up(p.blk_rows, P->blk_rows, P->nBlk, st));
+  TNS_HIP(up(p.blk_cols, P->blk_cols, P->nBlk, st));
+  TNS_HIP(up(p.blk_ld, P->blk_ld, P->nBlk, st));
+  TNS_HIP(up(p.blk_off, P->blk_off, P->nBlk, st));
+  TNS_HIP(up(p.term_L, P->term_L, P->nTerms, st));
+  TNS_HIP(up(p.term_ma, P->term_ma, P->nTerms, st));
+  TNS_HIP(up(p.term_mb, P->term_mb, P->nTerms, st));
+  TNS_HIP(up(p.term_R, P->term_R, P->nTerms, st));
+  TNS_HIP(up(p.term_coef, P->term_coef, P->nTerms, st));
+
+  const int B = 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)P->nL * 16, B)), dim3(B), 0, st, p.psi_index,
+                     (int64_t)P->nL * 16, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)std::max(1, P->nOps) * nmax, B)), dim3(B), 0, st,
+                     p.blk_of_out, (int64_t)std::max(1, P->nOps) * nmax, -1);
+  if (P->nS > 0) hipLaunchKernelGGL(k_psi_index, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
+  if (P->nBlk > 0) hipLaunchKernelGGL(k_blk_of_out, dim3(nblk(P->nBlk, B)), dim3(B), 0, st, p);
+  TNS_HIP(hipGetLastError());
+  const unsigned wblk = nblk(std::max(1, P->nS), 4);
+  // levels 1-2: task counts per output sector -> CSR -> canonical fill
+  if (P->nS > 0) {
+    hipLaunchKernelGGL(k_tasks<false>, dim3(wblk), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.scan_tmp, p.scan_tmp, (int64_t)P->nS);
+  } else {
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(1), 0, st, p.scan_tmp, (int64_t)1, (int64_t)0);
+  }
+  hipLaunchKernelGGL(k_i64_to_i32, dim3(nblk(P->nS + 1, B)), dim3(B), 0, st, p.scan_tmp, p.out_ptr,
+                     (int64_t)P->nS + 1);
+  if (P->nS > 0) {
+    hipLaunchKernelGGL(k_tasks<true>, dim3(wblk), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_fwd_groups, dim3(wblk), dim3(256), 0, st, p, p.fwd);
+  }
+  TNS_HIP(hipGetLastError());
+  s = finish_sched(p, p.fwd, st);
+  if (s != TNS_OK) return s;
+  int64_t h[8];
+  TNS_HIP(hipMemcpyAsync(h, p.fwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+  int32_t nt32 = 0;
+  TNS_HIP(hipMemcpyAsync(&nt32, p.out_ptr + P->nS, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipStreamSynchronize(st));
+  p.ntasks = nt32;
+  read_sched(p.fwd, h);
+  if (p.fwd.nchunks > p.fwd.chunks_cap || p.fwd.nitems > p.fwd.items_cap) return TNS_ERR_WORKSPACE;
+
+  // backward grouping: stable sort of (key, task) entries by key
+  const int64_t nent = 3 * p.ntasks;
+  if (nent > 0) {
+    hipLaunchKernelGGL(k_bwd_keys, dim3(nblk(p.ntasks, B)), dim3(B), 0, st, p, p.ntasks);
+    size_t tmp = p.bsort_tmp_bytes;
+    TNS_HIP(hipcub::DeviceRadixSort::SortPairs(p.bsort_tmp, tmp, p.bkeys_in, p.bkeys_out, p.bvals_in, p.bwd.idx,
+                                               (int)nent, 0, 32, st));
+  }
+  const int bg = p.bwd.ngroups;
+  hipLaunchKernelGGL(k_fill_i64, dim3(nblk(bg + 1, B)), dim3(B), 0, st, p.bwd.scratch, (int64_t)bg + 1, (int64_t)0);
+  if (nent > 0) hipLaunchKernelGGL(k_bwd_count, dim3(nblk(nent, B)), dim3(B), 0, st, p, p.bwd, nent);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.bwd.scratch, p.bwd.grp_chunk_base, (int64_t)bg);
+  if (bg > 0) hipLaunchKernelGGL(k_bwd_groups, dim3(nblk(bg, B)), dim3(B), 0, st, p, p.bwd);
+  TNS_HIP(hipGetLastError());
+  s = finish_sched(p, p.bwd, st);
+  if (s != TNS_OK) return s;
+  TNS_HIP(hipMemcpyAsync(h, p.bwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipStreamSynchronize(st));
+  read_sched(p.bwd, h);
+  if (p.bwd.nchunks > p.bwd.chunks_cap || p.bwd.nitems > p.bwd.items_cap) return TNS_ERR_WORKSPACE;
+
+  memset(out, 0, sizeof(*out));
+  out->ntasks = p.ntasks;
+  out->nitems = p.fwd.nitems;
+  out->nslots = p.fwd.nchunks;
+  out->partial_elems = p.fwd.partial_elems;
+  out->total_flops = p.fwd.total_cost;
+  out->psi_dim = p.psi_dim;
+  out->tasks = p.tasks;
+  out->out_ptr = p.out_ptr;
+  memcpy(out->opaque, &p, sizeof(p));
+  return TNS_OK;
+}
+
+extern "C" const char *tns_status_string(tns_status s) {
+  switch (s) {
+    case TNS_OK: return "ok";
+    case TNS_ERR_ARG: return "invalid argument";
+    case TNS_ERR_SHAPE: return "inconsistent shape or offset";
+    case TNS_ERR_QN: return "quantum numbers not conserved";
+    case TNS_ERR_WORKSPACE: return "workspace too small";
+    case TNS_ERR_HIP: return "HIP runtime error";
+    case TNS_ERR_NUMERIC: return "non-finite value";
+    case TNS_ERR_NOT_CONVERGED: return "not converged";
+  }
+  return "unknown status";
+}

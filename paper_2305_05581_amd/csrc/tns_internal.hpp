@@ -1,0 +1,159 @@
+// Internal declarations of the gfx950 two-site H_eff library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/tns.h"
+
+namespace tns {
+
+// Row-panel height of one work item; every item owns TQ rows (or fewer) of
+// an output sector and all of its columns.
+constexpr int TQ = 32;
+// Work items per compute unit the schedule aims at (load balance of the
+// longest-first queue).
+constexpr int ITEMS_PER_CU = 8;
+
+// Evaluation modes of the fused chained product
+//   out(i, j) += alpha * sum_c (sum_k X(i, k) M(k, c)) Y(j, c)
+// (q, m: output / input left dims; r, n: output / input right dims; A = psi
+// input sector, G = grad of sigma output sector):
+//   0  (L A) R^T        X = L,   M = A,   Y = R      out = sigma rows   (q x r)
+//   1  L (A R^T)        X = R,   M = A^T, Y = L      out = sigma^T rows (r x q)
+//   2  d psi = L^T G R  X = L^T, M = G,   Y = R^T    out = (m x n)
+//   3  d L = G R A^T    X = G,   M = R,   Y = A      out = (q x m)
+//   4  d R = G^T L A    X = G^T, M = L,   Y = A^T    out = (r x n)
+enum Mode { M_FWD0 = 0, M_FWD1 = 1, M_DPSI = 2, M_DL = 3, M_DR = 4 };
+
+// One work item of the persistent kernel: rows [p0, p0+np) of the output
+// matrix of group `grp`, entries idx[tb..te) of that group's task list,
+// result into partial slot `slot` (one slot per chunk of a group).
+struct Item {
+  int32_t grp, mode, p0, np, tb, te, slot, out;
+  int64_t cost;
+};
+static_assert(sizeof(Item) == 40, "Item layout");
+
+struct Chunk {
+  int32_t grp, tb, te, pad;
+  int64_t cost;
+};
+
+// A schedule: groups of tasks that share one output matrix, cut into chunks
+// (partial slots) and row panels (work items), longest item first.
+struct Sched {
+  int32_t ngroups, pad_;
+  int64_t ntcap;        // capacity of idx
+  int64_t chunks_cap, items_cap;
+  int64_t nchunks, nitems, partial_elems, total_cost;
+  int32_t *idx;         // task indices, grouped
+  int32_t *grp_begin, *grp_n, *grp_rows, *grp_cols, *grp_out, *grp_mode;
+  int64_t *grp_cost, *grp_chunk_base;
+  Chunk *chunks;
+  int64_t *slot_off, *chunk_item_base;
+  Item *items_unsorted, *items;
+  uint64_t *keys_in, *keys_out;
+  int32_t *vals_in, *vals_out;
+  void *sort_tmp;
+  size_t sort_tmp_bytes;
+  int64_t *scratch;     // [max(ngroups, chunks_cap) + 1]
+  int64_t *scalars;     // [8]
+};
+
+// Host-side record of everything the compute calls need; lives in
+// tns_tasklist::opaque, all pointers are device pointers into the build
+// workspace.
+struct Plan {
+  int32_t nL, nR, nS, nOps, nBlk, nTerms, nmax, n_cu;
+  int64_t n_vals, psi_dim, ntasks;
+  // copied tables
+  int32_t *qL, *dimL, *qR, *dimR, *psi_sec;
+  int64_t *psi_off;
+  int32_t *op_side, *op_dN, *op_d2Sz;
+  int32_t *blk_op, *blk_in, *blk_out, *blk_rows, *blk_cols, *blk_ld;
+  int64_t *blk_off;
+  int32_t *term_L, *term_ma, *term_mb, *term_R;
+  double *term_coef;
+  // lookups
+  int32_t *psi_index;    // [nL*16] -> sector or -1
+  int32_t *blk_of_out;   // [nOps*nmax] -> block or -1
+  // task table
+  tns_task *tasks;       // [ntcap]
+  int32_t *out_ptr;      // [nS+1]
+  int64_t *scan_tmp;     // [nS+1]
+  int64_t *scalars;      // [8]
+  // backward grouping keys: 3 entries per task
+  int32_t *bkeys_in, *bkeys_out, *bvals_in;
+  void *bsort_tmp;
+  size_t bsort_tmp_bytes;
+  Sched fwd, bwd;
+};
+static_assert(sizeof(Plan) <= sizeof(((tns_tasklist *)0)->opaque), "Plan too large");
+
+inline Plan &plan_of(tns_tasklist *t) { return *reinterpret_cast<Plan *>(t->opaque); }
+inline const Plan &plan_of(const tns_tasklist *t) { return *reinterpret_cast<const Plan *>(t->opaque); }
+
+#define TNS_HIP(call)                                       \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return TNS_ERR_HIP;               \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace.
+struct Carve {
+  char *base;
+  size_t off, cap;
+  template <class T>
+  T *take(size_t n) {
+    off = align_up(off, 256);
+    T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// --- site algebra (the library's own table; see tns.h for the conventions) --
+// Applies monomial m = 4u + d to site state s (bit 0 = up, bit 1 = down).
+// Returns the output state or -1, and the matrix element (+-1) in *val.
+__host__ __device__ inline int mono_apply(int m, int s, int *val) {
+  int u = m >> 2, d = m & 3;
+  int v = 1;
+  // down factor acts first (it stands to the right); passing the up mode
+  // (which precedes it in Jordan-Wigner order) costs (-1)^{n_up} for c+/c
+  int up = s & 1, dn = (s >> 1) & 1;
+  switch (d) {
+    case 1: if (!dn) return -1; break;
+    case 2: if (dn) return -1; dn = 1; if (up) v = -v; break;
+    case 3: if (!dn) return -1; dn = 0; if (up) v = -v; break;
+    default: break;
+  }
+  switch (u) {
+    case 1: if (!up) return -1; break;
+    case 2: if (up) return -1; up = 1; break;
+    case 3: if (!up) return -1; up = 0; break;
+    default: break;
+  }
+  *val = v;
+  return up | (dn << 1);
+}
+__host__ __device__ inline int mono_parity(int m) {
+  int u = m >> 2, d = m & 3;
+  return ((u >= 2) + (d >= 2)) & 1;
+}
+__host__ __device__ inline int site_N(int s) { return (s & 1) + ((s >> 1) & 1); }
+__host__ __device__ inline int site_2Sz(int s) { return (s & 1) - ((s >> 1) & 1); }
+__host__ __device__ inline void mono_shift(int m, int *dN, int *d2Sz) {
+  int u = m >> 2, d = m & 3;
+  int du = (u == 2) ? 1 : (u == 3 ? -1 : 0);
+  int dd = (d == 2) ? 1 : (d == 3 ? -1 : 0);
+  *dN = du + dd;
+  *d2Sz = du - dd;
+}
+
+// Launch helpers implemented in tasklist.hip / apply.hip
+tns_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
+
+}  // namespace tns

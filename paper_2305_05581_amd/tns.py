@@ -1,0 +1,318 @@
+"""ctypes binding of ``libtns.so`` (argument marshalling only).
+
+Every step of sigma = H_eff psi runs in the library's HIP kernels; this module
+only lays out host tables, owns the device buffers (torch tensors) and passes
+pointers and the current torch stream.  A missing library raises at first
+use: there is no CPU fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtns.so")
+
+F64, F32, BF16X3 = 0, 1, 2
+PREC_NAMES = {F64: "f64", F32: "f32", BF16X3: "bf16x3"}
+_PREC_OF = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "inconsistent shape or offset", -3: "quantum numbers not conserved",
+          -4: "workspace too small", -5: "HIP runtime error", -6: "non-finite value", -7: "not converged"}
+
+# 40-byte task record (see include/tns.h)
+TASK_DTYPE = np.dtype([("out", "<i4"), ("in", "<i4"), ("term", "<i4"), ("lblk", "<i4"),
+                       ("rblk", "<i4"), ("order", "<i4"), ("alpha", "<f8"), ("cost", "<i8")])
+
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class TnsProblem(ctypes.Structure):
+    _fields_ = [("nL", _i32), ("nR", _i32), ("nS", _i32), ("nOps", _i32), ("nBlk", _i32), ("nTerms", _i32),
+                ("target_N", _i32), ("target_2Sz", _i32), ("n_vals", _i64)] + \
+               [(n, _P) for n in ("qL", "dimL", "qR", "dimR", "psi_sec", "psi_off", "op_side", "op_dN", "op_d2Sz",
+                                  "blk_op", "blk_in", "blk_out", "blk_rows", "blk_cols", "blk_ld", "blk_off",
+                                  "term_L", "term_ma", "term_mb", "term_R", "term_coef")]
+
+
+class TnsTasklist(ctypes.Structure):
+    _fields_ = [("ntasks", _i64), ("nitems", _i64), ("nslots", _i64), ("partial_elems", _i64),
+                ("total_flops", _i64), ("psi_dim", _i64), ("tasks", _P), ("out_ptr", _P),
+                ("opaque", ctypes.c_uint8 * 2048)]
+
+
+class TnsDavidsonOpts(ctypes.Structure):
+    _fields_ = [("max_sub", _i32), ("keep", _i32), ("max_iter", _i32), ("refine", _i32),
+                ("tol_res", ctypes.c_double), ("tol_e", ctypes.c_double), ("inner", _i32)]
+
+
+class TnsDavidsonInfo(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("matvecs_lo", _i32), ("matvecs_f64", _i32),
+                ("res_norm", ctypes.c_double), ("e_lo", ctypes.c_double)]
+
+
+EXPORTS = ("tns_tasklist_workspace_bytes", "tns_build_tasklist", "tns_apply_workspace_bytes",
+           "tns_prepare_operands", "tns_apply_heff", "tns_backward_workspace_bytes", "tns_apply_heff_backward",
+           "tns_davidson_workspace_bytes", "tns_davidson", "tns_status_string")
+
+_lib = None
+
+
+def library(path=LIB_PATH):
+    """Load ``libtns.so`` (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libtns.so is not built; run `python -m paper_2305_05581_amd.build`")
+    L = ctypes.CDLL(path)
+    sz = ctypes.c_size_t
+    L.tns_tasklist_workspace_bytes.restype = sz
+    L.tns_tasklist_workspace_bytes.argtypes = [ctypes.POINTER(TnsProblem)]
+    L.tns_build_tasklist.restype = ctypes.c_int
+    L.tns_build_tasklist.argtypes = [ctypes.POINTER(TnsProblem), _P, sz, ctypes.POINTER(TnsTasklist), _P]
+    L.tns_apply_workspace_bytes.restype = sz
+    L.tns_apply_workspace_bytes.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int]
+    L.tns_prepare_operands.restype = ctypes.c_int
+    L.tns_prepare_operands.argtypes = [ctypes.c_int, _P, _i64, _P, _P]
+    L.tns_apply_heff.restype = ctypes.c_int
+    L.tns_apply_heff.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, sz, _P]
+    if hasattr(L, "tns_apply_heff_backward"):
+        L.tns_backward_workspace_bytes.restype = sz
+        L.tns_backward_workspace_bytes.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int]
+        L.tns_apply_heff_backward.restype = ctypes.c_int
+        L.tns_apply_heff_backward.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int, _P, _P, _P, _P, _P, _P, sz,
+                                              _P]
+    if hasattr(L, "tns_davidson"):
+        L.tns_davidson_workspace_bytes.restype = sz
+        L.tns_davidson_workspace_bytes.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.POINTER(TnsDavidsonOpts)]
+        L.tns_davidson.restype = ctypes.c_int
+        L.tns_davidson.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.POINTER(TnsDavidsonOpts), _P, _P, _P, _P,
+                                   ctypes.POINTER(TnsDavidsonInfo), _P, sz, _P]
+    L.tns_status_string.restype = ctypes.c_char_p
+    L.tns_status_string.argtypes = [ctypes.c_int]
+    _lib = L
+    return L
+
+
+class TnsError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, STATUS.get(code, "unknown"), code))
+        self.code = code
+
+
+def _check(code, what):
+    if code != 0:
+        raise TnsError(code, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def prec_id(prec):
+    return _PREC_OF[prec] if isinstance(prec, str) else int(prec)
+
+
+class HeffProblem:
+    """A two-site problem resident on the GPU: task table and schedule built by
+    the library, FP64 operator values in HBM, operand copies per precision."""
+
+    _TABLES = (("qL", np.int32), ("dimL", np.int32), ("qR", np.int32), ("dimR", np.int32),
+               ("psi_sec", np.int32), ("psi_off", np.int64), ("op_side", np.int32), ("op_dN", np.int32),
+               ("op_d2Sz", np.int32), ("blk_op", np.int32), ("blk_in", np.int32), ("blk_out", np.int32),
+               ("blk_rows", np.int32), ("blk_cols", np.int32), ("blk_ld", np.int32), ("blk_off", np.int64),
+               ("term_L", np.int32), ("term_ma", np.int32), ("term_mb", np.int32), ("term_R", np.int32),
+               ("term_coef", np.float64))
+
+    def __init__(self, P, device="cuda", vals64=None):
+        self.P = P
+        self.device = torch.device(device)
+        L = library()
+        self._host = {}
+        cp = TnsProblem()
+        cp.nL, cp.nR, cp.nS = P.nL, P.nR, P.nS
+        cp.nOps, cp.nBlk, cp.nTerms = P.nOps, P.nBlk, P.nTerms
+        cp.target_N, cp.target_2Sz = int(P.target[0]), int(P.target[1])
+        n_vals = int(vals64.numel()) if vals64 is not None else len(P.op_vals)
+        cp.n_vals = n_vals
+        for name, dt in self._TABLES:
+            a = np.ascontiguousarray(getattr(P, name), dtype=dt)
+            self._host[name] = a
+            setattr(cp, name, a.ctypes.data_as(ctypes.c_void_p) if a.size else None)
+        self.cprob = cp
+        nbytes = L.tns_tasklist_workspace_bytes(ctypes.byref(cp))
+        if nbytes == 0:
+            raise ValueError("problem failed host validation")
+        self.ws_build = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.tl = TnsTasklist()
+        with torch.cuda.device(self.device):
+            _check(L.tns_build_tasklist(ctypes.byref(cp), _ptr(self.ws_build), int(nbytes), ctypes.byref(self.tl),
+                                        _stream()), "tns_build_tasklist")
+        if vals64 is None:
+            vals64 = torch.from_numpy(np.ascontiguousarray(P.op_vals)).to(self.device)
+        self.vals64 = vals64
+        self._ops = {F64: vals64}
+        self._ws = {}
+        self.psi_dim = int(self.tl.psi_dim)
+        self.ntasks = int(self.tl.ntasks)
+        self.total_flops = int(self.tl.total_flops)
+
+    # -- operands ----------------------------------------------------------
+    def operands(self, prec):
+        p = prec_id(prec)
+        if p not in self._ops:
+            n = self.vals64.numel()
+            if p == F32:
+                out = torch.empty(n, dtype=torch.float32, device=self.device)
+            else:
+                out = torch.empty(2 * n, dtype=torch.int16, device=self.device)
+            _check(library().tns_prepare_operands(p, _ptr(self.vals64), n, _ptr(out), _stream()),
+                   "tns_prepare_operands")
+            self._ops[p] = out
+        return self._ops[p]
+
+    def workspace(self, kind, prec):
+        key = (kind, prec)
+        L = library()
+        if key not in self._ws:
+            if kind == "apply":
+                n = L.tns_apply_workspace_bytes(ctypes.byref(self.tl), prec)
+            else:
+                n = L.tns_backward_workspace_bytes(ctypes.byref(self.tl), prec)
+            self._ws[key] = torch.empty(int(max(n, 256)), dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    # -- H_eff psi ------------------------------------------------------------
+    def _vec(self, x, dt, what):
+        if x.dtype != dt or x.device != self.device or x.numel() != self.psi_dim or not x.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of %d elements on %s"
+                             % (what, dt, self.psi_dim, self.device))
+
+    def _ops_arg(self, p, ops):
+        if ops is None:
+            return self.operands(p)
+        dt = torch.float64 if p == F64 else torch.float32
+        if p == BF16X3 or ops.dtype != dt or not ops.is_contiguous() or ops.numel() != self.vals64.numel() \
+                or ops.device != self.device:
+            raise ValueError("explicit operator values must be a contiguous %s tensor of %d elements"
+                             % (dt, self.vals64.numel()))
+        return ops
+
+    def apply(self, psi, prec="f64", out=None, beta=0.0, ops=None):
+        """sigma := beta sigma + H_eff psi in precision ``prec`` (``ops``:
+        optional operator values in the precision's dtype, op-value layout)."""
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        self._vec(psi, dt, "psi")
+        if out is None:
+            out = torch.empty(self.psi_dim, dtype=dt, device=self.device)
+            beta = 0.0
+        else:
+            self._vec(out, dt, "out")
+        ws = self.workspace("apply", p)
+        _check(library().tns_apply_heff(ctypes.byref(self.tl), p, _ptr(self._ops_arg(p, ops)), _ptr(psi), _ptr(out),
+                                        float(beta), _ptr(ws), ws.numel(), _stream()), "tns_apply_heff")
+        return out
+
+    def backward(self, psi, grad_sigma, prec="f64", want_psi=True, want_ops=True, ops=None):
+        """(grad_psi, grad_ops) of a loss with d loss / d sigma = grad_sigma."""
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        self._vec(psi, dt, "psi")
+        self._vec(grad_sigma, dt, "grad_sigma")
+        gp = torch.empty(self.psi_dim, dtype=dt, device=self.device) if want_psi else None
+        go = torch.empty(self.vals64.numel(), dtype=dt, device=self.device) if want_ops else None
+        ws = self.workspace("backward", p)
+        _check(library().tns_apply_heff_backward(
+            ctypes.byref(self.tl), p, _ptr(self._ops_arg(p, ops)), _ptr(psi), _ptr(grad_sigma),
+            _ptr(gp) if gp is not None else None, _ptr(go) if go is not None else None,
+            _ptr(ws), ws.numel(), _stream()), "tns_apply_heff_backward")
+        return gp, go
+
+    def davidson(self, psi0, inner="f64", tol_res=1e-6, tol_e=1e-10, max_sub=32, keep=8, max_iter=500,
+                 refine=8):
+        """Lowest eigenpair by the library's device Davidson.  Returns
+        ``(energy, psi, info)``; ``psi0`` (FP64) is not modified."""
+        L = library()
+        o = TnsDavidsonOpts(max_sub=max_sub, keep=keep, max_iter=max_iter, refine=refine,
+                            tol_res=tol_res, tol_e=tol_e, inner=prec_id(inner))
+        n = L.tns_davidson_workspace_bytes(ctypes.byref(self.tl), ctypes.byref(o))
+        if n == 0:
+            raise ValueError("invalid Davidson options")
+        ws = torch.empty(int(n), dtype=torch.uint8, device=self.device)
+        x = psi0.detach().to(self.device, torch.float64).contiguous().clone()
+        e = ctypes.c_double(0.0)
+        info = TnsDavidsonInfo()
+        code = L.tns_davidson(ctypes.byref(self.tl), ctypes.byref(o), _ptr(self.operands(o.inner)),
+                              _ptr(self.vals64), _ptr(x), ctypes.byref(e), ctypes.byref(info), _ptr(ws), int(n),
+                              _stream())
+        if code not in (0, -7):
+            raise TnsError(code, "tns_davidson")
+        return e.value, x, dict(iters=info.iters, matvecs_lo=info.matvecs_lo, matvecs_f64=info.matvecs_f64,
+                                res_norm=info.res_norm, e_lo=info.e_lo, converged=code == 0)
+
+    # -- inspection -------------------------------------------------------------
+    def tasks(self):
+        """Copy of the device task table (numpy, 40-byte records) and CSR pointer."""
+        n = self.ntasks
+        buf = torch.empty(n * TASK_DTYPE.itemsize, dtype=torch.uint8, device=self.device)
+        ptr = torch.empty(self.P.nS + 1, dtype=torch.int32, device=self.device)
+        if n:
+            _memcpy_d2d(buf, self.tl.tasks, n * TASK_DTYPE.itemsize)
+        _memcpy_d2d(ptr, self.tl.out_ptr, (self.P.nS + 1) * 4)
+        torch.cuda.synchronize(self.device)
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=TASK_DTYPE), ptr.cpu().numpy()
+
+
+def _memcpy_d2d(dst, src_ptr, nbytes):
+    hip = _hip()
+    r = hip.hipMemcpyAsync(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), ctypes.c_size_t(nbytes),
+                           ctypes.c_int(3), _stream())
+    if r != 0:
+        raise RuntimeError("hipMemcpyAsync failed (%d)" % r)
+
+
+_hiprt = None
+
+
+def _hip():
+    global _hiprt
+    if _hiprt is None:
+        _hiprt = ctypes.CDLL("libamdhip64.so")
+        _hiprt.hipMemcpyAsync.restype = ctypes.c_int
+        _hiprt.hipMemcpyAsync.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int, _P]
+    return _hiprt
+
+
+class HeffFunction(torch.autograd.Function):
+    """sigma = H_eff(vals) psi with the library's hand-written backward.
+
+    ``vals`` are the operator values in the op-value layout (FP64 or FP32,
+    matching ``prec``); gradients flow to ``psi`` and ``vals``."""
+
+    @staticmethod
+    def forward(ctx, psi, vals, problem, prec):
+        ctx.problem, ctx.prec = problem, prec
+        ctx.save_for_backward(psi, vals)
+        return problem.apply(psi.contiguous(), prec, ops=vals.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_sigma):
+        psi, vals = ctx.saved_tensors
+        gp, go = ctx.problem.backward(psi.contiguous(), grad_sigma.contiguous(), ctx.prec,
+                                      want_psi=ctx.needs_input_grad[0], want_ops=ctx.needs_input_grad[1],
+                                      ops=vals.contiguous())
+        return gp, go, None, None
+
+
+def heff(psi, vals, problem, prec="f64"):
+    return HeffFunction.apply(psi, vals, problem, prec)

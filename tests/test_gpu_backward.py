@@ -1,0 +1,91 @@
+"""GPU parity of the hand-written backward (d psi, d operator blocks) and of
+the autograd wrapper, against the oracle and finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from synth import synthetic_problem, gaussian_psi, molecular_integrals
+from oracle import grad as ograd
+from oracle import heff as oheff
+from oracle.blocks import Construction
+from oracle.fock import fci_hamiltonian, rdms
+
+from gpu_common import say, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def cases():
+    from paper_2305_05581_amd.tns import HeffProblem
+    out = {}
+    for name, mk in {
+        "small": lambda: synthetic_problem(16, 16, 0, 96, 8, 24, 60, seed=5, gapped=True),
+        "ragged": lambda: synthetic_problem(22, 22, 0, 700, 23, 187, 120, seed=12),
+        "exact_L6": lambda: Construction(*molecular_integrals(6, 11), 6, 0, l=2).problem(),
+    }.items():
+        say("build", name)
+        P = mk()
+        out[name] = (P, HeffProblem(P), oheff.enumerate_tasks(P))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["small", "ragged", "exact_L6"])
+def test_backward_parity(cases, name, prec):
+    P, H, tasks = cases[name]
+    psi, G = gaussian_psi(P, 1), gaussian_psi(P, 2)
+    dpsi, dvals, _ = ograd.backward(P, psi, G, tasks)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    say("backward", name, prec)
+    gp, go = H.backward(to_dev(psi, dt), to_dev(G, dt), prec)
+    e1 = rel(gp.double().cpu().numpy(), dpsi)
+    e2 = rel(go.double().cpu().numpy(), dvals)
+    say("  rel err dpsi %.2e dops %.2e" % (e1, e2))
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+    # one output at a time gives the same values
+    gp2, _ = H.backward(to_dev(psi, dt), to_dev(G, dt), prec, want_ops=False)
+    assert torch.equal(gp, gp2)
+
+
+def test_autograd_energy_gradients(cases):
+    from paper_2305_05581_amd.tns import heff
+    P, H, tasks = cases["small"]
+    psi = to_dev(gaussian_psi(P, 1)).requires_grad_(True)
+    vals = H.vals64.clone().requires_grad_(True)
+    sigma = heff(psi, vals, H, "f64")
+    E = torch.dot(psi, sigma)
+    E.backward()
+    # d<psi, H psi>/d psi = 2 H psi for symmetric H
+    Hpsi = H.apply(psi.detach(), "f64").cpu().numpy()
+    assert rel(psi.grad.cpu().numpy(), 2 * Hpsi) < 1e-12
+    # linear in the operator values: central difference along a random direction is exact up to rounding
+    rng = np.random.default_rng(0)
+    dirn = torch.from_numpy(rng.standard_normal(vals.numel())).cuda() * (vals.detach() != 0)
+    h = 1e-6
+    with torch.no_grad():
+        ep = torch.dot(psi, H.apply(psi.detach(), "f64", ops=(vals + h * dirn).contiguous())).item()
+        em = torch.dot(psi, H.apply(psi.detach(), "f64", ops=(vals - h * dirn).contiguous())).item()
+    fd = (ep - em) / (2 * h)
+    an = torch.dot(vals.grad, dirn).item()
+    assert abs(fd - an) < 1e-7 * max(1.0, abs(an))
+
+
+def test_rdm_from_gpu_block_gradients(cases):
+    """Integral gradients of the FCI ground state from the GPU operator-block
+    gradients, contracted with the construction's strings, equal the
+    brute-force RDMs."""
+    P, H, tasks = cases["exact_L6"]
+    h, eri = molecular_integrals(6, 11)
+    C = Construction(h, eri, 6, 0, l=2)
+    Hf, dets = fci_hamiltonian(h, eri, 6, 0)
+    e, v = np.linalg.eigh(Hf.toarray())
+    idx = C.fci_map(P, dets)
+    x = v[idx, 0]
+    _, go = H.backward(to_dev(x), to_dev(x), "f64", want_psi=False)
+    _, _, dcoef = ograd.backward(P, x, x, tasks)
+    dh, dv = ograd.integral_gradients(C, P, go.cpu().numpy(), dcoef, h.shape)
+    g1, g2 = rdms(v[:, 0], dets, 6)
+    assert abs(dh - g1).max() < 1e-10 and abs(dv - 0.5 * g2).max() < 1e-10

@@ -1,0 +1,59 @@
+"""Device Davidson against FCI, the oracle and ARPACK; mixed precision
+energies against FP64."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as sla
+import torch
+
+from synth import synthetic_problem, gaussian_psi, gapped_guess
+from oracle import heff as oheff
+
+from gpu_common import say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_cfg1_davidson_fci(cfg1):
+    from paper_2305_05581_amd.tns import HeffProblem
+    P, Hf = cfg1["P"], cfg1["H"]
+    e_fci = sla.eigsh(Hf, k=1, which="SA", tol=1e-14)[0][0]
+    H = HeffProblem(P)
+    for inner in ("f64", "f32", "bf16x3"):
+        say("cfg1 davidson", inner)
+        e, x, info = H.davidson(to_dev(gaussian_psi(P, 1)), inner=inner, tol_res=1e-6)
+        say("  E %.12f  dE %.2e  %s" % (e, e - e_fci, info))
+        assert abs(e - e_fci) < 1e-8
+        assert info["res_norm"] < 1e-4
+        # the returned vector is normalised and reproduces the energy
+        xv = x.cpu().numpy()
+        assert abs(np.linalg.norm(xv) - 1) < 1e-12
+        assert abs(xv @ oheff.sigma(P, xv) - e) < 1e-10
+
+
+def test_gapped_davidson_mixed_vs_f64():
+    from paper_2305_05581_amd.tns import HeffProblem
+    P = synthetic_problem(20, 20, 0, 256, 16, 128, 400, seed=3, gapped=True)
+    tasks = oheff.enumerate_tasks(P)
+    op = sla.LinearOperator((P.psi_dim, P.psi_dim), matvec=lambda v: oheff.sigma(P, v, tasks), dtype=np.float64)
+    e_ref = sla.eigsh(op, k=1, which="SA", tol=1e-12, v0=gapped_guess(P, 2))[0][0]
+    H = HeffProblem(P)
+    x0 = to_dev(gapped_guess(P, 2))
+    e64, _, i64 = H.davidson(x0, inner="f64", tol_res=1e-7)
+    say("f64", e64, e64 - e_ref, i64)
+    assert abs(e64 - e_ref) < 1e-10
+    for inner in ("f32", "bf16x3"):
+        e, _, info = H.davidson(x0, inner=inner, tol_res=1e-5)
+        say(inner, e, e - e64, info)
+        assert abs(e - e64) < 1e-8
+        assert info["matvecs_f64"] >= 1
+
+
+def test_davidson_restart_small_subspace():
+    from paper_2305_05581_amd.tns import HeffProblem
+    P = synthetic_problem(16, 16, 0, 96, 8, 24, 60, seed=5, gapped=True)
+    H = HeffProblem(P)
+    x0 = to_dev(gapped_guess(P, 1))
+    a, _, ia = H.davidson(x0, tol_res=1e-8, max_sub=6, keep=2)
+    b, _, ib = H.davidson(x0, tol_res=1e-8)
+    say("restart", a, b, ia, ib)
+    assert abs(a - b) < 1e-10

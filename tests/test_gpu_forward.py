@@ -1,0 +1,94 @@
+"""GPU parity of the device task table and of sigma = H_eff psi against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from synth import synthetic_problem, gaussian_psi, molecular_integrals
+from oracle import heff as oheff
+from oracle.blocks import Construction
+
+from gpu_common import say, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 2e-4}
+
+
+def _instances():
+    return {
+        "tiny": lambda: synthetic_problem(10, 10, 0, 24, 3, 8, 40, seed=77),
+        "small_gapped": lambda: synthetic_problem(16, 16, 0, 96, 8, 24, 60, seed=5, gapped=True),
+        "cfg1_exact": lambda: Construction(*molecular_integrals(8, 1), 8, 0).problem(),
+        "ragged": lambda: synthetic_problem(22, 22, 0, 700, 23, 187, 120, seed=12),
+    }
+
+
+@pytest.fixture(scope="module")
+def built():
+    from paper_2305_05581_amd.tns import HeffProblem
+    out = {}
+    for name, mk in _instances().items():
+        say("build", name)
+        P = mk()
+        H = HeffProblem(P)
+        tasks, ptr = oheff.task_table(P)
+        out[name] = (P, H, tasks, ptr)
+    return out
+
+
+@pytest.mark.parametrize("name", list(_instances()))
+def test_tasklist_bit_exact(built, name):
+    P, H, tasks, ptr = built[name]
+    say("tasklist", name, len(tasks))
+    dt, dp = H.tasks()
+    assert len(dt) == len(tasks)
+    assert dt.tobytes() == tasks.tobytes()
+    assert np.array_equal(dp, ptr)
+    assert H.total_flops == int(tasks["cost"].sum())
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("name", list(_instances()))
+def test_sigma_parity(built, name, prec):
+    P, H, tasks, ptr = built[name]
+    psi = gaussian_psi(P, 3)
+    ref = oheff.sigma(P, psi, [tuple(t) for t in tasks.tolist()])
+    dt = torch.float64 if prec == "f64" else torch.float32
+    say("sigma", name, prec)
+    got = H.apply(to_dev(psi, dt), prec).double().cpu().numpy()
+    e = rel(got, ref)
+    say("  rel err", e)
+    assert e <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_accumulate_and_determinism(built, prec):
+    P, H, _, _ = built["small_gapped"]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    x = to_dev(gaussian_psi(P, 1), dt)
+    a = H.apply(x, prec)
+    b = H.apply(x, prec)
+    assert torch.equal(a, b)  # bitwise run to run
+    base = to_dev(gaussian_psi(P, 9), dt)
+    acc = base.clone()
+    H.apply(x, prec, out=acc, beta=1.0)
+    ref = base.double() + a.double()
+    assert rel(acc.double().cpu().numpy(), ref.cpu().numpy()) < (1e-15 if prec == "f64" else 1e-7)
+
+
+def test_hermitian_on_gpu(built):
+    P, H, _, _ = built["ragged"]
+    x = to_dev(gaussian_psi(P, 1))
+    y = to_dev(gaussian_psi(P, 2))
+    lhs = float(torch.dot(x, H.apply(y)))
+    rhs = float(torch.dot(H.apply(x), y))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_invalid_problem_rejected():
+    from paper_2305_05581_amd.tns import HeffProblem
+    P = synthetic_problem(10, 10, 0, 24, 3, 8, 10, seed=7)
+    P.op_dN = P.op_dN.copy()
+    P.op_dN[0] += 2  # blocks no longer at the operator's shift
+    with pytest.raises(ValueError):
+        HeffProblem(P)
