@@ -573,8 +573,12 @@ static ApplyArgs make_args(const Plan &p, const Sched &S, const void *ops, const
   return a;
 }
 
+static hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
+
 tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
                       void *ws, size_t ws_bytes, hipStream_t st) {
+  hipEvent_t evb = g_ev_before, eva = g_ev_after;
+  g_ev_before = g_ev_after = nullptr;
   const Sched &S = p.fwd;
   if (ws_bytes < apply_ws(S, p.psi_dim, prec)) return TNS_ERR_WORKSPACE;
   char *w = reinterpret_cast<char *>(ws);
@@ -585,13 +589,17 @@ tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void 
   const int ibeta = beta != 0.0;
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, queue);
   if (prec == TNS_F64) {
+    if (evb && eva) TNS_HIP(hipEventRecord(evb, st));
     if (S.nitems > 0)
       hipLaunchKernelGGL(k_apply<TNS_F64>, dim3(grid_for(k_apply<TNS_F64>, p.n_cu)), dim3(NWG), 0, st, a);
+    if (evb && eva) TNS_HIP(hipEventRecord(eva, st));
     hipLaunchKernelGGL(k_epilogue_psi<double>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 2,
                        S.grp_chunk_base, S.slot_off, (const double *)part, (double *)sigma, p.psi_dim, ibeta);
   } else if (prec == TNS_F32) {
+    if (evb && eva) TNS_HIP(hipEventRecord(evb, st));
     if (S.nitems > 0)
       hipLaunchKernelGGL(k_apply<TNS_F32>, dim3(grid_for(k_apply<TNS_F32>, p.n_cu)), dim3(NWG), 0, st, a);
+    if (evb && eva) TNS_HIP(hipEventRecord(eva, st));
     hipLaunchKernelGGL(k_epilogue_psi<float>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 2,
                        S.grp_chunk_base, S.slot_off, (const float *)part, (float *)sigma, p.psi_dim, ibeta);
   } else {
@@ -599,8 +607,10 @@ tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void 
     hipLaunchKernelGGL(k_split_f32, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, (const float *)psi, p.psi_dim,
                        psplit, psplit + p.psi_dim);
     a.psi = psplit;
+    if (evb && eva) TNS_HIP(hipEventRecord(evb, st));
     if (S.nitems > 0)
       hipLaunchKernelGGL(k_apply_bf16x3, dim3(grid_for(k_apply_bf16x3, p.n_cu)), dim3(NWG), 0, st, a);
+    if (evb && eva) TNS_HIP(hipEventRecord(eva, st));
     hipLaunchKernelGGL(k_epilogue_psi<float>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 2,
                        S.grp_chunk_base, S.slot_off, (const float *)part, (float *)sigma, p.psi_dim, ibeta);
   }
@@ -663,6 +673,11 @@ extern "C" tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, cons
   if (prec != TNS_F64 && prec != TNS_F32 && prec != TNS_BF16X3) return TNS_ERR_ARG;
   if (beta != 0.0 && beta != 1.0) return TNS_ERR_ARG;
   return apply_impl(plan_of(tl), prec, op_vals, psi, sigma, beta, ws, ws_bytes, st);
+}
+
+extern "C" void tns_profile_events(hipEvent_t before, hipEvent_t after) {
+  g_ev_before = before;
+  g_ev_after = after;
 }
 
 extern "C" size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec) {

@@ -93,6 +93,9 @@ def library(path=LIB_PATH):
         L.tns_davidson.restype = ctypes.c_int
         L.tns_davidson.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.POINTER(TnsDavidsonOpts), _P, _P, _P, _P,
                                    ctypes.POINTER(TnsDavidsonInfo), _P, sz, _P]
+    if hasattr(L, "tns_profile_events"):
+        L.tns_profile_events.restype = None
+        L.tns_profile_events.argtypes = [_P, _P]
     L.tns_status_string.restype = ctypes.c_char_p
     L.tns_status_string.argtypes = [ctypes.c_int]
     _lib = L
@@ -290,7 +293,52 @@ def _hip():
         _hiprt = ctypes.CDLL("libamdhip64.so")
         _hiprt.hipMemcpyAsync.restype = ctypes.c_int
         _hiprt.hipMemcpyAsync.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int, _P]
+        _hiprt.hipEventCreate.restype = ctypes.c_int
+        _hiprt.hipEventCreate.argtypes = [ctypes.POINTER(_P)]
+        _hiprt.hipEventDestroy.restype = ctypes.c_int
+        _hiprt.hipEventDestroy.argtypes = [_P]
+        _hiprt.hipEventSynchronize.restype = ctypes.c_int
+        _hiprt.hipEventSynchronize.argtypes = [_P]
+        _hiprt.hipEventElapsedTime.restype = ctypes.c_int
+        _hiprt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), _P, _P]
     return _hiprt
+
+
+class KernelTimer:
+    """HIP event pairs around the persistent kernel of successive forward
+    products (library profiling hook); ``arm()`` before each product."""
+
+    def __init__(self, n):
+        hip = _hip()
+        self.ev = []
+        for _ in range(n):
+            a, b = _P(), _P()
+            if hip.hipEventCreate(ctypes.byref(a)) or hip.hipEventCreate(ctypes.byref(b)):
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append((a, b))
+        self.i = 0
+
+    def arm(self):
+        a, b = self.ev[self.i]
+        library().tns_profile_events(a, b)
+        self.i += 1
+
+    def times_ms(self):
+        hip = _hip()
+        out = []
+        for a, b in self.ev[:self.i]:
+            hip.hipEventSynchronize(b)
+            ms = ctypes.c_float(0.0)
+            hip.hipEventElapsedTime(ctypes.byref(ms), a, b)
+            out.append(ms.value)
+        return out
+
+    def close(self):
+        hip = _hip()
+        for a, b in self.ev:
+            hip.hipEventDestroy(a)
+            hip.hipEventDestroy(b)
+        self.ev = []
 
 
 class HeffFunction(torch.autograd.Function):

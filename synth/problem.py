@@ -435,7 +435,7 @@ def synthetic_problem(L, N, twoSz, D, mean, dmax, K, seed, gapped=False, lam=0.0
         vals = np.zeros(ALIGN)
         meta["n_vals"] = off
     else:
-        vals = np.zeros(max(off, ALIGN), dtype=np.float64)
+        vals = np.empty(max(off, ALIGN), dtype=np.float64)
         _fill_values(vals, layout, op_first_blk, ops_src, (qL, dimL, qR, dimR, nl, nr), seed, threads)
     return _assemble((N, twoSz), qL, dimL, qR, dimR, psi_sec, psi_off, ops_meta, layout, terms, vals, meta)
 
@@ -445,11 +445,15 @@ def _fill_values(vals, layout, op_first_blk, ops_src, tables, seed, threads):
     nops = len(ops_src)
 
     def fill_random(o):
+        # one counter-based stream per operator, keyed by (seed, operator)
         g = np.random.Generator(np.random.Philox(key=[seed & 0xFFFFFFFFFFFFFFFF, o]))
         for b in range(op_first_blk[o], op_first_blk[o + 1]):
             _, i, j, r, c, ld, bo = layout[b]
-            v = vals[bo:bo + r * ld].reshape(r, ld)
-            v[:, :c] = g.standard_normal((r, c)) * (1.0 / np.sqrt(c))
+            v = vals[bo:bo + r * ld]
+            g.standard_normal(out=v)
+            v *= 1.0 / np.sqrt(c)
+            if ld > c:
+                v.reshape(r, ld)[:, c:] = 0.0
 
     def fill_derived(o):
         src = ops_src[o]
@@ -460,7 +464,9 @@ def _fill_values(vals, layout, op_first_blk, ops_src, tables, seed, threads):
                 _, i, j, r, c, ld, bo = layout[b]
                 sb = sblk[(j, i)]
                 _, _, _, sr, sc, sld, sbo = layout[sb]
-                vals[bo:bo + r * ld].reshape(r, ld)[:, :c] = vals[sbo:sbo + sr * sld].reshape(sr, sld)[:, :sc].T
+                dst = vals[bo:bo + r * ld].reshape(r, ld)
+                dst[:, :c] = vals[sbo:sbo + sr * sld].reshape(sr, sld)[:, :sc].T
+                dst[:, c:] = 0.0
         else:
             side = src[1]
             q, dims, nsite = (qL, dimL, nl) if side == 0 else (qR, dimR, nr)
@@ -470,6 +476,7 @@ def _fill_values(vals, layout, op_first_blk, ops_src, tables, seed, threads):
                 r2 = (int(q[i][0]) - Nc) ** 2 + (int(q[i][1]) - Sc) ** 2
                 d = int(dims[i])
                 v = vals[bo:bo + r * ld].reshape(r, ld)
+                v[:] = 0.0
                 v[np.arange(d), np.arange(d)] = 1.0 + np.arange(d) / d + 0.5 * r2
 
     prim = [o for o in range(nops) if ops_src[o] is None]
