@@ -263,7 +263,7 @@ __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int wi = s_item;
+    const int wi = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (wi >= a.nitems) break;
     const Item it = a.items[wi];
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(NWG) void k_apply_bf16x3(ApplyArgs a) {
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.queue, 1);
     __syncthreads();
-    const int wi = s_item;
+    const int wi = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (wi >= a.nitems) break;
     const Item it = a.items[wi];

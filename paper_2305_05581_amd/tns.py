@@ -138,7 +138,10 @@ class HeffProblem:
 
     def __init__(self, P, device="cuda", vals64=None):
         self.P = P
-        self.device = torch.device(device)
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
         L = library()
         self._host = {}
         cp = TnsProblem()
