@@ -21,6 +21,11 @@
 
 namespace tns {
 
+// Element-wise kernels walk their array with a grid stride: operator arrays
+// exceed the 2^32 work items that one dispatch can address.
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
 constexpr int KK = 32;    // K1 step of stage 1
 constexpr int KC = 32;    // column chunk of M (K of stage 2)
 constexpr int CMAX = 512; // output columns held in accumulators per pass
@@ -85,16 +90,18 @@ struct ApplyArgs {
   void *partial;         // acc type
   int64_t n_vals, psi_dim;
   int32_t mode_mask;     // bit m set: items of mode m are computed, others skipped
+  const void *zero;      // 64 zero bytes: out-of-range loads read here
 };
 
 // Operand view of one matrix for the loaders: element (i, k) at
 // base[i * si + k * sk]; identity when `ident`.
 struct View {
-  int64_t off;   // element offset
-  int64_t si, sk;
-  int rows, cols;
-  int ident;
-  int src;       // 0 = operator values, 1 = psi, 2 = grad sigma
+  const void *p;  // element (0, 0), resolved in the precision of the kernel
+  int32_t si, sk; // element (i, k) at p[i * si + k * sk]
+  int32_t rows, cols;
+  int32_t ident;  // identity operator: (i == k)
+  int32_t src;    // 0 = operator values, 1 = psi, 2 = grad sigma (loaders of the BF16 kernel)
+  int64_t off;    // element offset of (0, 0) in its array
 };
 
 template <int P> struct Tile;
@@ -242,23 +249,122 @@ __device__ inline void out_dims(const ApplyArgs &a, const Item &it, int *rows, i
 
 // ---------------------------------------------------------------------------
 // persistent kernel, FP32 / FP64
+//
+// Per task and per KC-wide chunk of the middle operand's columns:
+//   stage 1: V (TQ x KC) = X[p0.., :] M[:, chunk], K1 stepped by KK;
+//   stage 2: acc (TQ x C) += alpha V Y[:, chunk]^T, KC stepped by KS, each
+//            stage-2 step staging a KS-wide slice of Y for all C <= CMAX
+//            output columns so that every wave updates all its accumulators.
+// Every step's global loads go to registers one step ahead (including across
+// the stage boundaries and into the next chunk or task), so their latency
+// overlaps the MFMA work of the current step; one LDS buffer per tile.
 // ---------------------------------------------------------------------------
+template <int P> struct K3;
+template <> struct K3<TNS_F32> { static constexpr int KK = 32, KC = 64, KS = 8, PAD = 2; };
+template <> struct K3<TNS_F64> { static constexpr int KK = 32, KC = 64, KS = 8, PAD = 1; };
+
+// Task operands with element pointers resolved in precision T.
+template <class T>
+__device__ inline TaskOps task_ops_p(const ApplyArgs &a, const tns_task &t, int mode) {
+  TaskOps o = task_ops(a, t, mode);
+  View *vs[3] = {&o.X, &o.M, &o.Y};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    View &v = *vs[i];
+    const T *b = (const T *)(v.src == 0 ? a.ops : (v.src == 1 ? a.psi : a.grad));
+    v.p = b + v.off;
+  }
+  return o;
+}
+
+// Coordinates of thread element j of an R x CC tile walked with the
+// memory-contiguous index fastest (CFAST: columns, else rows) across the
+// workgroup's threads: element e = tid + NWG * j.
+template <int R, int CC, bool CFAST>
+__device__ inline void tile_rc(int tid, int j, int *r, int *c) {
+  if constexpr (CFAST) {
+    static_assert(NWG % CC == 0, "tile width must divide the workgroup");
+    *r = tid / CC + j * (NWG / CC);
+    *c = tid % CC;
+  } else if constexpr (R <= NWG) {
+    static_assert(NWG % R == 0, "tile height must divide the workgroup");
+    *r = tid % R;
+    *c = tid / R + j * (NWG / R);
+  } else {
+    static_assert(R % NWG == 0, "tile height must be a multiple of the workgroup");
+    *r = tid + NWG * (j % (R / NWG));
+    *c = j / (R / NWG);
+  }
+}
+
+// Registers <- tile T(r, c) = v(i0 + r, k0 + c), r < R, c < CC; thread element j
+// at tile_rc(tid, j), the memory-contiguous index fastest across
+// threads.  KDIM selects the reduction index of the tile (0: r, 1: c): it is
+// masked to zero beyond the matrix, while the other index is clamped to the
+// last row/column (such values only reach accumulator rows or columns that
+// are never written).  Loads are unconditional (no exec-mask branches).
+template <class T, int R, int CC, int N, bool CFAST, int KDIM>
+__device__ inline void tload(T *reg, const View &v, int i0, int k0, const T *zp) {
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));  // keep per-element offsets in the step (no hoisting)
+  const T *p = (const T *)v.p;
+  const int si = v.si, sk = v.sk, rmax = v.rows - 1, cmax = v.cols - 1;
+  // the identity test is uniform: keep it outside the unrolled loops so that
+  // the loads form one straight-line block (issued back to back, one wait)
+  if (v.ident) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      int r, c;
+      tile_rc<R, CC, CFAST>(tid, j, &r, &c);
+      const int i = i0 + r, k = k0 + c;
+      reg[j] = (i == k && i <= rmax && k <= cmax) ? T(1) : T(0);
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int r, c;
+    tile_rc<R, CC, CFAST>(tid, j, &r, &c);
+    const int i = i0 + r, k = k0 + c;
+    const bool in = KDIM == 0 ? (i <= rmax) : (k <= cmax);
+    const int ic = KDIM == 0 ? i : min(i, rmax);
+    const int kc = KDIM == 1 ? k : min(k, cmax);
+    // select the address, not the value: nothing waits on the load here
+    reg[j] = *(in ? p + (ic * si + kc * sk) : zp);
+  }
+}
+
+// LDS <- registers of tload: element (r, c) at [r][c] (TRANS: [c][r]), stride S.
+template <class T, int R, int CC, int N, bool CFAST, bool TRANS, int S>
+__device__ inline void tstore(T *lds, const T *reg) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int r, c;
+    tile_rc<R, CC, CFAST>(tid, j, &r, &c);
+    lds[TRANS ? c * S + r : r * S + c] = reg[j];
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
   typedef typename Prec<P>::acc T;
   typedef typename Prec<P>::accv V4;
-  constexpr int S = Prec<P>::S;
-  constexpr int SV = KC + 2;
-  constexpr int NU = CMAX / 64;  // column tiles per wave
-  __shared__ TileStore<P> sm;
+  constexpr int KK_ = K3<P>::KK, KC_ = K3<P>::KC, KS_ = K3<P>::KS;
+  constexpr int SX = KK_ + K3<P>::PAD, SV = KC_ + K3<P>::PAD, SY = KS_ + K3<P>::PAD;
+  constexpr int NRT = TQ / 16;
+  constexpr int NU = CMAX / 64;
+  constexpr int NX = TQ * KK_ / NWG, NM = KK_ * KC_ / NWG, NY = CMAX * KS_ / NWG;
+  static_assert(TQ == 32 && KC_ == 64, "stage 1 maps V column tile w to wave w");
+  __shared__ T xs[TQ * SX];
+  __shared__ T ms[KC_ * SX];
+  __shared__ T vs[TQ * SV];
+  __shared__ T ys[CMAX * SY];
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
-  Bases<T> src;
-  src.ops = reinterpret_cast<const T *>(a.ops);
-  src.psi = reinterpret_cast<const T *>(a.psi);
-  src.grad = reinterpret_cast<const T *>(a.grad);
   T *part = reinterpret_cast<T *>(a.partial);
+  const T *zp = reinterpret_cast<const T *>(a.zero);
 
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.queue, 1);
@@ -268,67 +374,108 @@ __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
     if (wi >= a.nitems) break;
     const Item it = a.items[wi];
     if (!((a.mode_mask >> it.mode) & 1)) continue;
-    int Rtot, C;
-    out_dims(a, it, &Rtot, &C);
+    int Rtot, Ctot;
+    out_dims(a, it, &Rtot, &Ctot);
     T *slot = part + a.slot_off[it.slot];
-    for (int ct0 = 0; ct0 < C; ct0 += CMAX) {
-      const int Cn = min(CMAX, C - ct0);
+    const int p0 = it.p0;
+    for (int ct0 = 0; ct0 < Ctot; ct0 += CMAX) {
+      const int Cn = min(CMAX, Ctot - ct0);
       const int njt = (Cn + 15) >> 4;
-      V4 acc[2][NU];
+      V4 acc[NRT][NU];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+      for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int u = 0; u < NU; ++u) acc[rt][u] = vzero<V4>();
+      T r1[NX + NM];
+      T r2[NY];
+      auto load1 = [&](const TaskOps &o, int c0, int k0) {
+        if (o.X.sk == 1 || o.X.ident) tload<T, TQ, KK_, NX, true, 1>(r1, o.X, p0, k0, zp);
+        else tload<T, TQ, KK_, NX, false, 1>(r1, o.X, p0, k0, zp);
+        if (o.M.sk == 1) tload<T, KK_, KC_, NM, true, 0>(r1 + NX, o.M, k0, c0, zp);
+        else tload<T, KK_, KC_, NM, false, 0>(r1 + NX, o.M, k0, c0, zp);
+      };
+      auto store1 = [&](const TaskOps &o) {
+        if (o.X.sk == 1 || o.X.ident) tstore<T, TQ, KK_, NX, true, false, SX>(xs, r1);
+        else tstore<T, TQ, KK_, NX, false, false, SX>(xs, r1);
+        if (o.M.sk == 1) tstore<T, KK_, KC_, NM, true, true, SX>(ms, r1 + NX);
+        else tstore<T, KK_, KC_, NM, false, true, SX>(ms, r1 + NX);
+      };
+      auto load2 = [&](const TaskOps &o, int c) {
+        if (o.Y.sk == 1 || o.Y.ident) tload<T, CMAX, KS_, NY, true, 1>(r2, o.Y, ct0, c, zp);
+        else tload<T, CMAX, KS_, NY, false, 1>(r2, o.Y, ct0, c, zp);
+      };
+      auto store2 = [&](const TaskOps &o) {
+        if (o.Y.sk == 1 || o.Y.ident) tstore<T, CMAX, KS_, NY, true, false, SY>(ys, r2);
+        else tstore<T, CMAX, KS_, NY, false, false, SY>(ys, r2);
+      };
 
-      for (int ti = it.tb; ti < it.te; ++ti) {
-        const tns_task tk = a.tasks[a.idx[ti]];
-        const TaskOps o = task_ops(a, tk, it.mode);
-        const T alpha = (T)o.alpha;
-        for (int c0 = 0; c0 < o.K2; c0 += KC) {
-          // ---- stage 1: V = X[p0.., :] M[:, c0..] ------------------------
-          V4 vacc = vzero<V4>();
-          const int rt1 = w & 1, ct1 = w >> 1;
-          for (int k0 = 0; k0 < o.K1; k0 += KK) {
-            load_tile(sm.x, S, TQ, KK, src, o.X, it.p0, k0);
-            // M chunk stored transposed: m[c][k] = M(k0 + k, c0 + c)
-            load_tile(sm.m, S, KC, KK, src, transposed(o.M), c0, k0);
-            __syncthreads();
+      int ti = it.tb, c0 = 0;
+      TaskOps ops = task_ops_p<T>(a, a.tasks[a.idx[ti]], it.mode);
+      load1(ops, 0, 0);
+      for (;;) {
+        // ---- stage 1 -------------------------------------------------------------
+        V4 vacc[NRT];
 #pragma unroll
-            for (int kk = 0; kk < KK; kk += 4) {
-              const T av = sm.x[(rt1 * 16 + l16) * S + kk + lg];
-              const T bv = sm.m[(ct1 * 16 + l16) * S + kk + lg];
-              vacc = mfma(av, bv, vacc);
-            }
-            __syncthreads();
+        for (int rt = 0; rt < NRT; ++rt) vacc[rt] = vzero<V4>();
+        for (int k0 = 0; k0 < ops.K1; k0 += KK_) {
+          __syncthreads();
+          store1(ops);
+          __syncthreads();
+          if (k0 + KK_ < ops.K1) load1(ops, c0, k0 + KK_);
+          else load2(ops, c0);
+#pragma unroll
+          for (int kk = 0; kk < KK_; kk += 4) {
+            const T bv = ms[(w * 16 + l16) * SX + kk + lg];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt) vacc[rt] = mfma(xs[(rt * 16 + l16) * SX + kk + lg], bv, vacc[rt]);
           }
+        }
+        // publish alpha V: wave w owns V column tile w (the previous chunk's
+        // stage-2 reads of vs ended before the barriers of this stage 1)
+        {
+          const T al = (T)ops.alpha;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) sm.v[(rt1 * 16 + lg * 4 + v) * SV + ct1 * 16 + l16] = alpha * vacc[v];
-          // ---- stage 2: acc += V Y[:, c0..]^T, Y staged YG columns at a time
-          for (int g0 = 0; g0 < Cn; g0 += YG) {
-            __syncthreads();
-            load_tile(sm.y, SV, min(YG, (Cn - g0 + 15) & ~15), KC, src, o.Y, ct0 + g0, c0);
-            __syncthreads();
+          for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-            for (int kc = 0; kc < KC; kc += 4) {
-              const T a0 = sm.v[(0 * 16 + l16) * SV + kc + lg];
-              const T a1 = sm.v[(1 * 16 + l16) * SV + kc + lg];
+            for (int v = 0; v < 4; ++v) vs[(rt * 16 + lg * 4 + v) * SV + w * 16 + l16] = al * vacc[rt][v];
+        }
+        // next chunk / task, for the prefetch at the end of stage 2
+        int nc0 = c0 + KC_, nti = ti;
+        if (nc0 >= ops.K2) { nti = ti + 1; nc0 = 0; }
+        const bool more = nti < it.te;
+        TaskOps nops = ops;
+        if (more && nti != ti) nops = task_ops_p<T>(a, a.tasks[a.idx[nti]], it.mode);
+        // ---- stage 2 -------------------------------------------------------------
+        const int send = min(KC_, ops.K2 - c0);
+        for (int s2 = 0; s2 < send; s2 += KS_) {
+          __syncthreads();
+          store2(ops);
+          __syncthreads();
+          if (s2 + KS_ < send) load2(ops, c0 + s2 + KS_);
+          else if (more) load1(nops, nc0, 0);
 #pragma unroll
-              for (int u = 0; u < NU; ++u) {
-                const int jt = w + 4 * u;  // global column tile within the pass
-                if (jt * 16 >= g0 && jt * 16 < g0 + YG && jt < njt) {
-                  const T bv = sm.y[(jt * 16 - g0 + l16) * SV + kc + lg];
-                  acc[0][u] = mfma(a0, bv, acc[0][u]);
-                  acc[1][u] = mfma(a1, bv, acc[1][u]);
-                }
+          for (int kc = 0; kc < KS_; kc += 4) {
+            T av[NRT];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt) av[rt] = vs[(rt * 16 + l16) * SV + s2 + kc + lg];
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+              if (w + 4 * u < njt) {
+                const T bv = ys[((w + 4 * u) * 16 + l16) * SY + kc + lg];
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) acc[rt][u] = mfma(av[rt], bv, acc[rt][u]);
               }
             }
           }
-          __syncthreads();
         }
+        if (!more) break;
+        ti = nti;
+        c0 = nc0;
+        ops = nops;
       }
-      // ---- write the panel into the partial slot -----------------------------
+      // ---- write the panel into the partial slot ---------------------------------
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+      for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           const int jt = w + 4 * u;
@@ -337,34 +484,109 @@ __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
             for (int v = 0; v < 4; ++v) {
               const int row = rt * 16 + lg * 4 + v;
               const int col = ct0 + jt * 16 + l16;
-              if (row < it.np && col < C) {
-                const int64_t idx = it.mode == M_FWD1 ? ((int64_t)col * Rtot + it.p0 + row)
-                                                      : ((int64_t)(it.p0 + row) * C + col);
+              if (row < it.np && col < Ctot) {
+                const int64_t idx = it.mode == M_FWD1 ? ((int64_t)col * Rtot + p0 + row)
+                                                      : ((int64_t)(p0 + row) * Ctot + col);
                 slot[idx] = acc[rt][u][v];
               }
             }
           }
         }
+      __syncthreads();  // LDS reuse by the next pass / item
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // persistent kernel, split BF16 (three products, FP32 accumulation)
+//
+// Same step pipeline as k_apply; operands are (hi, lo) BF16 pairs, packed in
+// registers as hi | lo << 16 and stored in separate LDS planes so that one
+// 16-byte LDS read feeds an MFMA operand (8 consecutive k).
 // ---------------------------------------------------------------------------
+constexpr int BKK = 64, BKC = 64, BKS = 32, BPAD = 8;
+
+__device__ inline View bview(const ApplyArgs &a, View v) {
+  const uint16_t *h = (const uint16_t *)(v.src == 0 ? a.ops : a.psi);
+  v.p = h + v.off;
+  return v;
+}
+
+__device__ inline TaskOps task_ops_bf(const ApplyArgs &a, const tns_task &t, int mode) {
+  TaskOps o = task_ops(a, t, mode);
+  o.X = bview(a, o.X);
+  o.M = bview(a, o.M);
+  o.Y = bview(a, o.Y);
+  return o;
+}
+
+// As tload, for split BF16: the lo plane sits `plane` elements after the hi
+// plane of the same array.
+template <int R, int CC, int N, bool CFAST, int KDIM>
+__device__ inline void tload_bf(uint32_t *rh, uint32_t *rl, const View &v, int i0, int k0, int64_t plane_ops,
+                                int64_t plane_psi, const uint16_t *zp) {
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  const uint16_t *h = (const uint16_t *)v.p;
+  const uint16_t *l = h + (v.src == 0 ? plane_ops : plane_psi);
+  const int si = v.si, sk = v.sk, rmax = v.rows - 1, cmax = v.cols - 1;
+  if (v.ident) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      int r, c;
+      tile_rc<R, CC, CFAST>(tid, j, &r, &c);
+      const int i = i0 + r, k = k0 + c;
+      rh[j] = (i == k && i <= rmax && k <= cmax) ? 0x3f80u : 0u;
+      rl[j] = 0u;
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int r, c;
+    tile_rc<R, CC, CFAST>(tid, j, &r, &c);
+    const int i = i0 + r, k = k0 + c;
+    const bool in = KDIM == 0 ? (i <= rmax) : (k <= cmax);
+    const int ic = KDIM == 0 ? i : min(i, rmax);
+    const int kc = KDIM == 1 ? k : min(k, cmax);
+    const int off = ic * si + kc * sk;
+    rh[j] = *(in ? h + off : zp);
+    rl[j] = *(in ? l + off : zp);
+  }
+}
+
+template <int R, int CC, int N, bool CFAST, bool TRANS, int S, int PL>
+__device__ inline void tstore_bf(uint16_t *lds, const uint32_t *rh, const uint32_t *rl) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    int r, c;
+    tile_rc<R, CC, CFAST>(tid, j, &r, &c);
+    const int o = TRANS ? c * S + r : r * S + c;
+    lds[o] = (uint16_t)rh[j];
+    lds[PL + o] = (uint16_t)rl[j];
+  }
+}
+
+struct __attribute__((aligned(16))) SmemBF {
+  uint16_t x[2 * TQ * (BKK + BPAD)];
+  uint16_t m[2 * BKC * (BKK + BPAD)];
+  uint16_t v[2 * TQ * (BKC + BPAD)];
+  uint16_t y[2 * CMAX * (BKS + BPAD)];
+};
+
 __global__ __launch_bounds__(NWG) void k_apply_bf16x3(ApplyArgs a) {
-  constexpr int S = KK + 8;
-  constexpr int SV = KC + 8;
-  constexpr int NU = CMAX / 64;
-  __shared__ TileStoreBF sm;
+  constexpr int SX = BKK + BPAD, SV = BKC + BPAD, SY = BKS + BPAD;
+  constexpr int PX = TQ * SX, PM = BKC * SX, PV = TQ * SV, PY = CMAX * SY;
+  constexpr int NRT = TQ / 16, NU = CMAX / 64;
+  constexpr int NX = TQ * BKK / NWG, NM = BKK * BKC / NWG, NY = CMAX * BKS / NWG;
+  __shared__ SmemBF sm;
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
-  const uint16_t *oh = reinterpret_cast<const uint16_t *>(a.ops);
-  const uint16_t *ol = oh + a.n_vals;
-  const uint16_t *ph = reinterpret_cast<const uint16_t *>(a.psi);
-  const uint16_t *pl = ph + a.psi_dim;
   float *part = reinterpret_cast<float *>(a.partial);
+  const int64_t pl_ops = a.n_vals, pl_psi = a.psi_dim;
+  const uint16_t *zp = reinterpret_cast<const uint16_t *>(a.zero);
 
   for (;;) {
     if (tid == 0) s_item = atomicAdd(a.queue, 1);
@@ -373,76 +595,124 @@ __global__ __launch_bounds__(NWG) void k_apply_bf16x3(ApplyArgs a) {
     __syncthreads();
     if (wi >= a.nitems) break;
     const Item it = a.items[wi];
-    int Rtot, C;
-    out_dims(a, it, &Rtot, &C);
+    int Rtot, Ctot;
+    out_dims(a, it, &Rtot, &Ctot);
     float *slot = part + a.slot_off[it.slot];
-    for (int ct0 = 0; ct0 < C; ct0 += CMAX) {
-      const int Cn = min(CMAX, C - ct0);
+    const int p0 = it.p0;
+    for (int ct0 = 0; ct0 < Ctot; ct0 += CMAX) {
+      const int Cn = min(CMAX, Ctot - ct0);
       const int njt = (Cn + 15) >> 4;
-      f4 acc[2][NU];
+      f4 acc[NRT][NU];
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+      for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int u = 0; u < NU; ++u) acc[rt][u] = vzero<f4>();
+      uint32_t r1h[NX + NM], r1l[NX + NM];
+      uint32_t r2h[NY], r2l[NY];
+      auto load1 = [&](const TaskOps &o, int c0, int k0) {
+        if (o.X.sk == 1 || o.X.ident) tload_bf<TQ, BKK, NX, true, 1>(r1h, r1l, o.X, p0, k0, pl_ops, pl_psi, zp);
+        else tload_bf<TQ, BKK, NX, false, 1>(r1h, r1l, o.X, p0, k0, pl_ops, pl_psi, zp);
+        if (o.M.sk == 1) tload_bf<BKK, BKC, NM, true, 0>(r1h + NX, r1l + NX, o.M, k0, c0, pl_ops, pl_psi, zp);
+        else tload_bf<BKK, BKC, NM, false, 0>(r1h + NX, r1l + NX, o.M, k0, c0, pl_ops, pl_psi, zp);
+      };
+      auto store1 = [&](const TaskOps &o) {
+        if (o.X.sk == 1 || o.X.ident) tstore_bf<TQ, BKK, NX, true, false, SX, PX>(sm.x, r1h, r1l);
+        else tstore_bf<TQ, BKK, NX, false, false, SX, PX>(sm.x, r1h, r1l);
+        if (o.M.sk == 1) tstore_bf<BKK, BKC, NM, true, true, SX, PM>(sm.m, r1h + NX, r1l + NX);
+        else tstore_bf<BKK, BKC, NM, false, true, SX, PM>(sm.m, r1h + NX, r1l + NX);
+      };
+      auto load2 = [&](const TaskOps &o, int c) {
+        if (o.Y.sk == 1 || o.Y.ident) tload_bf<CMAX, BKS, NY, true, 1>(r2h, r2l, o.Y, ct0, c, pl_ops, pl_psi, zp);
+        else tload_bf<CMAX, BKS, NY, false, 1>(r2h, r2l, o.Y, ct0, c, pl_ops, pl_psi, zp);
+      };
+      auto store2 = [&](const TaskOps &o) {
+        if (o.Y.sk == 1 || o.Y.ident) tstore_bf<CMAX, BKS, NY, true, false, SY, PY>(sm.y, r2h, r2l);
+        else tstore_bf<CMAX, BKS, NY, false, false, SY, PY>(sm.y, r2h, r2l);
+      };
 
-      for (int ti = it.tb; ti < it.te; ++ti) {
-        const tns_task tk = a.tasks[a.idx[ti]];
-        const TaskOps o = task_ops(a, tk, it.mode);
-        const float alpha = (float)o.alpha;
-        for (int c0 = 0; c0 < o.K2; c0 += KC) {
-          f4 vacc = vzero<f4>();
-          const int rt1 = w & 1, ct1 = w >> 1;
-          for (int k0 = 0; k0 < o.K1; k0 += KK) {
-            load_tile_bf(sm.xh, sm.xl, S, TQ, KK, oh, ol, o.X, it.p0, k0);
-            load_tile_bf(sm.mh, sm.ml, S, KC, KK, ph, pl, transposed(o.M), c0, k0);
-            __syncthreads();
-            const u16x8 ah = *reinterpret_cast<const u16x8 *>(&sm.xh[(rt1 * 16 + l16) * S + 8 * lg]);
-            const u16x8 al = *reinterpret_cast<const u16x8 *>(&sm.xl[(rt1 * 16 + l16) * S + 8 * lg]);
-            const u16x8 bh = *reinterpret_cast<const u16x8 *>(&sm.mh[(ct1 * 16 + l16) * S + 8 * lg]);
-            const u16x8 bl = *reinterpret_cast<const u16x8 *>(&sm.ml[(ct1 * 16 + l16) * S + 8 * lg]);
-            vacc = mfma_bf(al, bh, vacc);
-            vacc = mfma_bf(ah, bl, vacc);
-            vacc = mfma_bf(ah, bh, vacc);
-            __syncthreads();
+      int ti = it.tb, c0 = 0;
+      TaskOps ops = task_ops_bf(a, a.tasks[a.idx[ti]], it.mode);
+      load1(ops, 0, 0);
+      for (;;) {
+        f4 vacc[NRT];
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) vacc[rt] = vzero<f4>();
+        for (int k0 = 0; k0 < ops.K1; k0 += BKK) {
+          __syncthreads();
+          store1(ops);
+          __syncthreads();
+          if (k0 + BKK < ops.K1) load1(ops, c0, k0 + BKK);
+          else load2(ops, c0);
+#pragma unroll
+          for (int kk = 0; kk < BKK; kk += 32) {
+            const int mo = (w * 16 + l16) * SX + kk + 8 * lg;
+            const u16x8 bh = *reinterpret_cast<const u16x8 *>(&sm.m[mo]);
+            const u16x8 bl = *reinterpret_cast<const u16x8 *>(&sm.m[PM + mo]);
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt) {
+              const int xo = (rt * 16 + l16) * SX + kk + 8 * lg;
+              const u16x8 ah = *reinterpret_cast<const u16x8 *>(&sm.x[xo]);
+              const u16x8 al = *reinterpret_cast<const u16x8 *>(&sm.x[PX + xo]);
+              vacc[rt] = mfma_bf(al, bh, vacc[rt]);
+              vacc[rt] = mfma_bf(ah, bl, vacc[rt]);
+              vacc[rt] = mfma_bf(ah, bh, vacc[rt]);
+            }
+          }
+        }
+        {
+          const float al = (float)ops.alpha;
+#pragma unroll
+          for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float x = al * vacc[rt][v];
+              const uint16_t h = f32_to_bf16_rne(x);
+              const int o = (rt * 16 + lg * 4 + v) * SV + w * 16 + l16;
+              sm.v[o] = h;
+              sm.v[PV + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
+            }
+        }
+        int nc0 = c0 + BKC, nti = ti;
+        if (nc0 >= ops.K2) { nti = ti + 1; nc0 = 0; }
+        const bool more = nti < it.te;
+        TaskOps nops = ops;
+        if (more && nti != ti) nops = task_ops_bf(a, a.tasks[a.idx[nti]], it.mode);
+        const int send = min(BKC, ops.K2 - c0);
+        for (int s2 = 0; s2 < send; s2 += BKS) {
+          __syncthreads();
+          store2(ops);
+          __syncthreads();
+          if (s2 + BKS < send) load2(ops, c0 + s2 + BKS);
+          else if (more) load1(nops, nc0, 0);
+          u16x8 ah[NRT], al[NRT];
+#pragma unroll
+          for (int rt = 0; rt < NRT; ++rt) {
+            const int vo = (rt * 16 + l16) * SV + s2 + 8 * lg;
+            ah[rt] = *reinterpret_cast<const u16x8 *>(&sm.v[vo]);
+            al[rt] = *reinterpret_cast<const u16x8 *>(&sm.v[PV + vo]);
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float x = alpha * vacc[v];
-            const uint16_t h = f32_to_bf16_rne(x);
-            const uint16_t l = f32_to_bf16_rne(x - bf16_to_f32(h));
-            const int idx = (rt1 * 16 + lg * 4 + v) * SV + ct1 * 16 + l16;
-            sm.vh[idx] = h;
-            sm.vl[idx] = l;
-          }
-          for (int g0 = 0; g0 < Cn; g0 += YG) {
-            __syncthreads();
-            load_tile_bf(sm.yh, sm.yl, SV, min(YG, (Cn - g0 + 15) & ~15), KC, oh, ol, o.Y, ct0 + g0, c0);
-            __syncthreads();
-            const u16x8 a0h = *reinterpret_cast<const u16x8 *>(&sm.vh[(0 * 16 + l16) * SV + 8 * lg]);
-            const u16x8 a0l = *reinterpret_cast<const u16x8 *>(&sm.vl[(0 * 16 + l16) * SV + 8 * lg]);
-            const u16x8 a1h = *reinterpret_cast<const u16x8 *>(&sm.vh[(1 * 16 + l16) * SV + 8 * lg]);
-            const u16x8 a1l = *reinterpret_cast<const u16x8 *>(&sm.vl[(1 * 16 + l16) * SV + 8 * lg]);
+          for (int u = 0; u < NU; ++u) {
+            if (w + 4 * u < njt) {
+              const int yo = ((w + 4 * u) * 16 + l16) * SY + 8 * lg;
+              const u16x8 bh = *reinterpret_cast<const u16x8 *>(&sm.y[yo]);
+              const u16x8 bl = *reinterpret_cast<const u16x8 *>(&sm.y[PY + yo]);
 #pragma unroll
-            for (int u = 0; u < NU; ++u) {
-              const int jt = w + 4 * u;
-              if (jt * 16 >= g0 && jt * 16 < g0 + YG && jt < njt) {
-                const int yo = (jt * 16 - g0 + l16) * SV + 8 * lg;
-                const u16x8 bh = *reinterpret_cast<const u16x8 *>(&sm.yh[yo]);
-                const u16x8 bl = *reinterpret_cast<const u16x8 *>(&sm.yl[yo]);
-                acc[0][u] = mfma_bf(a0l, bh, acc[0][u]);
-                acc[0][u] = mfma_bf(a0h, bl, acc[0][u]);
-                acc[0][u] = mfma_bf(a0h, bh, acc[0][u]);
-                acc[1][u] = mfma_bf(a1l, bh, acc[1][u]);
-                acc[1][u] = mfma_bf(a1h, bl, acc[1][u]);
-                acc[1][u] = mfma_bf(a1h, bh, acc[1][u]);
+              for (int rt = 0; rt < NRT; ++rt) {
+                acc[rt][u] = mfma_bf(al[rt], bh, acc[rt][u]);
+                acc[rt][u] = mfma_bf(ah[rt], bl, acc[rt][u]);
+                acc[rt][u] = mfma_bf(ah[rt], bh, acc[rt][u]);
               }
             }
           }
-          __syncthreads();
         }
+        if (!more) break;
+        ti = nti;
+        c0 = nc0;
+        ops = nops;
       }
 #pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
+      for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           const int jt = w + 4 * u;
@@ -451,14 +721,15 @@ __global__ __launch_bounds__(NWG) void k_apply_bf16x3(ApplyArgs a) {
             for (int v = 0; v < 4; ++v) {
               const int row = rt * 16 + lg * 4 + v;
               const int col = ct0 + jt * 16 + l16;
-              if (row < it.np && col < C) {
-                const int64_t idx = it.mode == M_FWD1 ? ((int64_t)col * Rtot + it.p0 + row)
-                                                      : ((int64_t)(it.p0 + row) * C + col);
+              if (row < it.np && col < Ctot) {
+                const int64_t idx = it.mode == M_FWD1 ? ((int64_t)col * Rtot + p0 + row)
+                                                      : ((int64_t)(p0 + row) * Ctot + col);
                 slot[idx] = acc[rt][u][v];
               }
             }
           }
         }
+      __syncthreads();
     }
   }
 }
@@ -472,19 +743,19 @@ template <class T>
 __global__ void k_epilogue_psi(const int64_t *__restrict__ psi_off, int nS, int gps,
                                const int64_t *__restrict__ grp_chunk_base, const int64_t *__restrict__ slot_off,
                                const T *__restrict__ part, T *__restrict__ out, int64_t psi_dim, int beta) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= psi_dim) return;
-  int lo = 0, hi = nS;  // s with psi_off[s] <= e < psi_off[s+1]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (psi_off[mid] <= e) lo = mid; else hi = mid;
+  GRID_STRIDE(e, psi_dim) {
+    int lo = 0, hi = nS;  // s with psi_off[s] <= e < psi_off[s+1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (psi_off[mid] <= e) lo = mid; else hi = mid;
+    }
+    const int s = lo;
+    const int64_t loc = e - psi_off[s];
+    double acc = beta ? (double)out[e] : 0.0;
+    const int64_t c0 = grp_chunk_base[gps * s], c1 = grp_chunk_base[gps * s + gps];
+    for (int64_t c = c0; c < c1; ++c) acc += (double)part[slot_off[c] + loc];
+    out[e] = (T)acc;
   }
-  const int s = lo;
-  const int64_t loc = e - psi_off[s];
-  double acc = beta ? (double)out[e] : 0.0;
-  const int64_t c0 = grp_chunk_base[gps * s], c1 = grp_chunk_base[gps * s + gps];
-  for (int64_t c = c0; c < c1; ++c) acc += (double)part[slot_off[c] + loc];
-  out[e] = (T)acc;
 }
 
 // operator-block outputs (d L, d R): one workgroup per block, group nS + b.
@@ -505,44 +776,48 @@ __global__ void k_epilogue_blk(int nS, const int64_t *__restrict__ grp_chunk_bas
   }
 }
 
-__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+// queue counter and the 64-byte zero region that out-of-range loads read
+__global__ void k_reset_head(int32_t *p) {
+  if (threadIdx.x < 32) p[threadIdx.x] = 0;
+}
 
 template <class T>
 __global__ void k_zero(T *p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = T(0);
+  GRID_STRIDE(i, n) p[i] = T(0);
 }
 
 __global__ void k_split_f32(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float v = x[i];
-  const uint16_t h = f32_to_bf16_rne(v);
-  hi[i] = h;
-  lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
+  GRID_STRIDE(i, n) {
+    const float v = x[i];
+    const uint16_t h = f32_to_bf16_rne(v);
+    hi[i] = h;
+    lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
+  }
 }
 
 __global__ void k_split_f64(const double *__restrict__ x, int64_t n, uint16_t *__restrict__ hi,
                             uint16_t *__restrict__ lo) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float v = (float)x[i];
-  const uint16_t h = f32_to_bf16_rne(v);
-  hi[i] = h;
-  lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
+  GRID_STRIDE(i, n) {
+    const float v = (float)x[i];
+    const uint16_t h = f32_to_bf16_rne(v);
+    hi[i] = h;
+    lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
+  }
 }
 
 __global__ void k_f64_to_f32(const double *__restrict__ x, int64_t n, float *__restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = (float)x[i];
+  GRID_STRIDE(i, n) y[i] = (float)x[i];
 }
 
 __global__ void k_copy_f64(const double *__restrict__ x, int64_t n, double *__restrict__ y) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[i];
+  GRID_STRIDE(i, n) y[i] = x[i];
 }
 
-static inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// Blocks for an element-wise launch over n elements (capped; kernels stride).
+static inline unsigned nb(int64_t n, int b) {
+  const int64_t g = (n + b - 1) / b;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 16));
+}
 
 static size_t elem_bytes(tns_prec p) { return p == TNS_F64 ? 8 : 4; }
 
@@ -570,6 +845,7 @@ static ApplyArgs make_args(const Plan &p, const Sched &S, const void *ops, const
   a.ops = ops; a.psi = psi; a.grad = grad; a.partial = part;
   a.n_vals = p.n_vals; a.psi_dim = p.psi_dim;
   a.mode_mask = 0x1f;
+  a.zero = reinterpret_cast<const char *>(queue) + 64;
   return a;
 }
 
@@ -587,7 +863,7 @@ tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void 
   const size_t pbytes = align_up((size_t)std::max<int64_t>(S.partial_elems, 1) * elem_bytes(prec), 256);
   ApplyArgs a = make_args(p, S, ops, psi, nullptr, part, queue);
   const int ibeta = beta != 0.0;
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, queue);
+  hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(32), 0, st, queue);
   if (prec == TNS_F64) {
     if (evb && eva) TNS_HIP(hipEventRecord(evb, st));
     if (S.nitems > 0)
@@ -627,7 +903,7 @@ static tns_status backward_impl(const Plan &p, const void *ops, const void *psi,
   T *part = reinterpret_cast<T *>(w + 256);
   ApplyArgs a = make_args(p, S, ops, psi, G, part, queue);
   a.mode_mask = (gpsi ? (1 << M_DPSI) : 0) | (gops ? ((1 << M_DL) | (1 << M_DR)) : 0);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, queue);
+  hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(32), 0, st, queue);
   if (S.nitems > 0) hipLaunchKernelGGL(k_apply<P>, dim3(grid_for(k_apply<P>, p.n_cu)), dim3(NWG), 0, st, a);
   if (gpsi)
     hipLaunchKernelGGL(k_epilogue_psi<T>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 1,
