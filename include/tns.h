@@ -28,8 +28,10 @@
  *   element offset psi_off[s].  sigma has the same layout.
  * - Operator blocks are row-major matrices (rows = dimension of the output
  *   sector, cols = dimension of the input sector) at element offset blk_off
- *   with leading dimension blk_ld (>= cols) in one value array.  An operator
- *   has at most one block per input sector, mapping in -> in + shift.
+ *   with leading dimension blk_ld (>= cols) in one value array; blk_off and
+ *   blk_ld are multiples of 8 and blk_off + rows * blk_ld <= n_vals, so that
+ *   the kernels read every row as 16-byte vectors.  An operator has at most
+ *   one block per input sector, mapping in -> in + shift.
  * - Terms are (op_L, mono_a, mono_b, op_R, coef); op id -1 is the identity.
  *
  * Ownership and errors
@@ -95,7 +97,7 @@ typedef struct {
   const int32_t *blk_out;    /* [nBlk] output sector (= in + shift)                  */
   const int32_t *blk_rows;   /* [nBlk] = dim(out)                                    */
   const int32_t *blk_cols;   /* [nBlk] = dim(in)                                     */
-  const int32_t *blk_ld;     /* [nBlk] >= cols                                       */
+  const int32_t *blk_ld;     /* [nBlk] >= cols, multiple of 8                        */
   const int64_t *blk_off;    /* [nBlk] element offset into the value array           */
   const int32_t *term_L;     /* [nTerms] left operator or -1                         */
   const int32_t *term_ma;    /* [nTerms] site-a monomial 0..15                       */
@@ -155,7 +157,9 @@ size_t tns_apply_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
 /* Convert FP64 operator values (device, n elements) into the operand format of
  * `prec`: TNS_F64 copies, TNS_F32 rounds to float (`out` = float[n]),
  * TNS_BF16X3 writes hi = bf16(x) then lo = bf16(x - hi) (round to nearest
- * even each), `out` = uint16[2n] (n hi values followed by n lo values). */
+ * even each), `out` = uint16[2 n8] with n8 = n rounded up to a multiple of 8:
+ * the n hi values at element 0 and the n lo values at element n8 (both halves
+ * start 16-byte aligned). */
 tns_status tns_prepare_operands(tns_prec prec, const double *vals64, int64_t n, void *out,
                                 hipStream_t stream);
 

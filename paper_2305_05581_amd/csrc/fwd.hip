@@ -1,0 +1,541 @@
+// sigma = H_eff psi (the sum of Eq. (2), level 3 of the hierarchy of
+// Section III.A.1) as two grouped GEMM phases on MFMA.
+//
+// Task k of output sector s' (input sector s, left block L_k, right block R_k,
+// alpha_k = coefficient x Jordan-Wigner sign) contributes
+//   class 0:   sigma_s'   += alpha_k (L_k A_s) R_k^T
+//   class 1:   sigma_s'^T += alpha_k (R_k A_s^T) L_k^T
+// (the cheaper association of the two, chosen when the task list is built).
+//
+// Phase A forms the intermediate of every task,
+//   T_k = alpha_k X_k M_k      (class 0: X = L, M = A;  class 1: X = R, M = A^T),
+// in 128 x 128 output tiles and stores it, row-major with leading dimension
+// ld8(K2), in the workspace.  Phase B forms, per chunk of the task list of an
+// output group,
+//   slot = sum_k T_k Y_k^T     (class 0: Y = R;  class 1: Y = L)
+// as one GEMM whose inner dimension runs through all tasks of the chunk, in
+// 128 x 128 tiles of the group's output.  The epilogue adds the slots of each
+// sector in a fixed order.  This is the batched-GEMM arrangement of Alg. 2
+// (intermediates in device memory, one batched product per stage) with the
+// summation over terms folded into the inner dimension of the second GEMM.
+//
+// Both phases run one kernel: C(i, j) = sum over segments of
+// sum_k A(i, k) B(j, k) with every operand k-contiguous (rows of L, R, T and
+// of the padded copies of A and A^T), staged global -> registers -> LDS with
+// 16-byte loads and a double-buffered LDS pipeline, one barrier per K step.
+#include <algorithm>
+
+#include "kern.hpp"
+#include "tns_internal.hpp"
+
+namespace tns {
+
+constexpr int GTH = 256;  // threads per workgroup: 4 waves in a 2 x 2 grid of 64 x 64 wave tiles
+
+// Operand: element (i, k) at p[i * ld + k] for i < rows, k < K of the
+// segment; identity (i == k) when `ident`.  BF16X3: p is the high half, the
+// low half lies `lo` elements further.
+struct Mat {
+  const void *p;
+  int64_t lo;
+  int32_t ld, rows, ident;
+};
+
+struct FwdArgs {
+  const tns_task *tasks;
+  int64_t ntasks;
+  const int32_t *psi_sec, *dimL, *dimR;
+  const int64_t *blk_off;
+  const int32_t *blk_ld;
+  const void *ops;  // F64 / F32 values, or BF16 hi[n] then lo at ld8-aligned offset
+  int64_t ops_lo;   // element offset of the low half (BF16X3)
+  const void *pp, *pt;  // padded psi (m x ld8(n)) and psi^T (n x ld8(m)) per sector
+  int64_t pp_lo, pt_lo;
+  const int64_t *pp_off, *pt_off;
+  void *T;  // intermediates
+  int64_t T_lo;
+  const int64_t *t_off;
+  // phase B schedule
+  const Item *items;
+  int64_t nitems;
+  const int32_t *idx, *grp_rows, *grp_cols;
+  const int64_t *slot_off, *qbase;
+  void *partial;
+  int32_t *queue;  // [0, 8): phase A queues, [8, 16): phase B queues
+  int32_t nq;
+  const void *zero;  // 64 zero bytes
+};
+
+// --- per-precision tile parameters ---------------------------------------------
+template <int P> struct FP;
+template <> struct FP<TNS_F64> {
+  typedef double Acc;
+  typedef double E;  // element in memory and LDS
+  typedef d2 V;      // 16-byte vector
+  typedef d4 A4;     // MFMA accumulator
+  static constexpr int BK = 16, VEC = 2, LDK = BK + 2;
+};
+template <> struct FP<TNS_F32> {
+  typedef float Acc;
+  typedef float E;
+  typedef f4 V;
+  typedef f4 A4;
+  static constexpr int BK = 32, VEC = 4, LDK = BK + 4;
+};
+template <> struct FP<TNS_BF16X3> {
+  typedef float Acc;
+  typedef uint16_t E;
+  typedef u16x8 V;
+  typedef f4 A4;
+  static constexpr int BK = 32, VEC = 8, LDK = BK + 8;
+};
+
+template <int P> struct __attribute__((aligned(16))) FwdSmem {
+  typedef typename FP<P>::E E;
+  static constexpr int NH = P == TNS_BF16X3 ? 2 : 1;  // halves per operand
+  E a[2][NH][GM * FP<P>::LDK];
+  E b[2][NH][GN * FP<P>::LDK];
+};
+
+// --- operand loads -------------------------------------------------------------
+// Thread t stages vectors (row t / NV + j * RP, k-vector t % NV) of a
+// 128 x BK tile, j < NL.
+template <int P> struct Stage {
+  static constexpr int NV = FP<P>::BK / FP<P>::VEC;
+  static constexpr int RP = GTH / NV;
+  static constexpr int NL = GM / RP;
+  static constexpr int NH = P == TNS_BF16X3 ? 2 : 1;
+  typename FP<P>::V r[NH][NL];
+};
+
+template <int P>
+__device__ inline void stage_load(Stage<P> &s, const Mat &m, int r0, int k0, int K, const void *zero) {
+  typedef typename FP<P>::E E;
+  typedef typename FP<P>::V V;
+  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, NL = Stage<P>::NL, VEC = FP<P>::VEC;
+  if (m.ident) return;
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  const int kk = k0 + (t % NV) * VEC;
+  const E *base = reinterpret_cast<const E *>(m.p);
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int row = r0 + t / NV + j * RP;
+    const bool in = row < m.rows && kk < K;
+    const E *ad = in ? base + (int64_t)row * m.ld + kk : reinterpret_cast<const E *>(zero);
+    s.r[0][j] = *reinterpret_cast<const V *>(ad);
+    if constexpr (P == TNS_BF16X3) {
+      const E *al = in ? base + m.lo + (int64_t)row * m.ld + kk : reinterpret_cast<const E *>(zero);
+      s.r[1][j] = *reinterpret_cast<const V *>(al);
+    }
+  }
+}
+
+template <int P>
+__device__ inline void stage_store(typename FP<P>::E (*lds)[GM * FP<P>::LDK], Stage<P> &s, const Mat &m, int r0,
+                                   int k0, int K) {
+  typedef typename FP<P>::E E;
+  typedef typename FP<P>::V V;
+  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, NL = Stage<P>::NL, VEC = FP<P>::VEC, LDK = FP<P>::LDK;
+  const int t = threadIdx.x;
+  const int kv = (t % NV) * VEC, kk = k0 + kv;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int lrow = t / NV + j * RP, row = r0 + lrow;
+    V h, l;
+    if (m.ident) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const bool one = row == kk + e && row < m.rows && kk + e < K;
+        if constexpr (P == TNS_BF16X3) {
+          h[e] = one ? (uint16_t)0x3f80 : (uint16_t)0;
+          l[e] = 0;
+        } else {
+          h[e] = one ? E(1) : E(0);
+        }
+      }
+    } else {
+      h = s.r[0][j];
+      if constexpr (P == TNS_BF16X3) l = s.r[1][j];
+      if (kk + VEC > K) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          if (kk + e >= K) {
+            h[e] = 0;
+            if constexpr (P == TNS_BF16X3) l[e] = 0;
+          }
+      }
+    }
+    *reinterpret_cast<V *>(&lds[0][lrow * LDK + kv]) = h;
+    if constexpr (P == TNS_BF16X3) *reinterpret_cast<V *>(&lds[1][lrow * LDK + kv]) = l;
+  }
+}
+
+// --- MFMA on one LDS stage ------------------------------------------------------
+// Wave tile 64 x 64 at (wm, wn); acc[ti][tj] is the 16 x 16 tile
+// (16 ti, 16 tj).  Lane group g = lane / 16 owns k in [g BK/4, (g+1) BK/4).
+template <int P>
+__device__ inline void stage_mma(const FwdSmem<P> &sm, int buf, typename FP<P>::A4 (&acc)[4][4]) {
+  constexpr int LDK = FP<P>::LDK, BK = FP<P>::BK;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
+  if constexpr (P == TNS_BF16X3) {
+    u16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ra = (wm * 64 + i * 16 + l16) * LDK + g * 8, rb = (wn * 64 + i * 16 + l16) * LDK + g * 8;
+      ah[i] = *reinterpret_cast<const u16x8 *>(&sm.a[buf][0][ra]);
+      al[i] = *reinterpret_cast<const u16x8 *>(&sm.a[buf][1][ra]);
+      bh[i] = *reinterpret_cast<const u16x8 *>(&sm.b[buf][0][rb]);
+      bl[i] = *reinterpret_cast<const u16x8 *>(&sm.b[buf][1][rb]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = mfma_bf(al[i], bh[j], acc[i][j]);
+        acc[i][j] = mfma_bf(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = mfma_bf(ah[i], bh[j], acc[i][j]);
+      }
+  } else {
+    typedef typename FP<P>::E E;
+    typedef typename FP<P>::V V;
+    constexpr int VEC = FP<P>::VEC, KG = BK / 4;  // k per lane group
+#pragma unroll
+    for (int h = 0; h < KG / VEC; ++h) {
+      V a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = *reinterpret_cast<const V *>(&sm.a[buf][0][(wm * 64 + i * 16 + l16) * LDK + g * KG + h * VEC]);
+        b[i] = *reinterpret_cast<const V *>(&sm.b[buf][0][(wn * 64 + i * 16 + l16) * LDK + g * KG + h * VEC]);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma((E)a[i][e], (E)b[j][e], acc[i][j]);
+    }
+  }
+}
+
+// --- segment operands -------------------------------------------------------------
+template <int P>
+__device__ inline Mat op_mat(const FwdArgs &g, int blk, int rows) {
+  typedef typename FP<P>::E E;
+  Mat m;
+  m.rows = rows;
+  m.lo = g.ops_lo;
+  if (blk < 0) {
+    m.p = g.zero; m.ld = 0; m.ident = 1;
+  } else {
+    m.p = reinterpret_cast<const E *>(g.ops) + g.blk_off[blk];
+    m.ld = g.blk_ld[blk];
+    m.ident = 0;
+  }
+  return m;
+}
+
+// Operands (A, B) and inner dimension K of task t in phase PH.
+template <int P, int PH>
+__device__ inline void seg_ops(const FwdArgs &g, int t, Mat &A, Mat &B, int &K, double *alpha) {
+  typedef typename FP<P>::E E;
+  const tns_task k = g.tasks[t];
+  const int *so = g.psi_sec + 4 * k.out, *si = g.psi_sec + 4 * k.in;
+  const int q = g.dimL[so[0]], r = g.dimR[so[3]], m = g.dimL[si[0]], n = g.dimR[si[3]];
+  if (alpha) *alpha = k.alpha;
+  if (PH == 0) {
+    if (k.order == 0) {  // T = L A: B(j, k) = A(k, j) = A^T(j, k)
+      K = m;
+      A = op_mat<P>(g, k.lblk, q);
+      B.p = reinterpret_cast<const E *>(g.pt) + g.pt_off[k.in];
+      B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n; B.ident = 0;
+    } else {             // T = R A^T: B(j, k) = A(j, k)
+      K = n;
+      A = op_mat<P>(g, k.rblk, r);
+      B.p = reinterpret_cast<const E *>(g.pp) + g.pp_off[k.in];
+      B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m; B.ident = 0;
+    }
+  } else {
+    const int k2 = k.order == 0 ? n : m;
+    K = k2;
+    A.p = reinterpret_cast<const E *>(g.T) + g.t_off[t];
+    A.lo = g.T_lo; A.ld = ld8(k2); A.rows = k.order == 0 ? q : r; A.ident = 0;
+    B = k.order == 0 ? op_mat<P>(g, k.rblk, r) : op_mat<P>(g, k.lblk, q);
+  }
+}
+
+// --- work queues --------------------------------------------------------------------
+// Phase A: tasks in blocks of 4 consecutive ones, block b on queue b mod nq.
+__device__ inline int64_t qa_count(int64_t ntasks, int nq, int q) {
+  const int64_t per = 4 * (int64_t)nq, full = ntasks / per;
+  const int64_t rest = ntasks - full * per - 4 * (int64_t)q;
+  return full * 4 + (rest < 0 ? 0 : (rest > 4 ? 4 : rest));
+}
+__device__ inline int64_t qa_task(int nq, int q, int64_t j) { return (j / 4) * 4 * nq + 4 * q + (j % 4); }
+
+template <int PH>
+__device__ inline int64_t pop_work(const FwdArgs &g) {
+  const int home = blockIdx.x % g.nq;
+  for (int k = 0; k < g.nq; ++k) {
+    const int q = home + k < g.nq ? home + k : home + k - g.nq;
+    if (PH == 0) {
+      const int64_t n = qa_count(g.ntasks, g.nq, q);
+      if (n <= 0) continue;
+      const int j = atomicAdd(g.queue + q, 1);
+      if (j < n) return qa_task(g.nq, q, j);
+    } else {
+      const int64_t b = g.qbase[q], n = g.qbase[q + 1] - b;
+      if (n <= 0) continue;
+      const int j = atomicAdd(g.queue + 8 + q, 1);
+      if (j < n) return b + j;
+    }
+  }
+  return -1;
+}
+
+// --- the kernel -----------------------------------------------------------------------
+// One output tile: acc = sum over segments [sb, se) of A_seg B_seg^T on rows
+// [r0, r0+128) of A and [c0, c0+128) of B.
+template <int P, int PH>
+__device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int se, int r0, int c0,
+                                 typename FP<P>::A4 (&acc)[4][4]) {
+  typedef typename FP<P>::A4 A4;
+  constexpr int BK = FP<P>::BK;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
+  auto seg_task = [&](int s) { return PH == 0 ? s : g.idx[s]; };
+  Mat A, B;
+  int K;
+  seg_ops<P, PH>(g, seg_task(sb), A, B, K, nullptr);
+  Stage<P> sa, sb_;
+  stage_load<P>(sa, A, r0, 0, K, g.zero);
+  stage_load<P>(sb_, B, c0, 0, K, g.zero);
+  stage_store<P>(sm.a[0], sa, A, r0, 0, K);
+  stage_store<P>(sm.b[0], sb_, B, c0, 0, K);
+  __syncthreads();
+  int s = sb, k0 = 0, cur = 0;
+  for (;;) {
+    int ns = s, nk = k0 + BK, nK = K;
+    Mat nA = A, nB = B;
+    if (nk >= K) {
+      ns = s + 1;
+      nk = 0;
+      if (ns < se) seg_ops<P, PH>(g, seg_task(ns), nA, nB, nK, nullptr);
+    }
+    const bool more = ns < se;
+    if (more) {
+      stage_load<P>(sa, nA, r0, nk, nK, g.zero);
+      stage_load<P>(sb_, nB, c0, nk, nK, g.zero);
+    }
+    stage_mma<P>(sm, cur, acc);
+    if (more) {
+      stage_store<P>(sm.a[cur ^ 1], sa, nA, r0, nk, nK);
+      stage_store<P>(sm.b[cur ^ 1], sb_, nB, c0, nk, nK);
+    }
+    __syncthreads();
+    if (!more) break;
+    cur ^= 1;
+    s = ns;
+    k0 = nk;
+    K = nK;
+    A = nA;
+    B = nB;
+  }
+}
+
+template <int P, int PH>
+__global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
+  typedef typename FP<P>::A4 A4;
+  __shared__ FwdSmem<P> sm;
+  __shared__ int64_t s_work;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  for (;;) {
+    if (threadIdx.x == 0) s_work = pop_work<PH>(g);
+    __syncthreads();
+    const int64_t wk = s_work;
+    __syncthreads();
+    if (wk < 0) break;
+    A4 acc[4][4];
+    if (PH == 0) {
+      // every tile of task wk, row strips in turn
+      const int t = (int)wk;
+      Mat A, B;
+      int K;
+      double alpha;
+      seg_ops<P, 0>(g, t, A, B, K, &alpha);
+      const int rows = A.rows, cols = B.rows, ld = ld8(cols);
+      for (int r0 = 0; r0 < rows; r0 += GM)
+        for (int c0 = 0; c0 < cols; c0 += GN) {
+          tile_gemm<P, 0>(g, sm, t, t + 1, r0, c0, acc);
+          const float alf = (float)alpha;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int col = c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+                if (row < rows && col < ld) {
+                  const int64_t o = g.t_off[t] + (int64_t)row * ld + col;
+                  if constexpr (P == TNS_BF16X3) {
+                    const float x = alf * acc[i][j][v];
+                    const uint16_t h = f32_to_bf16_rne(x);
+                    reinterpret_cast<uint16_t *>(g.T)[o] = h;
+                    reinterpret_cast<uint16_t *>(g.T)[g.T_lo + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
+                  } else if constexpr (P == TNS_F32) {
+                    reinterpret_cast<float *>(g.T)[o] = alf * acc[i][j][v];
+                  } else {
+                    reinterpret_cast<double *>(g.T)[o] = alpha * acc[i][j][v];
+                  }
+                }
+              }
+            }
+        }
+    } else {
+      const Item it = g.items[wk];
+      tile_gemm<P, 1>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
+      const int R = g.grp_rows[it.grp], C = g.grp_cols[it.grp];
+      typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + g.slot_off[it.slot];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = it.c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+            if (row < R && col < C) {
+              const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
+              slot[o] = acc[i][j][v];
+            }
+          }
+        }
+    }
+  }
+}
+
+// --- padded copies of psi ----------------------------------------------------------
+// Sector s (m x n) to pp (m x ld8(n)) and, transposed, to pt (n x ld8(m));
+// BF16X3 writes high halves and, `lo` elements further, low halves.
+template <class In, int P>
+__global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, const int32_t *psi_sec,
+                          const int32_t *dimL, const int32_t *dimR, const int64_t *pp_off, const int64_t *pt_off,
+                          void *pp, void *pt, int64_t pp_lo, int64_t pt_lo) {
+  typedef typename FP<P>::E E;
+  const int s = blockIdx.x;
+  const int m = dimL[psi_sec[4 * s]], n = dimR[psi_sec[4 * s + 3]];
+  const int lm = ld8(m), ln = ld8(n);
+  const int64_t n_el = (int64_t)m * n;
+  E *P0 = reinterpret_cast<E *>(pp) + pp_off[s], *P1 = reinterpret_cast<E *>(pt) + pt_off[s];
+  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n_el; e += (int64_t)gridDim.y * blockDim.x) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    const In x = psi[psi_off[s] + e];
+    const int64_t a = (int64_t)i * ln + j, b = (int64_t)j * lm + i;
+    if constexpr (P == TNS_BF16X3) {
+      const float v = (float)x;
+      const uint16_t h = f32_to_bf16_rne(v), l = f32_to_bf16_rne(v - bf16_to_f32(h));
+      P0[a] = h; P0[pp_lo + a] = l;
+      P1[b] = h; P1[pt_lo + b] = l;
+    } else {
+      P0[a] = (E)x;
+      P1[b] = (E)x;
+    }
+  }
+}
+
+// --- host side --------------------------------------------------------------------------
+// BF16X3 halves: the low half of an array of n elements starts at ld8(n).
+static inline int64_t lo_of(int64_t n) { return (n + 7) & ~int64_t(7); }
+
+// Bytes of an operand array of n elements in a precision (BF16X3: both halves).
+static size_t region(int64_t n, tns_prec p) {
+  n = std::max<int64_t>(n, 1);
+  const size_t b = p == TNS_F64 ? (size_t)n * 8 : p == TNS_F32 ? (size_t)n * 4 : (size_t)lo_of(n) * 4;
+  return align_up(b + 64, 256);
+}
+
+// Workspace of the forward product:
+// [queue counters, zero bytes | partial slots | T | padded psi | padded psi^T].
+size_t fwd_workspace(const Plan &p, tns_prec prec) {
+  return 256 + align_up((size_t)std::max<int64_t>(p.fwd.partial_elems, 1) * (prec == TNS_F64 ? 8 : 4), 256) +
+         region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec);
+}
+
+// queue counters (bytes 0..63) and the 64-byte zero region that out-of-range
+// loads read (bytes 64..127)
+__global__ void k_reset_queues(int32_t *p) {
+  if (threadIdx.x < 32) p[threadIdx.x] = 0;
+}
+
+template <class K>
+static int grid_of(K kern, int n_cu) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, GTH, 0) != hipSuccess || per <= 0) per = 1;
+  return per * n_cu;
+}
+
+template <int P, class In>
+static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void *sigma, int beta, char *w,
+                             hipStream_t st, hipEvent_t evb, hipEvent_t eva) {
+  typedef typename FP<P>::Acc Acc;
+  const Sched &S = p.fwd;
+  const tns_prec prec = (tns_prec)P;
+  int32_t *queue = reinterpret_cast<int32_t *>(w);
+  char *c = w + 256;
+  void *part = c;
+  c += align_up((size_t)std::max<int64_t>(S.partial_elems, 1) * sizeof(Acc), 256);
+  void *T = c;
+  c += region(p.t_elems, prec);
+  void *pp = c;
+  c += region(p.pp_elems, prec);
+  void *pt = c;
+
+  FwdArgs g;
+  memset(&g, 0, sizeof(g));
+  g.tasks = p.tasks; g.ntasks = p.ntasks;
+  g.psi_sec = p.psi_sec; g.dimL = p.dimL; g.dimR = p.dimR;
+  g.blk_off = p.blk_off; g.blk_ld = p.blk_ld;
+  g.ops = ops; g.ops_lo = lo_of(p.n_vals);
+  g.pp = pp; g.pt = pt; g.pp_lo = lo_of(p.pp_elems); g.pt_lo = lo_of(p.pt_elems);
+  g.pp_off = p.pp_off; g.pt_off = p.pt_off;
+  g.T = T; g.T_lo = lo_of(p.t_elems); g.t_off = p.t_off;
+  g.items = S.items; g.nitems = S.nitems; g.idx = S.idx; g.grp_rows = S.grp_rows; g.grp_cols = S.grp_cols;
+  g.slot_off = S.slot_off; g.qbase = S.qbase; g.partial = part;
+  g.queue = queue; g.nq = S.nq;
+  g.zero = w + 64;
+
+  hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, queue);
+  if (p.nS > 0)
+    hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
+                       p.dimR, p.pp_off, p.pt_off, pp, pt, g.pp_lo, g.pt_lo);
+  if (evb && eva) TNS_HIP(hipEventRecord(evb, st));
+  if (p.ntasks > 0) {
+    hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
+    if (S.nitems > 0) hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
+  }
+  if (evb && eva) TNS_HIP(hipEventRecord(eva, st));
+  return launch_epilogue_psi(p, prec == TNS_F64, part, sigma, beta, st);
+}
+
+tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
+                     void *ws, size_t ws_bytes, hipStream_t st, hipEvent_t evb, hipEvent_t eva) {
+  if (ws_bytes < fwd_workspace(p, prec)) return TNS_ERR_WORKSPACE;
+  char *w = reinterpret_cast<char *>(ws);
+  const int ib = beta != 0.0;
+  tns_status s;
+  if (prec == TNS_F64)
+    s = fwd_launch<TNS_F64>(p, ops, (const double *)psi, sigma, ib, w, st, evb, eva);
+  else if (prec == TNS_F32)
+    s = fwd_launch<TNS_F32>(p, ops, (const float *)psi, sigma, ib, w, st, evb, eva);
+  else
+    s = fwd_launch<TNS_BF16X3>(p, ops, (const float *)psi, sigma, ib, w, st, evb, eva);
+  if (s != TNS_OK) return s;
+  return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
+}
+
+}  // namespace tns

@@ -221,9 +221,16 @@ __global__ __launch_bounds__(256) void k_group_cost(Plan p, Sched S) {
   }
 }
 
+// Tiles (work items) of one chunk of a group with a rows x cols output.
+__device__ inline int n_tiles(const Sched &S, int rows, int cols) {
+  const int nr = (rows + S.tile_r - 1) / S.tile_r;
+  const int nc = S.tile_c > 0 ? (cols + S.tile_c - 1) / S.tile_c : 1;
+  return nr * nc;
+}
+
 // Greedy task chunks per group: a chunk closes before the task that would
-// push it over cap = target_item_cost * panels (each chunk is then cut into
-// row panels of TQ rows, so items cost about target_item_cost each).
+// push it over cap = target_item_cost * tiles (each chunk is then cut into
+// output tiles, so items cost about target_item_cost each).
 template <bool FILL>
 __global__ void k_chunks(Plan p, Sched S) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -233,8 +240,7 @@ __global__ void k_chunks(Plan p, Sched S) {
   if (n > 0) {
     const int64_t total = S.scalars[0];
     const int64_t target = total / ((int64_t)ITEMS_PER_CU * p.n_cu) + 1;
-    const int npan = (S.grp_rows[g] + TQ - 1) / TQ;
-    const int64_t cap = target * npan;
+    const int64_t cap = target * n_tiles(S, S.grp_rows[g], S.grp_cols[g]);
     const int b = S.grp_begin[g], mode = S.grp_mode[g];
     int64_t cur = 0;
     int start = b;
@@ -263,7 +269,7 @@ __global__ void k_chunk_sizes(Sched S, int64_t *slot_sz, int64_t *item_n) {
   if (c >= nch) { slot_sz[c] = 0; item_n[c] = 0; return; }
   const int g = S.chunks[c].grp;
   slot_sz[c] = (int64_t)S.grp_rows[g] * S.grp_cols[g];
-  item_n[c] = (S.grp_rows[g] + TQ - 1) / TQ;
+  item_n[c] = n_tiles(S, S.grp_rows[g], S.grp_cols[g]);
 }
 
 __global__ void k_items(Sched S) {
@@ -271,31 +277,72 @@ __global__ void k_items(Sched S) {
   const int64_t nch = S.grp_chunk_base[S.ngroups];
   if (c >= nch) return;
   const Chunk ch = S.chunks[c];
-  const int rows = S.grp_rows[ch.grp];
-  const int npan = (rows + TQ - 1) / TQ;
+  const int rows = S.grp_rows[ch.grp], cols = S.grp_cols[ch.grp];
+  const int tc = S.tile_c > 0 ? S.tile_c : cols;
+  const int ncol = (cols + tc - 1) / tc;
+  const int nt = n_tiles(S, rows, cols);
   const int64_t ib = S.chunk_item_base[c];
-  for (int k = 0; k < npan; ++k) {
+  for (int k = 0; k < nt; ++k) {
     Item it;
     it.grp = ch.grp;
     it.mode = S.grp_mode[ch.grp];
-    it.p0 = k * TQ;
-    it.np = min(TQ, rows - k * TQ);
+    it.p0 = (k / ncol) * S.tile_r;
+    it.np = min(S.tile_r, rows - it.p0);
+    it.c0 = (k % ncol) * tc;
+    it.nc = min(tc, cols - it.c0);
     it.tb = ch.tb;
     it.te = ch.te;
     it.slot = (int32_t)c;
     it.out = S.grp_out[ch.grp];
-    it.cost = ch.cost * it.np / rows;
+    it.cost = ch.cost * ((int64_t)it.np * it.nc) / ((int64_t)rows * cols);
     S.items_unsorted[ib + k] = it;
   }
 }
 
+// Chunks by descending cost (ascending key; padding last).
+__global__ void k_chunk_keys(Sched S) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= S.chunks_cap) return;
+  const int64_t nch = S.grp_chunk_base[S.ngroups];
+  S.keys_in[c] = (c < nch) ? (~(uint64_t)S.chunks[c].cost - 1ull) : ~0ull;
+  S.vals_in[c] = (int32_t)c;
+}
+
+// XCD of each chunk: boustrophedon over the cost-sorted chunks (ranks 0..nq-1
+// to queues 0..nq-1, the next nq ranks back from nq-1, ...), which keeps the
+// queue totals close while all row panels of a chunk share one L2.
+__global__ void k_chunk_xcd(Sched S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nch = S.grp_chunk_base[S.ngroups];
+  if (i >= nch) return;
+  const int64_t round = i / S.nq, pos = i % S.nq;
+  S.chunks[S.vals_out[i]].xcd = (int32_t)((round & 1) ? S.nq - 1 - pos : pos);
+}
+
+// Item order: by queue, then longest first; padding entries sort last.
 __global__ void k_sort_keys(Sched S) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.items_cap) return;
   const int64_t nit = S.chunk_item_base[S.grp_chunk_base[S.ngroups]];
-  // ascending key = descending cost; padding entries sort last
-  S.keys_in[i] = (i < nit) ? (~(uint64_t)S.items_unsorted[i].cost - 1ull) : ~0ull;
+  constexpr uint64_t CM = (1ull << 56) - 1;
+  uint64_t key = ~0ull;
+  if (i < nit) {
+    const Item it = S.items_unsorted[i];
+    const uint64_t c = (uint64_t)it.cost < CM ? (uint64_t)it.cost : CM;
+    key = ((uint64_t)S.chunks[it.slot].xcd << 56) | (CM - c);
+  }
+  S.keys_in[i] = key;
   S.vals_in[i] = (int32_t)i;
+}
+
+// Queue bounds from the sorted keys: qbase[q] = first item of queue q.
+__global__ void k_queue_bounds(Sched S) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nit = S.chunk_item_base[S.grp_chunk_base[S.ngroups]];
+  if (i > nit) return;
+  const int prev = i == 0 ? -1 : (int)(S.keys_out[i - 1] >> 56);
+  const int cur = i == nit ? S.nq : (int)(S.keys_out[i] >> 56);
+  for (int q = prev + 1; q <= cur; ++q) S.qbase[q] = i;
 }
 
 __global__ void k_gather_items(Sched S) {
@@ -311,6 +358,28 @@ __global__ void k_sched_totals(Sched S) {
   S.scalars[1] = nch;
   S.scalars[2] = S.chunk_item_base[nch];
   S.scalars[3] = S.slot_off[nch];
+}
+
+// Sizes of the forward intermediates T_k (output rows x ld8(K2), K2 = n for
+// class 0 and m for class 1), scanned in place into offsets afterwards.
+__global__ void k_t_sizes(Plan p, int64_t ntasks) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  const tns_task k = p.tasks[t];
+  const int *so = p.psi_sec + 4 * k.out, *si = p.psi_sec + 4 * k.in;
+  const int64_t rows = k.order == 0 ? p.dimL[so[0]] : p.dimR[so[3]];
+  const int k2 = k.order == 0 ? p.dimR[si[3]] : p.dimL[si[0]];
+  p.t_off[t] = rows * ld8(k2);
+}
+
+// Sizes of the padded copies of psi: sector s as m x ld8(n) and as its
+// transpose n x ld8(m).
+__global__ void k_pad_sizes(Plan p) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.nS) return;
+  const int64_t m = p.dimL[p.psi_sec[4 * s]], n = p.dimR[p.psi_sec[4 * s + 3]];
+  p.pp_off[s] = m * ld8((int)n);
+  p.pt_off[s] = n * ld8((int)m);
 }
 
 // Backward grouping: three (key, task) entries per task -- input sector,
@@ -425,7 +494,8 @@ static tns_status validate(const tns_problem *P, int32_t *nmax_out, int32_t *max
     if (i < 0 || i >= ns || j < 0 || j >= ns) return TNS_ERR_SHAPE;
     if (q[2 * j] != q[2 * i] + P->op_dN[o] || q[2 * j + 1] != q[2 * i + 1] + P->op_d2Sz[o]) return TNS_ERR_QN;
     if (P->blk_rows[b] != dim[j] || P->blk_cols[b] != dim[i] || P->blk_ld[b] < P->blk_cols[b]) return TNS_ERR_SHAPE;
-    if (P->blk_off[b] < 0 || P->blk_off[b] + (int64_t)(P->blk_rows[b] - 1) * P->blk_ld[b] + P->blk_cols[b] > P->n_vals)
+    if (P->blk_off[b] < 0 || P->blk_off[b] % 8 != 0 || P->blk_ld[b] % 8 != 0 ||
+        P->blk_off[b] + (int64_t)P->blk_rows[b] * P->blk_ld[b] > P->n_vals)
       return TNS_ERR_SHAPE;
     if (seen[(size_t)o * nmax + i]++) return TNS_ERR_SHAPE;
   }
@@ -454,6 +524,13 @@ static int device_cu_count() {
   return n;
 }
 
+static int device_xcd_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || n <= 0) return 1;
+  return std::min(n, NQ_MAX);
+}
+
 static size_t radix_tmp_u64(int64_t n) {
   size_t tmp = 0;
   (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
@@ -468,12 +545,16 @@ static size_t radix_tmp_i32(int64_t n) {
 }
 
 // Carves one schedule's arrays; `idx` may be supplied by the caller.
-static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, int64_t chunks_cap, int npmax,
-                         bool own_idx) {
+static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, int64_t chunks_cap, int maxdim,
+                         int tile_r, int tile_c, int nq, bool own_idx) {
   S.ngroups = ngroups;
   S.ntcap = ntcap;
   S.chunks_cap = chunks_cap;
-  S.items_cap = chunks_cap * npmax;
+  S.tile_r = tile_r;
+  S.tile_c = tile_c;
+  const int64_t tmax = (int64_t)((maxdim + tile_r - 1) / tile_r) * (tile_c > 0 ? (maxdim + tile_c - 1) / tile_c : 1);
+  S.items_cap = chunks_cap * tmax;
+  S.nq = nq;
   if (own_idx) S.idx = cv.take<int32_t>(ntcap);
   const size_t ng = std::max(1, ngroups);
   S.grp_begin = cv.take<int32_t>(ng); S.grp_n = cv.take<int32_t>(ng);
@@ -489,12 +570,14 @@ static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, in
   S.vals_in = cv.take<int32_t>(S.items_cap); S.vals_out = cv.take<int32_t>(S.items_cap);
   S.sort_tmp_bytes = radix_tmp_u64(S.items_cap);
   S.sort_tmp = cv.take<char>(S.sort_tmp_bytes + 256);
+  S.qbase = cv.take<int64_t>(NQ_MAX + 1);
   S.scratch = cv.take<int64_t>(std::max<int64_t>(ng, chunks_cap) + 1);
   S.scalars = cv.take<int64_t>(8);
 }
 
 // Lays out (or, with base == nullptr, sizes) the build workspace.
-static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_cu, char *base, Plan *pl) {
+static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_cu, int n_xcd, char *base,
+                     Plan *pl) {
   Carve cv{base, 0, 0};
   Plan p;
   memset(&p, 0, sizeof(p));
@@ -502,7 +585,6 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals;
   p.psi_dim = P->psi_off[P->nS];
   const int64_t ntcap = std::max<int64_t>(1, (int64_t)P->nTerms * P->nS);
-  const int npmax = (maxdim + TQ - 1) / TQ;
   p.qL = cv.take<int32_t>(2 * P->nL); p.dimL = cv.take<int32_t>(P->nL);
   p.qR = cv.take<int32_t>(2 * P->nR); p.dimR = cv.take<int32_t>(P->nR);
   p.psi_sec = cv.take<int32_t>(4 * (size_t)std::max(1, P->nS)); p.psi_off = cv.take<int64_t>(P->nS + 1);
@@ -519,9 +601,12 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.out_ptr = cv.take<int32_t>(P->nS + 1);
   p.scan_tmp = cv.take<int64_t>(P->nS + 1);
   p.scalars = cv.take<int64_t>(8);
-  // forward schedule: 2 groups per sector
+  p.t_off = cv.take<int64_t>(ntcap + 1);
+  p.pp_off = cv.take<int64_t>(P->nS + 1);
+  p.pt_off = cv.take<int64_t>(P->nS + 1);
+  // forward schedule: 2 groups per sector, output tiles GM x GN
   const int64_t fchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 4 * (int64_t)P->nS + 16;
-  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, npmax, true);
+  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, maxdim, GM, GN, n_xcd, true);
   // backward schedule: one group per sector (d psi) and one per block (d L / d R)
   const int64_t bent = 3 * ntcap;
   p.bkeys_in = cv.take<int32_t>(bent); p.bkeys_out = cv.take<int32_t>(bent); p.bvals_in = cv.take<int32_t>(bent);
@@ -530,7 +615,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.bsort_tmp = cv.take<char>(p.bsort_tmp_bytes + 256);
   const int32_t bgroups = P->nS + P->nBlk;
   const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
-  layout_sched(cv, p.bwd, bgroups, bent, bchunks, npmax, false);
+  layout_sched(cv, p.bwd, bgroups, bent, bchunks, maxdim, TQ, 0, n_xcd, false);
   if (pl) *pl = p;
   return cv.off + 256;
 }
@@ -561,12 +646,19 @@ static tns_status finish_sched(const Plan &p, Sched &S, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, slot_sz, S.slot_off, S.chunks_cap);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, item_n, S.chunk_item_base, S.chunks_cap);
   hipLaunchKernelGGL(k_items, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S);
+  hipLaunchKernelGGL(k_chunk_keys, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S);
+  TNS_HIP(hipGetLastError());
+  size_t tmp = S.sort_tmp_bytes;  // sized for items_cap >= chunks_cap entries
+  TNS_HIP(hipcub::DeviceRadixSort::SortPairs(S.sort_tmp, tmp, S.keys_in, S.keys_out, S.vals_in, S.vals_out,
+                                             (int)S.chunks_cap, 0, 64, st));
+  hipLaunchKernelGGL(k_chunk_xcd, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S);
   hipLaunchKernelGGL(k_sort_keys, dim3(nblk(S.items_cap, B)), dim3(B), 0, st, S);
   TNS_HIP(hipGetLastError());
-  size_t tmp = S.sort_tmp_bytes;
+  tmp = S.sort_tmp_bytes;
   TNS_HIP(hipcub::DeviceRadixSort::SortPairs(S.sort_tmp, tmp, S.keys_in, S.keys_out, S.vals_in, S.vals_out,
                                              (int)S.items_cap, 0, 64, st));
   hipLaunchKernelGGL(k_gather_items, dim3(nblk(S.items_cap, B)), dim3(B), 0, st, S);
+  hipLaunchKernelGGL(k_queue_bounds, dim3(nblk(S.items_cap + 1, B)), dim3(B), 0, st, S);
   hipLaunchKernelGGL(k_sched_totals, dim3(1), dim3(1), 0, st, S);
   TNS_HIP(hipGetLastError());
   return TNS_OK;
@@ -586,7 +678,7 @@ using namespace tns;
 extern "C" size_t tns_tasklist_workspace_bytes(const tns_problem *prob) {
   int32_t nmax = 0, maxdim = 0;
   if (validate(prob, &nmax, &maxdim) != TNS_OK) return 0;
-  return layout(prob, nmax, maxdim, device_cu_count(), nullptr, nullptr);
+  return layout(prob, nmax, maxdim, device_cu_count(), device_xcd_count(), nullptr, nullptr);
 }
 
 extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t ws_bytes, tns_tasklist *out,
@@ -595,11 +687,11 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   int32_t nmax = 0, maxdim = 0;
   tns_status s = validate(P, &nmax, &maxdim);
   if (s != TNS_OK) return s;
-  const int n_cu = device_cu_count();
-  const size_t need = layout(P, nmax, maxdim, n_cu, nullptr, nullptr);
+  const int n_cu = device_cu_count(), n_xcd = device_xcd_count();
+  const size_t need = layout(P, nmax, maxdim, n_cu, n_xcd, nullptr, nullptr);
   if (ws_bytes < need) return TNS_ERR_WORKSPACE;
   Plan p;
-  layout(P, nmax, maxdim, n_cu, (char *)ws, &p);
+  layout(P, nmax, maxdim, n_cu, n_xcd, (char *)ws, &p);
   TNS_HIP(up(p.qL, P->qL, 2 * (size_t)P->nL, st));
   TNS_HIP(up(p.dimL, P->dimL, P->nL, st));
   TNS_HIP(up(p.qR, P->qR, 2 * (size_t)P->nR, st));
@@ -627,7 +719,12 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
                      (int64_t)P->nL * 16, -1);
   hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)std::max(1, P->nOps) * nmax, B)), dim3(B), 0, st,
                      p.blk_of_out, (int64_t)std::max(1, P->nOps) * nmax, -1);
-  if (P->nS > 0) hipLaunchKernelGGL(k_psi_index, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
+  if (P->nS > 0) {
+    hipLaunchKernelGGL(k_psi_index, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
+    hipLaunchKernelGGL(k_pad_sizes, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
+  }
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.pp_off, p.pp_off, (int64_t)P->nS);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.pt_off, p.pt_off, (int64_t)P->nS);
   if (P->nBlk > 0) hipLaunchKernelGGL(k_blk_of_out, dim3(nblk(P->nBlk, B)), dim3(B), 0, st, p);
   TNS_HIP(hipGetLastError());
   const unsigned wblk = nblk(std::max(1, P->nS), 4);
@@ -656,6 +753,10 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   read_sched(p.fwd, h);
   if (p.fwd.nchunks > p.fwd.chunks_cap || p.fwd.nitems > p.fwd.items_cap) return TNS_ERR_WORKSPACE;
 
+  // forward intermediates
+  if (p.ntasks > 0) hipLaunchKernelGGL(k_t_sizes, dim3(nblk(p.ntasks, B)), dim3(B), 0, st, p, p.ntasks);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.t_off, p.t_off, p.ntasks);
+
   // backward grouping: stable sort of (key, task) entries by key
   const int64_t nent = 3 * p.ntasks;
   if (nent > 0) {
@@ -673,8 +774,15 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   s = finish_sched(p, p.bwd, st);
   if (s != TNS_OK) return s;
   TNS_HIP(hipMemcpyAsync(h, p.bwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+  int64_t ext[3];
+  TNS_HIP(hipMemcpyAsync(ext, p.t_off + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 1, p.pp_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 2, p.pt_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   read_sched(p.bwd, h);
+  p.t_elems = ext[0];
+  p.pp_elems = ext[1];
+  p.pt_elems = ext[2];
   if (p.bwd.nchunks > p.bwd.chunks_cap || p.bwd.nitems > p.bwd.items_cap) return TNS_ERR_WORKSPACE;
 
   memset(out, 0, sizeof(*out));

@@ -14,6 +14,10 @@ constexpr int TQ = 32;
 // Work items per compute unit the schedule aims at (load balance of the
 // longest-first queue).
 constexpr int ITEMS_PER_CU = 8;
+// Most work queues of a schedule: one per XCD (accelerator complex die, each
+// with its own L2).  Workgroup b of a launch runs on XCD b mod n_xcd, since
+// workgroups are dispatched to the dies round-robin.
+constexpr int NQ_MAX = 8;
 
 // Evaluation modes of the fused chained product
 //   out(i, j) += alpha * sum_c (sum_k X(i, k) M(k, c)) Y(j, c)
@@ -26,24 +30,29 @@ constexpr int ITEMS_PER_CU = 8;
 //   4  d R = G^T L A    X = G^T, M = L,   Y = A^T    out = (r x n)
 enum Mode { M_FWD0 = 0, M_FWD1 = 1, M_DPSI = 2, M_DL = 3, M_DR = 4 };
 
-// One work item of the persistent kernel: rows [p0, p0+np) of the output
-// matrix of group `grp`, entries idx[tb..te) of that group's task list,
-// result into partial slot `slot` (one slot per chunk of a group).
+// One work item of a persistent kernel: the tile rows [p0, p0+np) x columns
+// [c0, c0+nc) of the output matrix of group `grp`, entries idx[tb..te) of
+// that group's task list, result into partial slot `slot` (one slot per
+// chunk of a group).
 struct Item {
-  int32_t grp, mode, p0, np, tb, te, slot, out;
+  int32_t grp, mode, p0, np, tb, te, slot, out, c0, nc;
   int64_t cost;
 };
-static_assert(sizeof(Item) == 40, "Item layout");
+static_assert(sizeof(Item) == 48, "Item layout");
+
+// Output tile of the forward grouped GEMMs (both phases).
+constexpr int GM = 128, GN = 128;
 
 struct Chunk {
-  int32_t grp, tb, te, pad;
+  int32_t grp, tb, te, xcd;  // xcd: queue the chunk's row panels go to
   int64_t cost;
 };
 
 // A schedule: groups of tasks that share one output matrix, cut into chunks
 // (partial slots) and row panels (work items), longest item first.
 struct Sched {
-  int32_t ngroups, pad_;
+  int32_t ngroups, nq;  // nq: work queues (XCDs)
+  int32_t tile_r, tile_c;  // item tile; tile_c == 0: all columns
   int64_t ntcap;        // capacity of idx
   int64_t chunks_cap, items_cap;
   int64_t nchunks, nitems, partial_elems, total_cost;
@@ -57,6 +66,7 @@ struct Sched {
   int32_t *vals_in, *vals_out;
   void *sort_tmp;
   size_t sort_tmp_bytes;
+  int64_t *qbase;       // [NQ_MAX + 1]: queue q = items[qbase[q], qbase[q+1])
   int64_t *scratch;     // [max(ngroups, chunks_cap) + 1]
   int64_t *scalars;     // [8]
 };
@@ -83,6 +93,12 @@ struct Plan {
   int32_t *out_ptr;      // [nS+1]
   int64_t *scan_tmp;     // [nS+1]
   int64_t *scalars;      // [8]
+  // forward intermediates T_k = alpha X_k M_k (one per task, row-major,
+  // leading dimension K2 rounded up to 8) and the padded copies of psi
+  int64_t *t_off;        // [ntcap + 1] element offset of T_k
+  int64_t t_elems;
+  int64_t *pp_off, *pt_off;  // [nS + 1] sector offsets: m x ld8(n) and n x ld8(m)
+  int64_t pp_elems, pt_elems;
   // backward grouping keys: 3 entries per task
   int32_t *bkeys_in, *bkeys_out, *bvals_in;
   void *bsort_tmp;
@@ -101,6 +117,9 @@ inline const Plan &plan_of(const tns_tasklist *t) { return *reinterpret_cast<con
   } while (0)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+// Leading dimension of the library's own row-major buffers: 8 elements keep
+// every row 16-byte aligned for all element types.
+__host__ __device__ inline int ld8(int x) { return (x + 7) & ~7; }
 
 // Bump allocator over a caller workspace.
 struct Carve {
@@ -153,7 +172,12 @@ __host__ __device__ inline void mono_shift(int m, int *dN, int *d2Sz) {
   *d2Sz = du - dd;
 }
 
-// Launch helpers implemented in tasklist.hip / apply.hip
+// Launch helpers implemented in tasklist.hip / apply.hip / fwd.hip
 tns_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
+// sigma (+)= sum of the forward partial slots of every sector (beta 0 or 1)
+tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *sigma, int beta, hipStream_t st);
+size_t fwd_workspace(const Plan &p, tns_prec prec);
+tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
+                     void *ws, size_t ws_bytes, hipStream_t st, hipEvent_t evb, hipEvent_t eva);
 
 }  // namespace tns

@@ -180,7 +180,7 @@ class HeffProblem:
             if p == F32:
                 out = torch.empty(n, dtype=torch.float32, device=self.device)
             else:
-                out = torch.empty(2 * n, dtype=torch.int16, device=self.device)
+                out = torch.empty(2 * ((n + 7) // 8 * 8), dtype=torch.int16, device=self.device)
             _check(library().tns_prepare_operands(p, _ptr(self.vals64), n, _ptr(out), _stream()),
                    "tns_prepare_operands")
             self._ops[p] = out
