@@ -28,7 +28,109 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0}  # TFLOP/s per algorithmic flop
-KERNEL = {"f64": "k_apply<0>", "f32": "k_apply<1>", "bf16x3": "k_apply_bf16x3"}
+PREC_ID = {"f64": 0, "f32": 1, "bf16x3": 2}
+# the two MFMA kernels of a product: phase A (T_k = alpha X_k M_k), phase B (sum_k T_k Y_k^T)
+KERNEL = {p: ("k_fwd<%d, 0>" % i, "k_fwd<%d, 1>" % i) for p, i in PREC_ID.items()}
+KERNEL_SOURCES = ["paper_2305_05581_amd/csrc/fwd.hip", "paper_2305_05581_amd/csrc/kern.hpp",
+                  "paper_2305_05581_amd/csrc/tns_internal.hpp"]
+TRAFFIC_FILE = os.path.join("profiles", "traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config, prec):
+    """HBM bytes per phase-A launch from the committed counter runs, if they
+    were taken on the current kernel sources (else None)."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = rec.get("entries", {}).get("%s/%s" % (config, prec))
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    per = {}
+    for x in rows:
+        k = (int(x["Dispatch_Id"]), x["Kernel_Name"])
+        per[k] = per.get(k, 0.0) + float(x["Counter_Value"])
+    return per
+
+
+def ingest_counters(args):
+    """Per-launch HBM bytes of each phase-A kernel in two counter runs of
+    `bench.py --only P --calib-bytes N`: FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch) scaled by what the same counter reads for the element-wise
+    calibration kernel that reads and writes N bytes."""
+    if args.calib_bytes <= 0:
+        sys.exit("--ingest-counters needs --calib-bytes (the size used in the counter runs)")
+    fetch, write = _counter_rows(args.ingest_counters[0]), _counter_rows(args.ingest_counters[1])
+    cal = [(v, k) for k, v in fetch.items() if "elementwise" in k[1]]
+    if not cal:
+        sys.exit("no calibration kernel in the FETCH_SIZE run")
+    fv, ck = max(cal)
+    f_fetch = args.calib_bytes / (fv * 1024.0)
+    f_write = args.calib_bytes / (write[ck] * 1024.0)
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        rec = {"entries": {}}
+    rec["note"] = ("HBM bytes per launch of the phase-A kernel: FETCH_SIZE x f_fetch + WRITE_SIZE x f_write, "
+                   "f = calibration bytes / counter reading of a plain element-wise kernel of known size")
+    for prec, (ka, _) in KERNEL.items():
+        name = ka.replace("k_fwd", "tns::k_fwd")
+        fk = [v for k, v in fetch.items() if name in k[1]]
+        wk = [v for k, v in write.items() if name in k[1]]
+        if not fk or not wk:
+            continue
+        fb = float(np.mean(fk)) * 1024 * f_fetch
+        wb = float(np.mean(wk)) * 1024 * f_write
+        rec["entries"]["%s/%s" % (args.config, prec)] = {
+            "kernel": ka, "source_hash": kernel_source_hash(), "bytes_per_launch": round(fb + wb),
+            "fetch_bytes": round(fb), "write_bytes": round(wb), "dispatches": len(fk),
+            "f_fetch": round(f_fetch, 4), "f_write": round(f_write, 4)}
+        log("%s %s: fetch %.1f GB, write %.1f GB per launch (f_fetch %.3f, f_write %.3f)"
+            % (prec, ka, fb / 1e9, wb / 1e9, f_fetch, f_write))
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+
+
+def phase_flops(P, tasks):
+    """Algorithmic flops of the two phases: phase A 2 R K1 K2 per task with a
+    non-identity X, phase B 2 R K2 C per task with a non-identity Y."""
+    out, inn = tasks["out"], tasks["in"]
+    q = P.dimL[P.psi_sec[out, 0]].astype(np.int64)
+    r = P.dimR[P.psi_sec[out, 3]].astype(np.int64)
+    m = P.dimL[P.psi_sec[inn, 0]].astype(np.int64)
+    n = P.dimR[P.psi_sec[inn, 3]].astype(np.int64)
+    o1 = tasks["order"] == 1
+    R = np.where(o1, r, q)
+    C = np.where(o1, q, r)
+    K1 = np.where(o1, n, m)
+    K2 = np.where(o1, m, n)
+    idX = np.where(o1, tasks["rblk"] < 0, tasks["lblk"] < 0)
+    idY = np.where(o1, tasks["lblk"] < 0, tasks["rblk"] < 0)
+    fa = int(np.sum(np.where(idX, 0, 2 * R * K1 * K2)))
+    fb = int(np.sum(np.where(idY, 0, 2 * R * K2 * C)))
+    return fa, fb
 CONFIGS = {
     "d4096": dict(L=54, N=54, twoSz=0, D=4096, mean=64, dmax=512, K=3000, seed=3, gapped=True),
     "d1024": dict(L=30, N=30, twoSz=0, D=1024, mean=32, dmax=256, K=900, seed=2, gapped=False),
@@ -52,9 +154,15 @@ def main():
     ap.add_argument("--dav-iter", type=int, default=120, help="cap on Davidson products per solve")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes first (counter calibration under a profiler)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="write the phase-A HBM traffic of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; "
+                         "with --calib-bytes) into " + TRAFFIC_FILE + " and exit")
     ap.add_argument("--only", default=None, choices=["bf16x3", "f32", "f64"],
                     help="time only this precision (profiling runs)")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU's share only: this build runs on a single GPU "
               "(no collectives or sharding); run with --gpus 1", file=sys.stderr)
@@ -101,6 +209,11 @@ def main():
         log("calibration copy: %d bytes" % (src.numel() * 4))
         del src, dst
 
+    tasks_dev, ptr = H.tasks()
+    flops_a, flops_b = phase_flops(P, tasks_dev)
+    log("phase A %.3f TFLOP, phase B %.3f TFLOP (sum %.3f)" % (flops_a / 1e12, flops_b / 1e12,
+                                                               (flops_a + flops_b) / 1e12))
+
     def run(prec, steps, warmup):
         x = psi64 if prec == "f64" else psi32
         out = torch.empty_like(x)
@@ -114,9 +227,9 @@ def main():
             H.apply(x, prec, out=out)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t) / steps
-        kms = kt.times_ms()
+        kms = np.array(kt.times_ms())
         kt.close()
-        return out, wall, float(np.mean(kms)) / 1e3
+        return out, wall, kms.mean(axis=0) / 1e3
 
     res = {}
     order = [p for p in ("f64", "f32", "bf16x3") if p != args.prec] + [args.prec]
@@ -125,12 +238,16 @@ def main():
     outs = {}
     for prec in order:
         steps = args.steps if prec == args.prec else max(2, args.steps // 3)
-        out, wall, kern = run(prec, steps, args.warmup if prec == args.prec else 1)
+        out, wall, (ka, kb) = run(prec, steps, args.warmup if prec == args.prec else 1)
         outs[prec] = out.double()
-        res[prec] = dict(ms_per_step=wall * 1e3, kernel_ms=kern * 1e3, tflops=flops / wall / 1e12,
-                         kernel_tflops=flops / kern / 1e12, pct_peak=100 * flops / wall / 1e12 / PEAK[prec])
-        log("%-6s %8.2f ms/step  %7.2f TFLOP/s  (kernel %7.2f ms, %.1f%% of %s peak)"
-            % (prec, wall * 1e3, flops / wall / 1e12, kern * 1e3, res[prec]["pct_peak"], prec))
+        res[prec] = dict(ms_per_step=wall * 1e3, kernel_ms=(ka + kb) * 1e3, tflops=flops / wall / 1e12,
+                         kernel_tflops=flops / (ka + kb) / 1e12, pct_peak=100 * flops / wall / 1e12 / PEAK[prec],
+                         phaseA_ms=ka * 1e3, phaseA_tflops=flops_a / ka / 1e12,
+                         phaseB_ms=kb * 1e3, phaseB_tflops=flops_b / kb / 1e12)
+        log("%-6s %8.2f ms/step  %7.2f TFLOP/s  (%.1f%% of %s peak; phase A %.2f ms %.1f TFLOP/s, "
+            "phase B %.2f ms %.1f TFLOP/s)"
+            % (prec, wall * 1e3, flops / wall / 1e12, res[prec]["pct_peak"], prec, ka * 1e3,
+               flops_a / ka / 1e12, kb * 1e3, flops_b / kb / 1e12))
     if "f64" in outs:
         ref = outs["f64"]
         for prec in ("f32", "bf16x3"):
@@ -184,7 +301,6 @@ def main():
     if not args.no_cpu:
         from oracle import heff as oheff
         rng = np.random.default_rng(11)
-        tasks_dev, ptr = H.tasks()
         sec_cost = np.add.reduceat(tasks_dev["cost"], ptr[:-1]) if len(tasks_dev) else np.zeros(P.nS)
         sec_cost = np.where(np.diff(ptr) > 0, sec_cost, 0)
         order = rng.permutation(P.nS)
@@ -215,6 +331,18 @@ def main():
             sample_parity[prec] = float(np.sqrt(num / max(den, 1e-300)))
 
     head = res[args.prec]
+    # dominant kernel of the headline precision: the longer of the two phases
+    dom = 0 if head["phaseA_ms"] >= head["phaseB_ms"] else 1
+    d_ms = head["phaseA_ms"] if dom == 0 else head["phaseB_ms"]
+    d_fl = flops_a if dom == 0 else flops_b
+    ach = d_fl / (d_ms / 1e3) / 1e12
+    roofline = {"bound": "mfma", "kernel": KERNEL[args.prec][dom], "achieved": round(ach, 3),
+                "peak": round(PEAK[args.prec], 1), "unit": "TFLOP/s", "frac": round(ach / PEAK[args.prec], 4),
+                "traffic": measured_traffic(args.config, args.prec) if dom == 0 else None,
+                "algorithmic_flops_per_launch": d_fl, "avg_launch_ms": round(d_ms, 3),
+                "both_phases_tflops": round(head["kernel_tflops"], 3),
+                "peak_note": ("BF16 dense 2516.6 TFLOP/s / 3 MFMA products per algorithmic flop"
+                              if args.prec == "bf16x3" else "dense MFMA peak of the dtype")}
     line = {
         "metric": "H_eff*psi TFLOP/s (% MFMA peak) at D=4096, mixed vs FP64, at 1e-8 Ha",
         "value": round(head["tflops"], 3),
@@ -238,12 +366,7 @@ def main():
         "precisions": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in res.items()},
         "mixed_vs_f64_speedup": round(res[args.prec]["tflops"] / res["f64"]["tflops"], 3),
-        "roofline": {"bound": "mfma", "kernel": KERNEL[args.prec],
-                     "achieved": round(head["kernel_tflops"], 3), "peak": round(PEAK[args.prec], 1),
-                     "unit": "TFLOP/s", "frac": round(head["kernel_tflops"] / PEAK[args.prec], 4),
-                     "traffic": None,
-                     "peak_note": ("BF16 dense 2516.6 TFLOP/s / 3 MFMA products per algorithmic flop"
-                                   if args.prec == "bf16x3" else "dense MFMA peak of the dtype")},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "sampled_oracle_parity": sample_parity,
         "davidson": dav,

@@ -217,12 +217,13 @@ tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_opts *opts, c
 
 const char *tns_status_string(tns_status s);
 
-/* Profiling aid: when both events are non-null, the next forward product
- * records `before` on its stream immediately before the persistent MFMA
- * kernel and `after` immediately after it (then forgets them), so that a
- * caller can time that kernel alone.  Pass nulls to disable.  Not
- * thread-safe; the events belong to the caller. */
-void tns_profile_events(hipEvent_t before, hipEvent_t after);
+/* Profiling aid: when all three events are non-null, the next forward
+ * product records `before` on its stream immediately before its first GEMM
+ * phase (the intermediates T_k), `mid` between the two phases and `after`
+ * immediately after the second (the summed products), then forgets them, so
+ * that a caller can time each MFMA kernel alone.  Pass nulls to disable.
+ * Not thread-safe; the events belong to the caller. */
+void tns_profile_events(hipEvent_t before, hipEvent_t mid, hipEvent_t after);
 
 #ifdef __cplusplus
 }

@@ -558,7 +558,7 @@ static ApplyArgs make_args(const Plan &p, const Sched &S, const void *ops, const
   return a;
 }
 
-static hipEvent_t g_ev_before = nullptr, g_ev_after = nullptr;
+static hipEvent_t g_ev_before = nullptr, g_ev_mid = nullptr, g_ev_after = nullptr;
 
 tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *sigma, int beta, hipStream_t st) {
   const Sched &S = p.fwd;
@@ -573,9 +573,9 @@ tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *
 
 tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
                       void *ws, size_t ws_bytes, hipStream_t st) {
-  hipEvent_t evb = g_ev_before, eva = g_ev_after;
-  g_ev_before = g_ev_after = nullptr;
-  return fwd_apply(p, prec, ops, psi, sigma, beta, ws, ws_bytes, st, evb, eva);
+  hipEvent_t ev[3] = {g_ev_before, g_ev_mid, g_ev_after};
+  g_ev_before = g_ev_mid = g_ev_after = nullptr;
+  return fwd_apply(p, prec, ops, psi, sigma, beta, ws, ws_bytes, st, ev[0] && ev[1] && ev[2] ? ev : nullptr);
 }
 
 template <int P>
@@ -635,8 +635,9 @@ extern "C" tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, cons
   return apply_impl(plan_of(tl), prec, op_vals, psi, sigma, beta, ws, ws_bytes, st);
 }
 
-extern "C" void tns_profile_events(hipEvent_t before, hipEvent_t after) {
+extern "C" void tns_profile_events(hipEvent_t before, hipEvent_t mid, hipEvent_t after) {
   g_ev_before = before;
+  g_ev_mid = mid;
   g_ev_after = after;
 }
 

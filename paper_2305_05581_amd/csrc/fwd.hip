@@ -481,7 +481,7 @@ static int grid_of(K kern, int n_cu) {
 
 template <int P, class In>
 static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void *sigma, int beta, char *w,
-                             hipStream_t st, hipEvent_t evb, hipEvent_t eva) {
+                             hipStream_t st, const hipEvent_t *ev) {
   typedef typename FP<P>::Acc Acc;
   const Sched &S = p.fwd;
   const tns_prec prec = (tns_prec)P;
@@ -513,27 +513,27 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   if (p.nS > 0)
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
                        p.dimR, p.pp_off, p.pt_off, pp, pt, g.pp_lo, g.pt_lo);
-  if (evb && eva) TNS_HIP(hipEventRecord(evb, st));
-  if (p.ntasks > 0) {
-    hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
-    if (S.nitems > 0) hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
-  }
-  if (evb && eva) TNS_HIP(hipEventRecord(eva, st));
+  if (ev) TNS_HIP(hipEventRecord(ev[0], st));
+  if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
+  if (ev) TNS_HIP(hipEventRecord(ev[1], st));
+  if (p.ntasks > 0 && S.nitems > 0)
+    hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
+  if (ev) TNS_HIP(hipEventRecord(ev[2], st));
   return launch_epilogue_psi(p, prec == TNS_F64, part, sigma, beta, st);
 }
 
 tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
-                     void *ws, size_t ws_bytes, hipStream_t st, hipEvent_t evb, hipEvent_t eva) {
+                     void *ws, size_t ws_bytes, hipStream_t st, const hipEvent_t *ev) {
   if (ws_bytes < fwd_workspace(p, prec)) return TNS_ERR_WORKSPACE;
   char *w = reinterpret_cast<char *>(ws);
   const int ib = beta != 0.0;
   tns_status s;
   if (prec == TNS_F64)
-    s = fwd_launch<TNS_F64>(p, ops, (const double *)psi, sigma, ib, w, st, evb, eva);
+    s = fwd_launch<TNS_F64>(p, ops, (const double *)psi, sigma, ib, w, st, ev);
   else if (prec == TNS_F32)
-    s = fwd_launch<TNS_F32>(p, ops, (const float *)psi, sigma, ib, w, st, evb, eva);
+    s = fwd_launch<TNS_F32>(p, ops, (const float *)psi, sigma, ib, w, st, ev);
   else
-    s = fwd_launch<TNS_BF16X3>(p, ops, (const float *)psi, sigma, ib, w, st, evb, eva);
+    s = fwd_launch<TNS_BF16X3>(p, ops, (const float *)psi, sigma, ib, w, st, ev);
   if (s != TNS_OK) return s;
   return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
 }

@@ -95,7 +95,7 @@ def library(path=LIB_PATH):
                                    ctypes.POINTER(TnsDavidsonInfo), _P, sz, _P]
     if hasattr(L, "tns_profile_events"):
         L.tns_profile_events.restype = None
-        L.tns_profile_events.argtypes = [_P, _P]
+        L.tns_profile_events.argtypes = [_P, _P, _P]
     L.tns_status_string.restype = ctypes.c_char_p
     L.tns_status_string.argtypes = [ctypes.c_int]
     _lib = L
@@ -308,39 +308,42 @@ def _hip():
 
 
 class KernelTimer:
-    """HIP event pairs around the persistent kernel of successive forward
-    products (library profiling hook); ``arm()`` before each product."""
+    """HIP events around the two MFMA phases of successive forward products
+    (library profiling hook); ``arm()`` before each product.  ``times_ms``
+    returns (phase A ms, phase B ms) per armed product."""
 
     def __init__(self, n):
         hip = _hip()
         self.ev = []
         for _ in range(n):
-            a, b = _P(), _P()
-            if hip.hipEventCreate(ctypes.byref(a)) or hip.hipEventCreate(ctypes.byref(b)):
-                raise RuntimeError("hipEventCreate failed")
-            self.ev.append((a, b))
+            e = [_P(), _P(), _P()]
+            for x in e:
+                if hip.hipEventCreate(ctypes.byref(x)):
+                    raise RuntimeError("hipEventCreate failed")
+            self.ev.append(e)
         self.i = 0
 
     def arm(self):
-        a, b = self.ev[self.i]
-        library().tns_profile_events(a, b)
+        a, m, b = self.ev[self.i]
+        library().tns_profile_events(a, m, b)
         self.i += 1
 
     def times_ms(self):
         hip = _hip()
         out = []
-        for a, b in self.ev[:self.i]:
+        for a, m, b in self.ev[:self.i]:
             hip.hipEventSynchronize(b)
-            ms = ctypes.c_float(0.0)
-            hip.hipEventElapsedTime(ctypes.byref(ms), a, b)
-            out.append(ms.value)
+            t1, t2 = ctypes.c_float(0.0), ctypes.c_float(0.0)
+            hip.hipEventElapsedTime(ctypes.byref(t1), a, m)
+            hip.hipEventElapsedTime(ctypes.byref(t2), m, b)
+            out.append((t1.value, t2.value))
         return out
 
     def close(self):
         hip = _hip()
-        for a, b in self.ev:
-            hip.hipEventDestroy(a)
-            hip.hipEventDestroy(b)
+        for e in self.ev:
+            for x in e:
+                hip.hipEventDestroy(x)
         self.ev = []
 
 
