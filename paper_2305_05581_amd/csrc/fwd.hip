@@ -41,6 +41,23 @@ struct Mat {
   int32_t ld, rows, ident;
 };
 
+// Read of schedule / task metadata that no kernel of the product writes:
+// through the constant address space, so that uniform reads become scalar
+// loads (they do not count against the vector-memory loads in flight).
+template <class T>
+__device__ inline T cld(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)p;
+}
+
+// The fields of a work item the product kernels use, through cld.
+__device__ inline Item load_item(const Item *p) {
+  Item it;
+  it.grp = cld(&p->grp); it.mode = cld(&p->mode); it.p0 = cld(&p->p0); it.np = cld(&p->np);
+  it.tb = cld(&p->tb); it.te = cld(&p->te); it.slot = cld(&p->slot); it.out = cld(&p->out);
+  it.c0 = cld(&p->c0); it.nc = cld(&p->nc); it.cost = 0;
+  return it;
+}
+
 struct FwdArgs {
   const tns_task *tasks;
   int64_t ntasks;
@@ -64,6 +81,9 @@ struct FwdArgs {
   int32_t *queue;  // [0, 8): phase A queues, [8, 16): phase B queues
   int32_t nq;
   const void *zero;  // 64 zero bytes
+  const void *ident;  // BF16X3: identity matrix maxdim x ld8(maxdim) (hi; lo `ident_lo` further)
+  int64_t ident_lo;
+  int32_t ident_ld;
 };
 
 // --- per-precision tile parameters ---------------------------------------------
@@ -226,11 +246,13 @@ __device__ inline Mat op_mat(const FwdArgs &g, int blk, int rows) {
   Mat m;
   m.rows = rows;
   m.lo = g.ops_lo;
-  if (blk < 0) {
+  if (P == TNS_BF16X3 && blk < 0) {  // the identity as a matrix in memory
+    m.p = g.ident; m.lo = g.ident_lo; m.ld = g.ident_ld; m.ident = 0;
+  } else if (blk < 0) {
     m.p = g.zero; m.ld = 0; m.ident = 1;
   } else {
-    m.p = reinterpret_cast<const E *>(g.ops) + g.blk_off[blk];
-    m.ld = g.blk_ld[blk];
+    m.p = reinterpret_cast<const E *>(g.ops) + cld(&g.blk_off[blk]);
+    m.ld = cld(&g.blk_ld[blk]);
     m.ident = 0;
   }
   return m;
@@ -240,28 +262,32 @@ __device__ inline Mat op_mat(const FwdArgs &g, int blk, int rows) {
 template <int P, int PH>
 __device__ inline void seg_ops(const FwdArgs &g, int t, Mat &A, Mat &B, int &K, double *alpha) {
   typedef typename FP<P>::E E;
-  const tns_task k = g.tasks[t];
-  const int *so = g.psi_sec + 4 * k.out, *si = g.psi_sec + 4 * k.in;
-  const int q = g.dimL[so[0]], r = g.dimR[so[3]], m = g.dimL[si[0]], n = g.dimR[si[3]];
-  if (alpha) *alpha = k.alpha;
+  t = __builtin_amdgcn_readfirstlane(t);  // uniform: scalar loads of the task record
+  const tns_task *tp = g.tasks + t;
+  const int out = cld(&tp->out), in = cld(&tp->in), order = cld(&tp->order);
+  const int lblk = cld(&tp->lblk), rblk = cld(&tp->rblk);
+  const int *so = g.psi_sec + 4 * out, *si = g.psi_sec + 4 * in;
+  const int q = cld(&g.dimL[cld(&so[0])]), r = cld(&g.dimR[cld(&so[3])]);
+  const int m = cld(&g.dimL[cld(&si[0])]), n = cld(&g.dimR[cld(&si[3])]);
+  if (alpha) *alpha = cld(&tp->alpha);
   if (PH == 0) {
-    if (k.order == 0) {  // T = L A: B(j, k) = A(k, j) = A^T(j, k)
+    if (order == 0) {  // T = L A: B(j, k) = A(k, j) = A^T(j, k)
       K = m;
-      A = op_mat<P>(g, k.lblk, q);
-      B.p = reinterpret_cast<const E *>(g.pt) + g.pt_off[k.in];
+      A = op_mat<P>(g, lblk, q);
+      B.p = reinterpret_cast<const E *>(g.pt) + cld(&g.pt_off[in]);
       B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n; B.ident = 0;
-    } else {             // T = R A^T: B(j, k) = A(j, k)
+    } else {           // T = R A^T: B(j, k) = A(j, k)
       K = n;
-      A = op_mat<P>(g, k.rblk, r);
-      B.p = reinterpret_cast<const E *>(g.pp) + g.pp_off[k.in];
+      A = op_mat<P>(g, rblk, r);
+      B.p = reinterpret_cast<const E *>(g.pp) + cld(&g.pp_off[in]);
       B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m; B.ident = 0;
     }
   } else {
-    const int k2 = k.order == 0 ? n : m;
+    const int k2 = order == 0 ? n : m;
     K = k2;
-    A.p = reinterpret_cast<const E *>(g.T) + g.t_off[t];
-    A.lo = g.T_lo; A.ld = ld8(k2); A.rows = k.order == 0 ? q : r; A.ident = 0;
-    B = k.order == 0 ? op_mat<P>(g, k.rblk, r) : op_mat<P>(g, k.lblk, q);
+    A.p = reinterpret_cast<const E *>(g.T) + cld(&g.t_off[t]);
+    A.lo = g.T_lo; A.ld = ld8(k2); A.rows = order == 0 ? q : r; A.ident = 0;
+    B = order == 0 ? op_mat<P>(g, rblk, r) : op_mat<P>(g, lblk, q);
   }
 }
 
@@ -275,7 +301,7 @@ __device__ inline int64_t qa_count(int64_t ntasks, int nq, int q) {
 __device__ inline int64_t qa_task(int nq, int q, int64_t j) { return (j / 4) * 4 * nq + 4 * q + (j % 4); }
 
 template <int PH>
-__device__ inline int64_t pop_work(const FwdArgs &g) {
+__device__ inline int pop_work(const FwdArgs &g) {
   const int home = blockIdx.x % g.nq;
   for (int k = 0; k < g.nq; ++k) {
     const int q = home + k < g.nq ? home + k : home + k - g.nq;
@@ -283,12 +309,12 @@ __device__ inline int64_t pop_work(const FwdArgs &g) {
       const int64_t n = qa_count(g.ntasks, g.nq, q);
       if (n <= 0) continue;
       const int j = atomicAdd(g.queue + q, 1);
-      if (j < n) return qa_task(g.nq, q, j);
+      if (j < n) return (int)qa_task(g.nq, q, j);
     } else {
       const int64_t b = g.qbase[q], n = g.qbase[q + 1] - b;
       if (n <= 0) continue;
       const int j = atomicAdd(g.queue + 8 + q, 1);
-      if (j < n) return b + j;
+      if (j < n) return (int)(b + j);
     }
   }
   return -1;
@@ -306,7 +332,7 @@ __device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int s
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  auto seg_task = [&](int s) { return PH == 0 ? s : g.idx[s]; };
+  auto seg_task = [&](int s) { return PH == 0 ? s : cld(&g.idx[s]); };
   Mat A, B;
   int K;
   seg_ops<P, PH>(g, seg_task(sb), A, B, K, nullptr);
@@ -350,13 +376,15 @@ template <int P, int PH>
 __global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
   typedef typename FP<P>::A4 A4;
   __shared__ FwdSmem<P> sm;
-  __shared__ int64_t s_work;
+  __shared__ int s_work;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
   for (;;) {
     if (threadIdx.x == 0) s_work = pop_work<PH>(g);
     __syncthreads();
-    const int64_t wk = s_work;
+    // uniform: the item's metadata then comes through scalar loads, which
+    // leave the vector-memory count (operand loads in flight) alone
+    const int wk = __builtin_amdgcn_readfirstlane((int)s_work);
     __syncthreads();
     if (wk < 0) break;
     A4 acc[4][4];
@@ -381,7 +409,7 @@ __global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
               for (int v = 0; v < 4; ++v) {
                 const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
                 if (row < rows && col < ld) {
-                  const int64_t o = g.t_off[t] + (int64_t)row * ld + col;
+                  const int64_t o = cld(&g.t_off[t]) + (int64_t)row * ld + col;
                   if constexpr (P == TNS_BF16X3) {
                     const float x = alf * acc[i][j][v];
                     const uint16_t h = f32_to_bf16_rne(x);
@@ -397,10 +425,10 @@ __global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
             }
         }
     } else {
-      const Item it = g.items[wk];
+      const Item it = load_item(g.items + wk);
       tile_gemm<P, 1>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
-      const int R = g.grp_rows[it.grp], C = g.grp_cols[it.grp];
-      typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + g.slot_off[it.slot];
+      const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
+      typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -419,6 +447,323 @@ __global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
   }
 }
 
+// --- BF16x3: direct global -> LDS loads into a ring of stages ---------------------
+// A stage holds 128 x 32 tiles of A and of B, high and low halves: four
+// arrays of eight 16-row chunks of 1 KB.  Row r of a chunk keeps its four
+// 16-byte k-vectors at slots kv ^ bswz(r), so that the 16 rows read by one
+// MFMA operand fetch fall into distinct LDS banks.  Loads go straight from
+// global memory into the ring (global_load_lds, 16 bytes per lane), BNS - 1
+// stages ahead of the MFMA work; a stage is consumed after a vector-memory
+// count wait and one barrier.  Out-of-range rows and whole k-vectors beyond
+// K read the zero region; the library's own operands (T, padded psi, the
+// identity) are zero beyond K, so the k-tail of an operator row meets zeros.
+constexpr int BNS = 4, BBK = 32;
+constexpr int BLOADS = 8;  // global_load_lds per wave and stage
+__device__ inline int bswz(int r) { return (r >> 1) & 3; }
+struct __attribute__((aligned(16))) BfRing {
+  uint16_t s[BNS][4][GM * BBK];  // [stage][A hi, A lo, B hi, B lo][chunk * 512 + slot]
+};
+
+__device__ inline void gl_lds(const void *src, void *dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                   (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+// Waits until at most n_after stages of this wave's ring loads are in flight
+// (vector-memory loads complete in order), then joins the workgroup.  No
+// fence: only the LDS written by this kernel's ring loads is exchanged here.
+__device__ inline void ring_sync(int n_after) {
+  constexpr int E = (7 << 4) | (15 << 8);  // expcnt, lgkmcnt: no wait
+  if (n_after >= 2)
+    __builtin_amdgcn_s_waitcnt(E | (2 * BLOADS & 15) | ((2 * BLOADS >> 4) << 14));
+  else if (n_after == 1)
+    __builtin_amdgcn_s_waitcnt(E | (BLOADS & 15) | ((BLOADS >> 4) << 14));
+  else
+    __builtin_amdgcn_s_waitcnt(E);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+static_assert(BNS == 4, "ring_sync covers up to two stages in flight after the awaited one");
+
+__device__ inline void bf_issue(BfRing &rg, int buf, const Mat &A, const Mat &B, int r0, int c0, int k0, int K,
+                                const void *zero) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rin = lane >> 2;
+  const int k = k0 + 8 * ((lane & 3) ^ bswz(rin));
+  const uint16_t *z = reinterpret_cast<const uint16_t *>(zero);
+  const bool kin = k < K;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int chunk = 2 * w + h;
+    const int ra = r0 + 16 * chunk + rin, rb = c0 + 16 * chunk + rin;
+    const bool ia = kin && ra < A.rows, ib = kin && rb < B.rows;
+    const uint16_t *pa = reinterpret_cast<const uint16_t *>(A.p) + (int64_t)ra * A.ld + k;
+    const uint16_t *pb = reinterpret_cast<const uint16_t *>(B.p) + (int64_t)rb * B.ld + k;
+    gl_lds(ia ? pa : z, &rg.s[buf][0][chunk * 512]);
+    gl_lds(ia ? pa + A.lo : z, &rg.s[buf][1][chunk * 512]);
+    gl_lds(ib ? pb : z, &rg.s[buf][2][chunk * 512]);
+    gl_lds(ib ? pb + B.lo : z, &rg.s[buf][3][chunk * 512]);
+  }
+}
+
+__device__ inline void bf_mma(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
+  const int off = (l16 * 4 + (g ^ bswz(l16))) * 8;
+  u16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ah[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * 4 + i) * 512 + off]);
+    al[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * 4 + i) * 512 + off]);
+    bh[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * 4 + i) * 512 + off]);
+    bl[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * 4 + i) * 512 + off]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = mfma_bf(al[i], bh[j], acc[i][j]);
+      acc[i][j] = mfma_bf(ah[i], bl[j], acc[i][j]);
+      acc[i][j] = mfma_bf(ah[i], bh[j], acc[i][j]);
+    }
+}
+
+template <int PH>
+__global__ __launch_bounds__(GTH) void k_fwd_bf(FwdArgs g) {
+  __shared__ BfRing rg;
+  __shared__ int s_work;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  for (;;) {
+    if (threadIdx.x == 0) s_work = pop_work<PH>(g);
+    __syncthreads();
+    // uniform: the item's metadata then comes through scalar loads, which
+    // leave the vector-memory count (operand loads in flight) alone
+    const int wk = __builtin_amdgcn_readfirstlane((int)s_work);
+    __syncthreads();
+    if (wk < 0) break;
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
+    if (PH == 0) {
+      // all tiles of task wk as one stream of K steps, row strips in turn
+      const int t = (int)wk;
+      Mat A, B;
+      int K;
+      double alpha;
+      seg_ops<TNS_BF16X3, 0>(g, t, A, B, K, &alpha);
+      const int rows = A.rows, cols = B.rows, ld = ld8(cols);
+      const int nk = (K + BBK - 1) / BBK, ntc = (cols + GN - 1) / GN;
+      const int nsteps = ((rows + GM - 1) / GM) * ntc * nk;
+      auto issue = [&](int ls) {
+        const int tile = ls / nk, j = ls - tile * nk;
+        bf_issue(rg, ls % BNS, A, B, (tile / ntc) * GM, (tile % ntc) * GN, j * BBK, K, g.zero);
+      };
+      for (int ls = 0; ls < BNS - 1 && ls < nsteps; ++ls) issue(ls);
+      const float alf = (float)alpha;
+      uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[t]);
+      for (int s = 0; s < nsteps; ++s) {
+        ring_sync(min(nsteps, s + BNS - 1) - 1 - s);
+        if (s + BNS - 1 < nsteps) issue(s + BNS - 1);
+        bf_mma(rg, s % BNS, acc);
+        if ((s + 1) % nk == 0) {
+          const int tile = s / nk, r0 = (tile / ntc) * GM, c0 = (tile % ntc) * GN;
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int col = c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+                if (row < rows && col < ld) {
+                  const float x = alf * acc[i][j][v];
+                  const uint16_t h = f32_to_bf16_rne(x);
+                  const int64_t o = (int64_t)row * ld + col;
+                  Th[o] = h;
+                  Th[g.T_lo + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
+                }
+              }
+              acc[i][j] = vzero<f4>();
+            }
+        }
+      }
+    } else {
+      const Item it = load_item(g.items + wk);
+      int ls = it.tb, lj = 0, lK, issued = 0;
+      bool ldone = false;
+      Mat LA, LB;
+      seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+      auto issue_next = [&]() {
+        bf_issue(rg, issued % BNS, LA, LB, it.p0, it.c0, lj * BBK, lK, g.zero);
+        ++issued;
+        if (++lj * BBK >= lK) {
+          lj = 0;
+          if (++ls < it.te) seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+          else ldone = true;
+        }
+      };
+      while (!ldone && issued < BNS - 1) issue_next();
+      for (int s = 0; s < issued; ++s) {
+        ring_sync(issued - 1 - s);
+        if (!ldone) issue_next();
+        bf_mma(rg, s % BNS, acc);
+      }
+      const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
+      float *slot = reinterpret_cast<float *>(g.partial) + cld(&g.slot_off[it.slot]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = it.c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+            if (row < R && col < C) {
+              const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
+              slot[o] = acc[i][j][v];
+            }
+          }
+        }
+    }
+  }
+}
+
+// Phase A of the BF16x3 path.  A work item is a block of ABT consecutive
+// tasks; all tiles of all its tasks form one stream of K steps, so the ring
+// keeps loading across tile and task boundaries.  The MFMA operand roles are
+// swapped (D = M-side x X-side^T), which gives every lane four consecutive
+// columns of one row of T: the epilogue writes 8-byte groups of the high and
+// low halves.
+constexpr int ABT = 4;
+
+__device__ inline int pop_block(const FwdArgs &g, int64_t nblk) {
+  const int home = blockIdx.x % g.nq;
+  for (int k = 0; k < g.nq; ++k) {
+    const int q = home + k < g.nq ? home + k : home + k - g.nq;
+    const int64_t n = nblk > q ? (nblk - 1 - q) / g.nq + 1 : 0;
+    if (n <= 0) continue;
+    const int j = atomicAdd(g.queue + q, 1);
+    if (j < n) return (int)((int64_t)j * g.nq + q);
+  }
+  return -1;
+}
+
+__device__ inline void bf_mma_t(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
+  const int off = (l16 * 4 + (g ^ bswz(l16))) * 8;
+  u16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    ah[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * 4 + i) * 512 + off]);
+    al[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * 4 + i) * 512 + off]);
+    bh[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * 4 + i) * 512 + off]);
+    bl[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * 4 + i) * 512 + off]);
+  }
+  // acc[i][j]: rows = T columns wn*64 + 16 i + .., columns = T rows wm*64 + 16 j + ..
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = mfma_bf(bl[i], ah[j], acc[i][j]);
+      acc[i][j] = mfma_bf(bh[i], al[j], acc[i][j]);
+      acc[i][j] = mfma_bf(bh[i], ah[j], acc[i][j]);
+    }
+}
+
+typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(GTH) void k_fwd_bfa(FwdArgs g) {
+  __shared__ BfRing rg;
+  __shared__ int s_work;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  const int64_t nblk = (g.ntasks + ABT - 1) / ABT;
+  for (;;) {
+    if (threadIdx.x == 0) s_work = pop_block(g, nblk);
+    __syncthreads();
+    const int b = __builtin_amdgcn_readfirstlane(s_work);
+    __syncthreads();
+    if (b < 0) break;
+    const int t_end = (int)min((int64_t)(b + 1) * ABT, g.ntasks);
+    // load cursor: (task, tile row, tile column, k) in stream order
+    int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0;
+    bool ldone = false;
+    Mat LA, LB;
+    seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+    auto issue_next = [&]() {
+      bf_issue(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
+      ++issued;
+      if ((lk0 += BBK) < lK) return;
+      lk0 = 0;
+      if ((lc0 += GN) < LB.rows) return;
+      lc0 = 0;
+      if ((lr0 += GM) < LA.rows) return;
+      lr0 = 0;
+      if (++lt < t_end) seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+      else ldone = true;
+    };
+    while (!ldone && issued < BNS - 1) issue_next();
+    // compute cursor, BNS - 1 steps behind
+    int ct = b * ABT, cr0 = 0, cc0 = 0, ck0 = 0, cK;
+    double alpha;
+    Mat CA, CB;
+    seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
+    for (int s = 0; s < issued; ++s) {
+      ring_sync(issued - 1 - s);
+      if (!ldone) issue_next();
+      bf_mma_t(rg, s % BNS, acc);
+      if ((ck0 += BBK) < cK) continue;
+      // tile (cr0, cc0) of task ct complete: T = alpha * acc as BF16 halves
+      {
+        const int rows = CA.rows, ld = ld8(CB.rows);
+        uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[ct]);
+        const float alf = (float)alpha;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = cr0 + wm * 64 + j * 16 + l16;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int col = cc0 + wn * 64 + i * 16 + 4 * lg;
+            if (row < rows && col < ld) {
+              const f4 x = alf * acc[i][j];
+              const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+              const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                              (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+              const int64_t o = (int64_t)row * ld + col;
+              *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
+              *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+            }
+            acc[i][j] = vzero<f4>();
+          }
+        }
+      }
+      ck0 = 0;
+      if ((cc0 += GN) < CB.rows) continue;
+      cc0 = 0;
+      if ((cr0 += GM) < CA.rows) continue;
+      cr0 = 0;
+      if (++ct < t_end) seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+    }
+  }
+}
+
+__global__ void k_ident_bf(uint16_t *p, int n, int ld, int64_t lo) {
+  GRID_STRIDE(e, (int64_t)n * ld) {
+    const int64_t i = e / ld, j = e % ld;
+    p[e] = i == j ? (uint16_t)0x3f80 : (uint16_t)0;
+    p[lo + e] = 0;
+  }
+}
+
 // --- padded copies of psi ----------------------------------------------------------
 // Sector s (m x n) to pp (m x ld8(n)) and, transposed, to pt (n x ld8(m));
 // BF16X3 writes high halves and, `lo` elements further, low halves.
@@ -430,20 +775,30 @@ __global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, co
   const int s = blockIdx.x;
   const int m = dimL[psi_sec[4 * s]], n = dimR[psi_sec[4 * s + 3]];
   const int lm = ld8(m), ln = ld8(n);
-  const int64_t n_el = (int64_t)m * n;
+  const In *A = psi + psi_off[s];
   E *P0 = reinterpret_cast<E *>(pp) + pp_off[s], *P1 = reinterpret_cast<E *>(pt) + pt_off[s];
-  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < n_el; e += (int64_t)gridDim.y * blockDim.x) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    const In x = psi[psi_off[s] + e];
-    const int64_t a = (int64_t)i * ln + j, b = (int64_t)j * lm + i;
+  const int64_t step = (int64_t)gridDim.y * blockDim.x, e0 = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  // padded rows (zeros beyond n), then padded transposed rows (zeros beyond m)
+  for (int64_t e = e0; e < (int64_t)m * ln; e += step) {
+    const int i = (int)(e / ln), j = (int)(e % ln);
+    const float v = j < n ? (float)A[(int64_t)i * n + j] : 0.f;
     if constexpr (P == TNS_BF16X3) {
-      const float v = (float)x;
-      const uint16_t h = f32_to_bf16_rne(v), l = f32_to_bf16_rne(v - bf16_to_f32(h));
-      P0[a] = h; P0[pp_lo + a] = l;
-      P1[b] = h; P1[pt_lo + b] = l;
+      const uint16_t h = f32_to_bf16_rne(v);
+      P0[e] = h;
+      P0[pp_lo + e] = f32_to_bf16_rne(v - bf16_to_f32(h));
     } else {
-      P0[a] = (E)x;
-      P1[b] = (E)x;
+      P0[e] = j < n ? (E)A[(int64_t)i * n + j] : E(0);
+    }
+  }
+  for (int64_t e = e0; e < (int64_t)n * lm; e += step) {
+    const int j = (int)(e / lm), i = (int)(e % lm);
+    const float v = i < m ? (float)A[(int64_t)i * n + j] : 0.f;
+    if constexpr (P == TNS_BF16X3) {
+      const uint16_t h = f32_to_bf16_rne(v);
+      P1[e] = h;
+      P1[pt_lo + e] = f32_to_bf16_rne(v - bf16_to_f32(h));
+    } else {
+      P1[e] = i < m ? (E)A[(int64_t)i * n + j] : E(0);
     }
   }
 }
@@ -459,17 +814,25 @@ static size_t region(int64_t n, tns_prec p) {
   return align_up(b + 64, 256);
 }
 
-// Workspace of the forward product:
-// [queue counters, zero bytes | partial slots | T | padded psi | padded psi^T].
+// Identity matrix of the BF16X3 path: maxdim x ld8(maxdim).
+static int64_t ident_elems(const Plan &p) { return (int64_t)p.maxdim * ld8(p.maxdim); }
+
+// Workspace of the forward product: [queue counters, zero bytes | partial
+// slots | T | padded psi | padded psi^T | (BF16X3) identity].
 size_t fwd_workspace(const Plan &p, tns_prec prec) {
   return 256 + align_up((size_t)std::max<int64_t>(p.fwd.partial_elems, 1) * (prec == TNS_F64 ? 8 : 4), 256) +
-         region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec);
+         region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec) +
+         (prec == TNS_BF16X3 ? region(ident_elems(p), prec) : 0);
 }
 
 // queue counters (bytes 0..63) and the 64-byte zero region that out-of-range
 // loads read (bytes 64..127)
 __global__ void k_reset_queues(int32_t *p) {
   if (threadIdx.x < 32) p[threadIdx.x] = 0;
+}
+
+static inline unsigned nblocks(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16));
 }
 
 template <class K>
@@ -494,6 +857,8 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   void *pp = c;
   c += region(p.pp_elems, prec);
   void *pt = c;
+  c += region(p.pt_elems, prec);
+  void *id = c;
 
   FwdArgs g;
   memset(&g, 0, sizeof(g));
@@ -508,16 +873,29 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   g.slot_off = S.slot_off; g.qbase = S.qbase; g.partial = part;
   g.queue = queue; g.nq = S.nq;
   g.zero = w + 64;
+  g.ident = id; g.ident_lo = lo_of(ident_elems(p)); g.ident_ld = ld8(p.maxdim);
 
   hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, queue);
+  if (P == TNS_BF16X3)
+    hipLaunchKernelGGL(k_ident_bf, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, (uint16_t *)id, p.maxdim,
+                       ld8(p.maxdim), g.ident_lo);
   if (p.nS > 0)
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
                        p.dimR, p.pp_off, p.pt_off, pp, pt, g.pp_lo, g.pt_lo);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
-  if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
+  if (p.ntasks > 0) {
+    if (P == TNS_BF16X3)
+      hipLaunchKernelGGL(k_fwd_bfa, dim3(grid_of(k_fwd_bfa, p.n_cu)), dim3(GTH), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
+  }
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
-  if (p.ntasks > 0 && S.nitems > 0)
-    hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
+  if (p.ntasks > 0 && S.nitems > 0) {
+    if (P == TNS_BF16X3)
+      hipLaunchKernelGGL(k_fwd_bf<1>, dim3(grid_of(k_fwd_bf<1>, p.n_cu)), dim3(GTH), 0, st, g);
+    else
+      hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
+  }
   if (ev) TNS_HIP(hipEventRecord(ev[2], st));
   return launch_epilogue_psi(p, prec == TNS_F64, part, sigma, beta, st);
 }

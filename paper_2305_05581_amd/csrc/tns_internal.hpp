@@ -76,6 +76,7 @@ struct Sched {
 // workspace.
 struct Plan {
   int32_t nL, nR, nS, nOps, nBlk, nTerms, nmax, n_cu;
+  int32_t maxdim, pad_;  // largest sector dimension
   int64_t n_vals, psi_dim, ntasks;
   // copied tables
   int32_t *qL, *dimL, *qR, *dimR, *psi_sec;
