@@ -141,13 +141,105 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def batch_specs(n, seed=4000):
+    """Instances of the batched workload: L ~ U{20..40}, D log-uniform in
+    [256, 2048], sector mean sqrt(D), max 8 sqrt(D), K = L^2 terms, seed 4000+i."""
+    import math
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = int(rng.integers(20, 41))
+        D = int(round(math.exp(rng.uniform(math.log(256), math.log(2048)))))
+        mean = max(1, int(round(math.sqrt(D))))
+        out.append(dict(L=L, N=L, twoSz=L % 2, D=D, mean=mean, dmax=min(D, 8 * mean), K=L * L, seed=seed + i))
+    return out
+
+
+def bench_batch(args):
+    """Many uneven products: one at a time (two launches each) against the
+    batched form (one launch per phase for all instances), eager and replayed
+    from a hipGraph.  Prints one JSON line."""
+    import torch
+    from synth import synthetic_problem, gaussian_psi
+    from paper_2305_05581_amd.tns import HeffProblem, HeffBatch
+    prec = args.only or "f32"
+    dt = torch.float64 if prec == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    specs = batch_specs(args.instances)
+    Hs, flops, t0 = [], 0, time.time()
+    for i, c in enumerate(specs):
+        P = synthetic_problem(c["L"], c["N"], c["twoSz"], c["D"], c["mean"], c["dmax"], c["K"], seed=c["seed"],
+                              threads=min(16, os.cpu_count() or 1))
+        vals = torch.from_numpy(P.op_vals).to(dev)
+        H = HeffProblem(P, device=dev, vals64=vals)
+        H.operands(prec)
+        P.op_vals = None  # the device copy is the only one needed from here on
+        Hs.append(H)
+        flops += H.total_flops
+        log("instance %2d: L=%d D=%d sectors %d tasks %d %.2f GFLOP  (%.0f s)"
+            % (i, c["L"], c["D"], P.nS, H.ntasks, H.total_flops / 1e9, time.time() - t0))
+    B = HeffBatch(Hs)
+    psis = [torch.from_numpy(gaussian_psi(H.P, 100 + i)).to(dev, dt) for i, H in enumerate(Hs)]
+    seq_out = [torch.empty_like(x) for x in psis]
+    bat_out = [torch.empty_like(x) for x in psis]
+
+    def one_at_a_time():
+        for H, x, y in zip(Hs, psis, seq_out):
+            H.apply(x, prec, out=y)
+
+    def batched():
+        B.apply(psis, prec, outs=bat_out)
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    t_seq = timed(one_at_a_time, args.steps)
+    log("one at a time: %.2f ms  %.2f TFLOP/s" % (t_seq * 1e3, flops / t_seq / 1e12))
+    t_bat = timed(batched, args.steps)
+    log("batched:       %.2f ms  %.2f TFLOP/s" % (t_bat * 1e3, flops / t_bat / 1e12))
+    same = all(torch.equal(a, b) for a, b in zip(seq_out, bat_out))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batched()
+    t_graph = timed(g.replay, args.steps)
+    same_graph = all(torch.equal(a, b) for a, b in zip(seq_out, bat_out))
+    log("batched graph: %.2f ms  %.2f TFLOP/s  (equal to one-at-a-time: %s / %s)"
+        % (t_graph * 1e3, flops / t_graph / 1e12, same, same_graph))
+    line = {
+        "metric": "batched H_eff*psi TFLOP/s, %d uneven instances in one launch per phase" % len(Hs),
+        "value": round(flops / t_graph / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_graph * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "batch64: %d instances, L ~ U{20..40}, N = L, 2Sz = L mod 2, D log-uniform "
+                               "[256, 2048], sector mean sqrt(D), max 8 sqrt(D), K = L^2, seeds 4000+i"
+                               % len(Hs),
+                   "flops_per_step": flops, "tasks": sum(H.ntasks for H in Hs)},
+        "one_at_a_time": {"ms_per_step": round(t_seq * 1e3, 3), "tflops": round(flops / t_seq / 1e12, 3)},
+        "batched_eager": {"ms_per_step": round(t_bat * 1e3, 3), "tflops": round(flops / t_bat / 1e12, 3)},
+        "batched_graph": {"ms_per_step": round(t_graph * 1e3, 3), "tflops": round(flops / t_graph / 1e12, 3)},
+        "speedup_vs_one_at_a_time": round(t_seq / t_graph, 3),
+        "equal_to_one_at_a_time": bool(same and same_graph),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "f32", "f64"])
-    ap.add_argument("--config", default="d4096", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="d4096", choices=sorted(CONFIGS) + ["batch64"],
+                    help="batch64: many uneven instances, one launch per phase vs one product at a time")
+    ap.add_argument("--instances", type=int, default=64, help="batch64: number of instances")
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-gflop", type=float, default=150.0, help="flops of the CPU oracle sample (GFLOP)")
@@ -167,6 +259,9 @@ def main():
         print("bench.py measures one GPU's share only: this build runs on a single GPU "
               "(no collectives or sharding); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.config == "batch64":
+        bench_batch(args)
+        return
 
     import torch
     from synth import synthetic_problem, gaussian_psi, gapped_guess

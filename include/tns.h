@@ -177,6 +177,22 @@ tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, const void *op_
  * grad_ops   = sum_tasks alpha G_out R A^T into L,    (operator-value layout,
  *              alpha G_out^T L A into R                 padding untouched; nullable)
  * Both outputs are overwritten (not accumulated).  FP32 and FP64 only. */
+/* Batched form of tns_apply_heff (level 3, Eq. (2), for many independent
+ * problems): sigma_i := beta * sigma_i + H_eff,i psi_i for i < n, with one
+ * persistent launch per GEMM phase for all instances together (work of the
+ * costliest instances first), so that small and uneven instances share the
+ * device.  tls[i]: task lists built by tns_build_tasklist on this device;
+ * op_vals[i], psi[i], sigma[i]: that instance's operands (device pointers, as
+ * in tns_apply_heff); the pointer arrays themselves are host memory, read
+ * during the call (their contents are recorded into the launch arguments, so
+ * the call can be captured into a hipGraph).  Results are bitwise identical
+ * to n separate tns_apply_heff calls.  TNS_ERR_ARG for null entries, n <= 0
+ * or task lists built for devices with different XCD counts. */
+size_t tns_apply_batch_workspace_bytes(const tns_tasklist *const *tls, int n, tns_prec prec);
+tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n, tns_prec prec,
+                                const void *const *op_vals, const void *const *psi, void *const *sigma,
+                                double beta, void *ws, size_t ws_bytes, hipStream_t stream);
+
 size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
 tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
                                    const void *psi, const void *grad_sigma, void *grad_psi,

@@ -560,6 +560,12 @@ static ApplyArgs make_args(const Plan &p, const Sched &S, const void *ops, const
 
 static hipEvent_t g_ev_before = nullptr, g_ev_mid = nullptr, g_ev_after = nullptr;
 
+bool take_profile_events(hipEvent_t ev[3]) {
+  ev[0] = g_ev_before; ev[1] = g_ev_mid; ev[2] = g_ev_after;
+  g_ev_before = g_ev_mid = g_ev_after = nullptr;
+  return ev[0] && ev[1] && ev[2];
+}
+
 tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *sigma, int beta, hipStream_t st) {
   const Sched &S = p.fwd;
   if (f64)
@@ -573,9 +579,9 @@ tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *
 
 tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
                       void *ws, size_t ws_bytes, hipStream_t st) {
-  hipEvent_t ev[3] = {g_ev_before, g_ev_mid, g_ev_after};
-  g_ev_before = g_ev_mid = g_ev_after = nullptr;
-  return fwd_apply(p, prec, ops, psi, sigma, beta, ws, ws_bytes, st, ev[0] && ev[1] && ev[2] ? ev : nullptr);
+  hipEvent_t ev[3];
+  const bool timed = take_profile_events(ev);
+  return fwd_apply(p, prec, ops, psi, sigma, beta, ws, ws_bytes, st, timed ? ev : nullptr);
 }
 
 template <int P>

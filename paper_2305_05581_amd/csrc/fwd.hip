@@ -24,6 +24,8 @@
 // of the padded copies of A and A^T), staged global -> registers -> LDS with
 // 16-byte loads and a double-buffered LDS pipeline, one barrier per K step.
 #include <algorithm>
+#include <type_traits>
+#include <vector>
 
 #include "kern.hpp"
 #include "tns_internal.hpp"
@@ -372,78 +374,85 @@ __device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int s
   }
 }
 
+// One work item of the register-staged path: phase A = all tiles of task
+// wk, phase B = item wk of the phase-B schedule.
 template <int P, int PH>
-__global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
+__device__ inline void fwd_item(const FwdArgs &g, FwdSmem<P> &sm, int wk) {
   typedef typename FP<P>::A4 A4;
-  __shared__ FwdSmem<P> sm;
-  __shared__ int s_work;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  A4 acc[4][4];
+  if (PH == 0) {
+    // every tile of task wk, row strips in turn
+    const int t = (int)wk;
+    Mat A, B;
+    int K;
+    double alpha;
+    seg_ops<P, 0>(g, t, A, B, K, &alpha);
+    const int rows = A.rows, cols = B.rows, ld = ld8(cols);
+    for (int r0 = 0; r0 < rows; r0 += GM)
+      for (int c0 = 0; c0 < cols; c0 += GN) {
+        tile_gemm<P, 0>(g, sm, t, t + 1, r0, c0, acc);
+        const float alf = (float)alpha;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int col = c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+              if (row < rows && col < ld) {
+                const int64_t o = cld(&g.t_off[t]) + (int64_t)row * ld + col;
+                if constexpr (P == TNS_BF16X3) {
+                  const float x = alf * acc[i][j][v];
+                  const uint16_t h = f32_to_bf16_rne(x);
+                  reinterpret_cast<uint16_t *>(g.T)[o] = h;
+                  reinterpret_cast<uint16_t *>(g.T)[g.T_lo + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
+                } else if constexpr (P == TNS_F32) {
+                  reinterpret_cast<float *>(g.T)[o] = alf * acc[i][j][v];
+                } else {
+                  reinterpret_cast<double *>(g.T)[o] = alpha * acc[i][j][v];
+                }
+              }
+            }
+          }
+      }
+  } else {
+    const Item it = load_item(g.items + wk);
+    tile_gemm<P, 1>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
+    const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
+    typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = it.c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+          if (row < R && col < C) {
+            const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
+            slot[o] = acc[i][j][v];
+          }
+        }
+      }
+  }
+}
+
+template <int P, int PH>
+__global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
+  __shared__ FwdSmem<P> sm;
+  __shared__ int s_work;
   for (;;) {
     if (threadIdx.x == 0) s_work = pop_work<PH>(g);
     __syncthreads();
     // uniform: the item's metadata then comes through scalar loads, which
     // leave the vector-memory count (operand loads in flight) alone
-    const int wk = __builtin_amdgcn_readfirstlane((int)s_work);
+    const int wk = __builtin_amdgcn_readfirstlane(s_work);
     __syncthreads();
     if (wk < 0) break;
-    A4 acc[4][4];
-    if (PH == 0) {
-      // every tile of task wk, row strips in turn
-      const int t = (int)wk;
-      Mat A, B;
-      int K;
-      double alpha;
-      seg_ops<P, 0>(g, t, A, B, K, &alpha);
-      const int rows = A.rows, cols = B.rows, ld = ld8(cols);
-      for (int r0 = 0; r0 < rows; r0 += GM)
-        for (int c0 = 0; c0 < cols; c0 += GN) {
-          tile_gemm<P, 0>(g, sm, t, t + 1, r0, c0, acc);
-          const float alf = (float)alpha;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int col = c0 + wn * 64 + j * 16 + l16;
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
-                if (row < rows && col < ld) {
-                  const int64_t o = cld(&g.t_off[t]) + (int64_t)row * ld + col;
-                  if constexpr (P == TNS_BF16X3) {
-                    const float x = alf * acc[i][j][v];
-                    const uint16_t h = f32_to_bf16_rne(x);
-                    reinterpret_cast<uint16_t *>(g.T)[o] = h;
-                    reinterpret_cast<uint16_t *>(g.T)[g.T_lo + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
-                  } else if constexpr (P == TNS_F32) {
-                    reinterpret_cast<float *>(g.T)[o] = alf * acc[i][j][v];
-                  } else {
-                    reinterpret_cast<double *>(g.T)[o] = alpha * acc[i][j][v];
-                  }
-                }
-              }
-            }
-        }
-    } else {
-      const Item it = load_item(g.items + wk);
-      tile_gemm<P, 1>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
-      const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
-      typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int col = it.c0 + wn * 64 + j * 16 + l16;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
-            if (row < R && col < C) {
-              const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
-              slot[o] = acc[i][j][v];
-            }
-          }
-        }
-    }
+    fwd_item<P, PH>(g, sm, wk);
   }
 }
 
@@ -528,108 +537,67 @@ __device__ inline void bf_mma(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
     }
 }
 
-template <int PH>
-__global__ __launch_bounds__(GTH) void k_fwd_bf(FwdArgs g) {
-  __shared__ BfRing rg;
-  __shared__ int s_work;
+// Phase B of the BF16x3 path: one item (output tile, chunk of tasks), the
+// tasks' K steps streamed through the ring.
+__device__ inline void bf_item_b(const FwdArgs &g, BfRing &rg, int wk) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
+  const Item it = load_item(g.items + wk);
+  int ls = it.tb, lj = 0, lK, issued = 0;
+  bool ldone = false;
+  Mat LA, LB;
+  seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+  auto issue_next = [&]() {
+    bf_issue(rg, issued % BNS, LA, LB, it.p0, it.c0, lj * BBK, lK, g.zero);
+    ++issued;
+    if (++lj * BBK >= lK) {
+      lj = 0;
+      if (++ls < it.te) seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+      else ldone = true;
+    }
+  };
+  while (!ldone && issued < BNS - 1) issue_next();
+  for (int s = 0; s < issued; ++s) {
+    ring_sync(issued - 1 - s);
+    if (!ldone) issue_next();
+    bf_mma(rg, s % BNS, acc);
+  }
+  const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
+  float *slot = reinterpret_cast<float *>(g.partial) + cld(&g.slot_off[it.slot]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = it.c0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+        if (row < R && col < C) {
+          const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
+          slot[o] = acc[i][j][v];
+        }
+      }
+    }
+}
+
+__global__ __launch_bounds__(GTH) void k_fwd_bfb(FwdArgs g) {
+  __shared__ BfRing rg;
+  __shared__ int s_work;
   for (;;) {
-    if (threadIdx.x == 0) s_work = pop_work<PH>(g);
+    if (threadIdx.x == 0) s_work = pop_work<1>(g);
     __syncthreads();
-    // uniform: the item's metadata then comes through scalar loads, which
-    // leave the vector-memory count (operand loads in flight) alone
-    const int wk = __builtin_amdgcn_readfirstlane((int)s_work);
+    const int wk = __builtin_amdgcn_readfirstlane(s_work);
     __syncthreads();
     if (wk < 0) break;
-    f4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
-    if (PH == 0) {
-      // all tiles of task wk as one stream of K steps, row strips in turn
-      const int t = (int)wk;
-      Mat A, B;
-      int K;
-      double alpha;
-      seg_ops<TNS_BF16X3, 0>(g, t, A, B, K, &alpha);
-      const int rows = A.rows, cols = B.rows, ld = ld8(cols);
-      const int nk = (K + BBK - 1) / BBK, ntc = (cols + GN - 1) / GN;
-      const int nsteps = ((rows + GM - 1) / GM) * ntc * nk;
-      auto issue = [&](int ls) {
-        const int tile = ls / nk, j = ls - tile * nk;
-        bf_issue(rg, ls % BNS, A, B, (tile / ntc) * GM, (tile % ntc) * GN, j * BBK, K, g.zero);
-      };
-      for (int ls = 0; ls < BNS - 1 && ls < nsteps; ++ls) issue(ls);
-      const float alf = (float)alpha;
-      uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[t]);
-      for (int s = 0; s < nsteps; ++s) {
-        ring_sync(min(nsteps, s + BNS - 1) - 1 - s);
-        if (s + BNS - 1 < nsteps) issue(s + BNS - 1);
-        bf_mma(rg, s % BNS, acc);
-        if ((s + 1) % nk == 0) {
-          const int tile = s / nk, r0 = (tile / ntc) * GM, c0 = (tile % ntc) * GN;
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int col = c0 + wn * 64 + j * 16 + l16;
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
-                if (row < rows && col < ld) {
-                  const float x = alf * acc[i][j][v];
-                  const uint16_t h = f32_to_bf16_rne(x);
-                  const int64_t o = (int64_t)row * ld + col;
-                  Th[o] = h;
-                  Th[g.T_lo + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
-                }
-              }
-              acc[i][j] = vzero<f4>();
-            }
-        }
-      }
-    } else {
-      const Item it = load_item(g.items + wk);
-      int ls = it.tb, lj = 0, lK, issued = 0;
-      bool ldone = false;
-      Mat LA, LB;
-      seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
-      auto issue_next = [&]() {
-        bf_issue(rg, issued % BNS, LA, LB, it.p0, it.c0, lj * BBK, lK, g.zero);
-        ++issued;
-        if (++lj * BBK >= lK) {
-          lj = 0;
-          if (++ls < it.te) seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
-          else ldone = true;
-        }
-      };
-      while (!ldone && issued < BNS - 1) issue_next();
-      for (int s = 0; s < issued; ++s) {
-        ring_sync(issued - 1 - s);
-        if (!ldone) issue_next();
-        bf_mma(rg, s % BNS, acc);
-      }
-      const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
-      float *slot = reinterpret_cast<float *>(g.partial) + cld(&g.slot_off[it.slot]);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int col = it.c0 + wn * 64 + j * 16 + l16;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
-            if (row < R && col < C) {
-              const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
-              slot[o] = acc[i][j][v];
-            }
-          }
-        }
-    }
+    bf_item_b(g, rg, wk);
   }
 }
+
 
 // Phase A of the BF16x3 path.  A work item is a block of ABT consecutive
 // tasks; all tiles of all its tasks form one stream of K steps, so the ring
@@ -676,11 +644,80 @@ __device__ inline void bf_mma_t(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
 
 typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
 
+// Phase A of the BF16x3 path: block b of ABT tasks as one stream.
+__device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  const int t_end = (int)min((int64_t)(b + 1) * ABT, g.ntasks);
+  // load cursor: (task, tile row, tile column, k) in stream order
+  int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0;
+  bool ldone = false;
+  Mat LA, LB;
+  seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+  auto issue_next = [&]() {
+    bf_issue(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
+    ++issued;
+    if ((lk0 += BBK) < lK) return;
+    lk0 = 0;
+    if ((lc0 += GN) < LB.rows) return;
+    lc0 = 0;
+    if ((lr0 += GM) < LA.rows) return;
+    lr0 = 0;
+    if (++lt < t_end) seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+    else ldone = true;
+  };
+  while (!ldone && issued < BNS - 1) issue_next();
+  // compute cursor, BNS - 1 steps behind
+  int ct = b * ABT, cr0 = 0, cc0 = 0, ck0 = 0, cK;
+  double alpha;
+  Mat CA, CB;
+  seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
+  for (int s = 0; s < issued; ++s) {
+    ring_sync(issued - 1 - s);
+    if (!ldone) issue_next();
+    bf_mma_t(rg, s % BNS, acc);
+    if ((ck0 += BBK) < cK) continue;
+    // tile (cr0, cc0) of task ct complete: T = alpha * acc as BF16 halves
+    {
+      const int rows = CA.rows, ld = ld8(CB.rows);
+      uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[ct]);
+      const float alf = (float)alpha;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = cr0 + wm * 64 + j * 16 + l16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int col = cc0 + wn * 64 + i * 16 + 4 * lg;
+          if (row < rows && col < ld) {
+            const f4 x = alf * acc[i][j];
+            const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+            const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                            (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+            const int64_t o = (int64_t)row * ld + col;
+            *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
+            *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+          }
+          acc[i][j] = vzero<f4>();
+        }
+      }
+    }
+    ck0 = 0;
+    if ((cc0 += GN) < CB.rows) continue;
+    cc0 = 0;
+    if ((cr0 += GM) < CA.rows) continue;
+    cr0 = 0;
+    if (++ct < t_end) seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+  }
+}
+
 __global__ __launch_bounds__(GTH) void k_fwd_bfa(FwdArgs g) {
   __shared__ BfRing rg;
   __shared__ int s_work;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
   const int64_t nblk = (g.ntasks + ABT - 1) / ABT;
   for (;;) {
     if (threadIdx.x == 0) s_work = pop_block(g, nblk);
@@ -688,71 +725,7 @@ __global__ __launch_bounds__(GTH) void k_fwd_bfa(FwdArgs g) {
     const int b = __builtin_amdgcn_readfirstlane(s_work);
     __syncthreads();
     if (b < 0) break;
-    const int t_end = (int)min((int64_t)(b + 1) * ABT, g.ntasks);
-    // load cursor: (task, tile row, tile column, k) in stream order
-    int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0;
-    bool ldone = false;
-    Mat LA, LB;
-    seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
-    auto issue_next = [&]() {
-      bf_issue(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
-      ++issued;
-      if ((lk0 += BBK) < lK) return;
-      lk0 = 0;
-      if ((lc0 += GN) < LB.rows) return;
-      lc0 = 0;
-      if ((lr0 += GM) < LA.rows) return;
-      lr0 = 0;
-      if (++lt < t_end) seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
-      else ldone = true;
-    };
-    while (!ldone && issued < BNS - 1) issue_next();
-    // compute cursor, BNS - 1 steps behind
-    int ct = b * ABT, cr0 = 0, cc0 = 0, ck0 = 0, cK;
-    double alpha;
-    Mat CA, CB;
-    seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
-    f4 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
-    for (int s = 0; s < issued; ++s) {
-      ring_sync(issued - 1 - s);
-      if (!ldone) issue_next();
-      bf_mma_t(rg, s % BNS, acc);
-      if ((ck0 += BBK) < cK) continue;
-      // tile (cr0, cc0) of task ct complete: T = alpha * acc as BF16 halves
-      {
-        const int rows = CA.rows, ld = ld8(CB.rows);
-        uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[ct]);
-        const float alf = (float)alpha;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int row = cr0 + wm * 64 + j * 16 + l16;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int col = cc0 + wn * 64 + i * 16 + 4 * lg;
-            if (row < rows && col < ld) {
-              const f4 x = alf * acc[i][j];
-              const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
-              const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
-                              (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
-              const int64_t o = (int64_t)row * ld + col;
-              *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
-              *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
-            }
-            acc[i][j] = vzero<f4>();
-          }
-        }
-      }
-      ck0 = 0;
-      if ((cc0 += GN) < CB.rows) continue;
-      cc0 = 0;
-      if ((cr0 += GM) < CA.rows) continue;
-      cr0 = 0;
-      if (++ct < t_end) seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
-    }
+    bf_item_a(g, rg, b);
   }
 }
 
@@ -768,11 +741,10 @@ __global__ void k_ident_bf(uint16_t *p, int n, int ld, int64_t lo) {
 // Sector s (m x n) to pp (m x ld8(n)) and, transposed, to pt (n x ld8(m));
 // BF16X3 writes high halves and, `lo` elements further, low halves.
 template <class In, int P>
-__global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, const int32_t *psi_sec,
-                          const int32_t *dimL, const int32_t *dimR, const int64_t *pp_off, const int64_t *pt_off,
-                          void *pp, void *pt, int64_t pp_lo, int64_t pt_lo) {
+__device__ inline void pad_sector(int s, const In *__restrict__ psi, const int64_t *psi_off, const int32_t *psi_sec,
+                                  const int32_t *dimL, const int32_t *dimR, const int64_t *pp_off,
+                                  const int64_t *pt_off, void *pp, void *pt, int64_t pp_lo, int64_t pt_lo) {
   typedef typename FP<P>::E E;
-  const int s = blockIdx.x;
   const int m = dimL[psi_sec[4 * s]], n = dimR[psi_sec[4 * s + 3]];
   const int lm = ld8(m), ln = ld8(n);
   const In *A = psi + psi_off[s];
@@ -781,8 +753,8 @@ __global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, co
   // padded rows (zeros beyond n), then padded transposed rows (zeros beyond m)
   for (int64_t e = e0; e < (int64_t)m * ln; e += step) {
     const int i = (int)(e / ln), j = (int)(e % ln);
-    const float v = j < n ? (float)A[(int64_t)i * n + j] : 0.f;
     if constexpr (P == TNS_BF16X3) {
+      const float v = j < n ? (float)A[(int64_t)i * n + j] : 0.f;
       const uint16_t h = f32_to_bf16_rne(v);
       P0[e] = h;
       P0[pp_lo + e] = f32_to_bf16_rne(v - bf16_to_f32(h));
@@ -792,8 +764,8 @@ __global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, co
   }
   for (int64_t e = e0; e < (int64_t)n * lm; e += step) {
     const int j = (int)(e / lm), i = (int)(e % lm);
-    const float v = i < m ? (float)A[(int64_t)i * n + j] : 0.f;
     if constexpr (P == TNS_BF16X3) {
+      const float v = i < m ? (float)A[(int64_t)i * n + j] : 0.f;
       const uint16_t h = f32_to_bf16_rne(v);
       P1[e] = h;
       P1[pt_lo + e] = f32_to_bf16_rne(v - bf16_to_f32(h));
@@ -801,6 +773,168 @@ __global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, co
       P1[e] = i < m ? (E)A[(int64_t)i * n + j] : E(0);
     }
   }
+}
+
+template <class In, int P>
+__global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, const int32_t *psi_sec,
+                          const int32_t *dimL, const int32_t *dimR, const int64_t *pp_off, const int64_t *pt_off,
+                          void *pp, void *pt, int64_t pp_lo, int64_t pt_lo) {
+  pad_sector<In, P>(blockIdx.x, psi, psi_off, psi_sec, dimL, dimR, pp_off, pt_off, pp, pt, pp_lo, pt_lo);
+}
+
+// ============================================================================
+// Many independent products in one launch per phase.  Instance i's arguments
+// live in a device table; every XCD queue of a phase is the concatenation of
+// the instances' own queue contents (instances ordered by descending cost);
+// a workgroup finds (instance, local work) by binary search over the
+// per-queue prefix sums and reads that instance's arguments by scalar loads.
+// ============================================================================
+struct InstArgs {
+  FwdArgs g;
+  const void *psi;  // input: double (F64) or float
+  void *sigma;
+  const int64_t *psi_off, *grp_chunk_base;
+  int64_t psi_dim;
+  int32_t nS, beta;
+};
+static_assert(sizeof(FwdArgs) % 8 == 0 && sizeof(InstArgs) % 8 == 0, "8-byte words");
+
+struct BatchArgs {
+  const InstArgs *tab;
+  int64_t *cum;     // [2][NQ_MAX][n + 1] work prefix per phase and queue
+  int32_t *queue;   // [0, 8) phase A, [8, 16) phase B
+  int32_t n, nq, blocks;  // blocks: phase-A unit is a block of ABT tasks (BF16X3)
+  int32_t pad_;
+};
+
+template <class T>
+__device__ inline T load_words(const T *p) {
+  T v;
+  const uint64_t *src = reinterpret_cast<const uint64_t *>(p);
+  uint64_t *dst = reinterpret_cast<uint64_t *>(&v);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 8); ++i) dst[i] = cld(src + i);
+  return v;
+}
+
+__device__ inline int64_t blk_count(int64_t ntasks, int nq, int q) {
+  const int64_t nblk = (ntasks + ABT - 1) / ABT;
+  return nblk > q ? (nblk - 1 - q) / nq + 1 : 0;
+}
+
+// Work of instance i on queue q of phase ph (16 threads: one per (ph, q)).
+__global__ void k_batch_cum(BatchArgs b) {
+  const int ph = threadIdx.x / NQ_MAX, q = threadIdx.x % NQ_MAX;
+  if (ph >= 2) return;
+  int64_t *c = b.cum + ((int64_t)ph * NQ_MAX + q) * (b.n + 1);
+  int64_t run = 0;
+  for (int i = 0; i < b.n; ++i) {
+    c[i] = run;
+    if (q < b.nq) {
+      const FwdArgs &g = b.tab[i].g;
+      if (ph == 0) run += b.blocks ? blk_count(g.ntasks, b.nq, q) : qa_count(g.ntasks, b.nq, q);
+      else run += g.qbase[q + 1] - g.qbase[q];
+    }
+  }
+  c[b.n] = run;
+}
+
+// Thread 0: next (instance, work id) of phase ph, own XCD queue first.
+__device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk) {
+  const int home = blockIdx.x % b.nq;
+  for (int k = 0; k < b.nq; ++k) {
+    const int q = home + k < b.nq ? home + k : home + k - b.nq;
+    const int64_t *c = b.cum + ((int64_t)ph * NQ_MAX + q) * (b.n + 1);
+    const int64_t tot = c[b.n];
+    if (tot <= 0) continue;
+    const int j = atomicAdd(b.queue + 8 * ph + q, 1);
+    if (j >= tot) continue;
+    int lo = 0, hi = b.n - 1;  // last instance with c[i] <= j
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (c[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    const int64_t loc = j - c[lo];
+    *inst = lo;
+    if (ph == 1) *wk = (int)(b.tab[lo].g.qbase[q] + loc);
+    else *wk = b.blocks ? (int)(loc * b.nq + q) : (int)qa_task(b.nq, q, loc);
+    return;
+  }
+  *inst = -1;
+  *wk = -1;
+}
+
+template <int P, int PH>
+__global__ __launch_bounds__(GTH) void k_fwd_batch(BatchArgs b) {
+  __shared__ FwdSmem<P> sm;
+  __shared__ int s_w[2];
+  for (;;) {
+    if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
+    __syncthreads();
+    const int inst = __builtin_amdgcn_readfirstlane(s_w[0]), wk = __builtin_amdgcn_readfirstlane(s_w[1]);
+    __syncthreads();
+    if (inst < 0) break;
+    const FwdArgs g = load_words(&b.tab[inst].g);
+    fwd_item<P, PH>(g, sm, wk);
+  }
+}
+
+template <int PH>
+__global__ __launch_bounds__(GTH) void k_fwd_bf_batch(BatchArgs b) {
+  __shared__ BfRing rg;
+  __shared__ int s_w[2];
+  for (;;) {
+    if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
+    __syncthreads();
+    const int inst = __builtin_amdgcn_readfirstlane(s_w[0]), wk = __builtin_amdgcn_readfirstlane(s_w[1]);
+    __syncthreads();
+    if (inst < 0) break;
+    const FwdArgs g = load_words(&b.tab[inst].g);
+    if (PH == 0) bf_item_a(g, rg, wk);
+    else bf_item_b(g, rg, wk);
+  }
+}
+
+template <class In, int P>
+__global__ void k_pad_psi_batch(const InstArgs *tab) {
+  const InstArgs &a = tab[blockIdx.z];
+  if ((int)blockIdx.x >= a.nS) return;
+  pad_sector<In, P>(blockIdx.x, reinterpret_cast<const In *>(a.psi), a.psi_off, a.g.psi_sec, a.g.dimL, a.g.dimR,
+                    a.g.pp_off, a.g.pt_off, const_cast<void *>(a.g.pp), const_cast<void *>(a.g.pt), a.g.pp_lo,
+                    a.g.pt_lo);
+}
+
+// sigma_i (+)= the sum of instance i's partial slots, as k_epilogue_psi.
+template <class T>
+__global__ void k_epilogue_batch(const InstArgs *tab) {
+  const InstArgs &a = tab[blockIdx.y];
+  const int64_t *psi_off = a.psi_off, *cb = a.grp_chunk_base, *slot_off = a.g.slot_off;
+  const T *part = reinterpret_cast<const T *>(a.g.partial);
+  T *out = reinterpret_cast<T *>(a.sigma);
+  const int nS = a.nS, beta = a.beta;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.psi_dim;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nS;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (psi_off[mid] <= e) lo = mid; else hi = mid;
+    }
+    const int64_t loc = e - psi_off[lo];
+    double acc = beta ? (double)out[e] : 0.0;
+    const int64_t c0 = cb[2 * lo], c1 = cb[2 * lo + 2];
+    for (int64_t c = c0; c < c1; ++c) acc += (double)part[slot_off[c] + loc];
+    out[e] = (T)acc;
+  }
+}
+
+constexpr int ARGS_PER_PUT = 3500 / (int)sizeof(InstArgs);
+struct PutArgs {
+  InstArgs a[ARGS_PER_PUT];
+  int32_t base, n;
+};
+static_assert(ARGS_PER_PUT >= 1 && sizeof(PutArgs) <= 4000, "argument chunk fits the kernel argument segment");
+__global__ void k_put_args(PutArgs c, InstArgs *tab) {
+  if ((int)threadIdx.x < c.n) tab[c.base + threadIdx.x] = c.a[threadIdx.x];
 }
 
 // --- host side --------------------------------------------------------------------------
@@ -842,13 +976,13 @@ static int grid_of(K kern, int n_cu) {
   return per * n_cu;
 }
 
-template <int P, class In>
-static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void *sigma, int beta, char *w,
-                             hipStream_t st, const hipEvent_t *ev) {
+// Arguments of one product whose workspace region (layout of fwd_workspace)
+// starts at w.
+template <int P>
+static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   typedef typename FP<P>::Acc Acc;
   const Sched &S = p.fwd;
   const tns_prec prec = (tns_prec)P;
-  int32_t *queue = reinterpret_cast<int32_t *>(w);
   char *c = w + 256;
   void *part = c;
   c += align_up((size_t)std::max<int64_t>(S.partial_elems, 1) * sizeof(Acc), 256);
@@ -859,7 +993,6 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   void *pt = c;
   c += region(p.pt_elems, prec);
   void *id = c;
-
   FwdArgs g;
   memset(&g, 0, sizeof(g));
   g.tasks = p.tasks; g.ntasks = p.ntasks;
@@ -871,17 +1004,25 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   g.T = T; g.T_lo = lo_of(p.t_elems); g.t_off = p.t_off;
   g.items = S.items; g.nitems = S.nitems; g.idx = S.idx; g.grp_rows = S.grp_rows; g.grp_cols = S.grp_cols;
   g.slot_off = S.slot_off; g.qbase = S.qbase; g.partial = part;
-  g.queue = queue; g.nq = S.nq;
+  g.queue = reinterpret_cast<int32_t *>(w); g.nq = S.nq;
   g.zero = w + 64;
   g.ident = id; g.ident_lo = lo_of(ident_elems(p)); g.ident_ld = ld8(p.maxdim);
+  return g;
+}
 
-  hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, queue);
+template <int P, class In>
+static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void *sigma, int beta, char *w,
+                             hipStream_t st, const hipEvent_t *ev) {
+  const Sched &S = p.fwd;
+  const FwdArgs g = fwd_args<P>(p, ops, w);
+  hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, g.queue);
   if (P == TNS_BF16X3)
-    hipLaunchKernelGGL(k_ident_bf, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, (uint16_t *)id, p.maxdim,
+    hipLaunchKernelGGL(k_ident_bf, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, (uint16_t *)g.ident, p.maxdim,
                        ld8(p.maxdim), g.ident_lo);
   if (p.nS > 0)
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
-                       p.dimR, p.pp_off, p.pt_off, pp, pt, g.pp_lo, g.pt_lo);
+                       p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt), g.pp_lo,
+                       g.pt_lo);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (p.ntasks > 0) {
     if (P == TNS_BF16X3)
@@ -892,12 +1033,117 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
   if (p.ntasks > 0 && S.nitems > 0) {
     if (P == TNS_BF16X3)
-      hipLaunchKernelGGL(k_fwd_bf<1>, dim3(grid_of(k_fwd_bf<1>, p.n_cu)), dim3(GTH), 0, st, g);
+      hipLaunchKernelGGL(k_fwd_bfb, dim3(grid_of(k_fwd_bfb, p.n_cu)), dim3(GTH), 0, st, g);
     else
       hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
   }
   if (ev) TNS_HIP(hipEventRecord(ev[2], st));
-  return launch_epilogue_psi(p, prec == TNS_F64, part, sigma, beta, st);
+  return launch_epilogue_psi(p, P == TNS_F64, g.partial, sigma, beta, st);
+}
+
+// --- batched products -------------------------------------------------------------------
+static int max_maxdim(const tns_tasklist *const *tls, int n) {
+  int md = 1;
+  for (int i = 0; i < n; ++i) md = std::max(md, plan_of(tls[i]).maxdim);
+  return md;
+}
+
+// [queue counters, zero bytes | argument table | prefix sums | (BF16X3) shared
+// identity | one forward workspace per instance]
+static size_t batch_bytes(const tns_tasklist *const *tls, int n, tns_prec prec) {
+  size_t b = 256 + align_up((size_t)n * sizeof(InstArgs), 256) + align_up((size_t)2 * NQ_MAX * (n + 1) * 8, 256);
+  const int md = max_maxdim(tls, n);
+  if (prec == TNS_BF16X3) b += region((int64_t)md * ld8(md), prec);
+  for (int i = 0; i < n; ++i) b += fwd_workspace(plan_of(tls[i]), prec);
+  return b;
+}
+
+template <int P>
+static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void *const *ops,
+                               const void *const *psi, void *const *sigma, int beta, char *w, hipStream_t st,
+                               const hipEvent_t *ev) {
+  typedef typename FP<P>::Acc Acc;
+  const tns_prec prec = (tns_prec)P;
+  int32_t *queue = reinterpret_cast<int32_t *>(w);
+  char *c = w + 256;
+  InstArgs *tab = reinterpret_cast<InstArgs *>(c);
+  c += align_up((size_t)n * sizeof(InstArgs), 256);
+  int64_t *cum = reinterpret_cast<int64_t *>(c);
+  c += align_up((size_t)2 * NQ_MAX * (n + 1) * 8, 256);
+  const int md = max_maxdim(tls, n);
+  const int64_t id_elems = (int64_t)md * ld8(md);
+  void *ident = c;
+  if (P == TNS_BF16X3) c += region(id_elems, prec);
+  // instances by descending cost: the big ones start first, the small ones fill the tail
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+    return plan_of(tls[x]).fwd.total_cost > plan_of(tls[y]).fwd.total_cost;
+  });
+  std::vector<char *> region_of(n);
+  for (int i = 0; i < n; ++i) {
+    region_of[i] = c;
+    c += fwd_workspace(plan_of(tls[i]), prec);
+  }
+  std::vector<InstArgs> args(n);
+  int max_nS = 1, n_cu = 1, any_tasks = 0, any_items = 0;
+  int64_t max_dim = 1;
+  for (int k = 0; k < n; ++k) {
+    const int i = perm[k];
+    const Plan &p = plan_of(tls[i]);
+    InstArgs &a = args[k];
+    memset(&a, 0, sizeof(a));
+    a.g = fwd_args<P>(p, ops[i], region_of[i]);
+    a.g.queue = queue;
+    a.g.zero = w + 64;
+    a.g.ident = ident; a.g.ident_lo = lo_of(id_elems); a.g.ident_ld = ld8(md);
+    a.psi = psi[i]; a.sigma = sigma[i];
+    a.psi_off = p.psi_off; a.grp_chunk_base = p.fwd.grp_chunk_base;
+    a.psi_dim = p.psi_dim; a.nS = p.nS; a.beta = beta;
+    max_nS = std::max(max_nS, p.nS);
+    max_dim = std::max(max_dim, p.psi_dim);
+    n_cu = std::max(n_cu, p.n_cu);
+    any_tasks |= p.ntasks > 0;
+    any_items |= p.fwd.nitems > 0;
+  }
+  BatchArgs b;
+  memset(&b, 0, sizeof(b));
+  b.tab = tab; b.cum = cum; b.queue = queue; b.n = n; b.nq = plan_of(tls[0]).fwd.nq;
+  b.blocks = P == TNS_BF16X3;
+
+  hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, queue);
+  for (int k0 = 0; k0 < n; k0 += ARGS_PER_PUT) {
+    PutArgs pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.base = k0;
+    pa.n = std::min(ARGS_PER_PUT, n - k0);
+    for (int k = 0; k < pa.n; ++k) pa.a[k] = args[k0 + k];
+    hipLaunchKernelGGL(k_put_args, dim3(1), dim3(64), 0, st, pa, tab);
+  }
+  hipLaunchKernelGGL(k_batch_cum, dim3(1), dim3(2 * NQ_MAX), 0, st, b);
+  if (P == TNS_BF16X3)
+    hipLaunchKernelGGL(k_ident_bf, dim3(nblocks(id_elems)), dim3(256), 0, st, (uint16_t *)ident, md, ld8(md),
+                       lo_of(id_elems));
+  typedef typename std::conditional<P == TNS_F64, double, float>::type In;
+  hipLaunchKernelGGL((k_pad_psi_batch<In, P>), dim3(max_nS, 8, n), dim3(256), 0, st, tab);
+  if (ev) TNS_HIP(hipEventRecord(ev[0], st));
+  if (any_tasks) {
+    if (P == TNS_BF16X3)
+      hipLaunchKernelGGL(k_fwd_bf_batch<0>, dim3(grid_of(k_fwd_bf_batch<0>, n_cu)), dim3(GTH), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);
+  }
+  if (ev) TNS_HIP(hipEventRecord(ev[1], st));
+  if (any_tasks && any_items) {
+    if (P == TNS_BF16X3)
+      hipLaunchKernelGGL(k_fwd_bf_batch<1>, dim3(grid_of(k_fwd_bf_batch<1>, n_cu)), dim3(GTH), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_fwd_batch<P, 1>), dim3(grid_of(k_fwd_batch<P, 1>, n_cu)), dim3(GTH), 0, st, b);
+  }
+  if (ev) TNS_HIP(hipEventRecord(ev[2], st));
+  const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_dim + 255) / 256);
+  hipLaunchKernelGGL(k_epilogue_batch<Acc>, dim3(gx, n), dim3(256), 0, st, tab);
+  return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
 }
 
 tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
@@ -917,3 +1163,34 @@ tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *
 }
 
 }  // namespace tns
+
+using namespace tns;
+
+static bool batch_ok(const tns_tasklist *const *tls, int n, tns_prec prec) {
+  if (!tls || n <= 0) return false;
+  if (prec != TNS_F64 && prec != TNS_F32 && prec != TNS_BF16X3) return false;
+  for (int i = 0; i < n; ++i)
+    if (!tls[i] || plan_of(tls[i]).fwd.nq != plan_of(tls[0]).fwd.nq) return false;
+  return true;
+}
+
+extern "C" size_t tns_apply_batch_workspace_bytes(const tns_tasklist *const *tls, int n, tns_prec prec) {
+  return batch_ok(tls, n, prec) ? batch_bytes(tls, n, prec) : 0;
+}
+
+extern "C" tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n, tns_prec prec,
+                                           const void *const *op_vals, const void *const *psi, void *const *sigma,
+                                           double beta, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!batch_ok(tls, n, prec) || !op_vals || !psi || !sigma || !ws) return TNS_ERR_ARG;
+  if (beta != 0.0 && beta != 1.0) return TNS_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!op_vals[i] || !psi[i] || !sigma[i]) return TNS_ERR_ARG;
+  if (ws_bytes < batch_bytes(tls, n, prec)) return TNS_ERR_WORKSPACE;
+  hipEvent_t ev[3];
+  const bool timed = take_profile_events(ev);
+  char *w = reinterpret_cast<char *>(ws);
+  const int ib = beta != 0.0;
+  if (prec == TNS_F64) return batch_launch<TNS_F64>(tls, n, op_vals, psi, sigma, ib, w, st, timed ? ev : nullptr);
+  if (prec == TNS_F32) return batch_launch<TNS_F32>(tls, n, op_vals, psi, sigma, ib, w, st, timed ? ev : nullptr);
+  return batch_launch<TNS_BF16X3>(tls, n, op_vals, psi, sigma, ib, w, st, timed ? ev : nullptr);
+}

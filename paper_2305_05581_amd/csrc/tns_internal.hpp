@@ -178,6 +178,8 @@ tns_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
 // sigma (+)= sum of the forward partial slots of every sector (beta 0 or 1)
 tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *sigma, int beta, hipStream_t st);
 size_t fwd_workspace(const Plan &p, tns_prec prec);
+// events armed by tns_profile_events (then cleared); false when not armed
+bool take_profile_events(hipEvent_t ev[3]);
 // ev: null, or events recorded before phase A, between the phases and after phase B
 tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *psi, void *sigma, double beta,
                      void *ws, size_t ws_bytes, hipStream_t st, const hipEvent_t *ev);

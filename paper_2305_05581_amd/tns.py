@@ -96,6 +96,14 @@ def library(path=LIB_PATH):
     if hasattr(L, "tns_profile_events"):
         L.tns_profile_events.restype = None
         L.tns_profile_events.argtypes = [_P, _P, _P]
+    if hasattr(L, "tns_apply_heff_batch"):
+        L.tns_apply_batch_workspace_bytes.restype = sz
+        L.tns_apply_batch_workspace_bytes.argtypes = [ctypes.POINTER(ctypes.POINTER(TnsTasklist)), ctypes.c_int,
+                                                      ctypes.c_int]
+        L.tns_apply_heff_batch.restype = ctypes.c_int
+        L.tns_apply_heff_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(TnsTasklist)), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                           ctypes.c_double, _P, sz, _P]
     L.tns_status_string.restype = ctypes.c_char_p
     L.tns_status_string.argtypes = [ctypes.c_int]
     _lib = L
@@ -305,6 +313,51 @@ def _hip():
         _hiprt.hipEventElapsedTime.restype = ctypes.c_int
         _hiprt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), _P, _P]
     return _hiprt
+
+
+class HeffBatch:
+    """Many products in one launch per GEMM phase (``tns_apply_heff_batch``).
+
+    ``problems``: HeffProblem instances on one device.  ``apply(psis, prec,
+    outs)`` computes outs[i] = H_eff,i psis[i] for every instance."""
+
+    def __init__(self, problems):
+        if not problems:
+            raise ValueError("empty batch")
+        self.problems = list(problems)
+        self.device = self.problems[0].device
+        n = len(self.problems)
+        self._tls = (ctypes.POINTER(TnsTasklist) * n)(*[ctypes.pointer(h.tl) for h in self.problems])
+        self._ws = {}
+
+    def workspace(self, prec):
+        p = prec_id(prec)
+        if p not in self._ws:
+            nb = library().tns_apply_batch_workspace_bytes(self._tls, len(self.problems), p)
+            if nb == 0:
+                raise ValueError("invalid batch")
+            self._ws[p] = torch.empty(int(nb), dtype=torch.uint8, device=self.device)
+        return self._ws[p]
+
+    def apply(self, psis, prec="f32", outs=None, beta=0.0):
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        n = len(self.problems)
+        if len(psis) != n:
+            raise ValueError("one psi per instance")
+        if outs is None:
+            outs = [torch.empty(h.psi_dim, dtype=dt, device=self.device) for h in self.problems]
+            beta = 0.0
+        for h, x, o in zip(self.problems, psis, outs):
+            h._vec(x, dt, "psi")
+            h._vec(o, dt, "out")
+        ops = (_P * n)(*[_ptr(h.operands(p)) for h in self.problems])
+        xs = (_P * n)(*[_ptr(x) for x in psis])
+        ys = (_P * n)(*[_ptr(o) for o in outs])
+        ws = self.workspace(p)
+        _check(library().tns_apply_heff_batch(self._tls, n, p, ops, xs, ys, float(beta), _ptr(ws), ws.numel(),
+                                              _stream()), "tns_apply_heff_batch")
+        return outs
 
 
 class KernelTimer:
