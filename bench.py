@@ -201,6 +201,11 @@ def bench_batch(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps
 
+    tiles = Hs[0].tiles
+    if args.autotune:
+        t = time.time()
+        tiles = B.autotune(psis, prec)
+        log("autotuned tile table %08x (%.1f s)" % (tiles, time.time() - t))
     t_seq = timed(one_at_a_time, args.steps)
     log("one at a time: %.2f ms  %.2f TFLOP/s" % (t_seq * 1e3, flops / t_seq / 1e12))
     t_bat = timed(batched, args.steps)
@@ -221,7 +226,8 @@ def bench_batch(args):
         "config": {"workload": "batch64: %d instances, L ~ U{20..40}, N = L, 2Sz = L mod 2, D log-uniform "
                                "[256, 2048], sector mean sqrt(D), max 8 sqrt(D), K = L^2, seeds 4000+i"
                                % len(Hs),
-                   "flops_per_step": flops, "tasks": sum(H.ntasks for H in Hs)},
+                   "flops_per_step": flops, "tasks": sum(H.ntasks for H in Hs),
+                   "tile_table": "%08x" % tiles, "autotuned": bool(args.autotune)},
         "one_at_a_time": {"ms_per_step": round(t_seq * 1e3, 3), "tflops": round(flops / t_seq / 1e12, 3)},
         "batched_eager": {"ms_per_step": round(t_bat * 1e3, 3), "tflops": round(flops / t_bat / 1e12, 3)},
         "batched_graph": {"ms_per_step": round(t_graph * 1e3, 3), "tflops": round(flops / t_graph / 1e12, 3)},
@@ -240,6 +246,8 @@ def main():
     ap.add_argument("--config", default="d4096", choices=sorted(CONFIGS) + ["batch64"],
                     help="batch64: many uneven instances, one launch per phase vs one product at a time")
     ap.add_argument("--instances", type=int, default=64, help="batch64: number of instances")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's tile autotuner (per sector-size bucket) before timing")
     ap.add_argument("--no-davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-gflop", type=float, default=150.0, help="flops of the CPU oracle sample (GFLOP)")
@@ -304,6 +312,10 @@ def main():
         log("calibration copy: %d bytes" % (src.numel() * 4))
         del src, dst
 
+    if args.autotune:
+        t = time.time()
+        tab = H.autotune(psi64 if args.prec == "f64" else psi32, args.prec)
+        log("autotuned tile table %08x for %s (%.1f s)" % (tab, args.prec, time.time() - t))
     tasks_dev, ptr = H.tasks()
     flops_a, flops_b = phase_flops(P, tasks_dev)
     log("phase A %.3f TFLOP, phase B %.3f TFLOP (sum %.3f)" % (flops_a / 1e12, flops_b / 1e12,
@@ -456,7 +468,8 @@ def main():
                                   cfg["dmax"], P.nTerms, " + gapped diagonal" if cfg["gapped"] else "",
                                   cfg["seed"]),
                    "tasks": H.ntasks, "flops_per_step": flops, "psi_dim": P.psi_dim,
-                   "operator_GB_f64": round(P.op_vals.nbytes / 1e9, 2), "parallelism": "single GPU"},
+                   "operator_GB_f64": round(P.op_vals.nbytes / 1e9, 2), "parallelism": "single GPU",
+                   "tile_table": "%08x" % H.tiles, "autotuned": bool(args.autotune)},
         "pct_mfma_peak": round(head["pct_peak"], 2),
         "precisions": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in res.items()},

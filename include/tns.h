@@ -193,6 +193,31 @@ tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n, tns_prec 
                                 const void *const *op_vals, const void *const *psi, void *const *sigma,
                                 double beta, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Tile shapes of the two forward GEMM phases per sector-size bucket (level 3
+ * work decomposition, Alg. 2's batched products; the bucket choice is this
+ * library's).  `tiles` packs four bytes: byte b is the tile extent (32, 64 or
+ * 128 rows/columns) used along any output dimension d of bucket b =
+ * [d <= 32, d <= 64, d <= 128, d > 128].  Default 0x80804020 (32, 64, 128,
+ * 128).  tns_set_tiles rebuilds the forward work items on the device and
+ * synchronises the stream (no product may be in flight on the task list);
+ * workspaces and results do not depend on the table (the sums are taken in
+ * the same order).  TNS_ERR_ARG for an invalid table. */
+tns_status tns_set_tiles(tns_tasklist *tl, uint32_t tiles, hipStream_t stream);
+uint32_t tns_get_tiles(const tns_tasklist *tl);
+
+/* Autotuner of the tile table: coordinate descent over the four buckets
+ * (largest first), each candidate timed as the median of three products
+ * (tns_apply_heff, or tns_apply_heff_batch over all instances) with HIP
+ * events after a warm-up product.  Leaves the fastest table set (on every
+ * task list of a batch) and returns it in *tiles_out (nullable).  Arguments
+ * as for the product calls; sigma is overwritten.  Synchronous. */
+tns_status tns_autotune_tiles(tns_tasklist *tl, tns_prec prec, const void *op_vals, const void *psi,
+                              void *sigma, void *ws, size_t ws_bytes, uint32_t *tiles_out,
+                              hipStream_t stream);
+tns_status tns_autotune_tiles_batch(tns_tasklist *const *tls, int n, tns_prec prec,
+                                    const void *const *op_vals, const void *const *psi, void *const *sigma,
+                                    void *ws, size_t ws_bytes, uint32_t *tiles_out, hipStream_t stream);
+
 size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
 tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
                                    const void *psi, const void *grad_sigma, void *grad_psi,

@@ -86,6 +86,7 @@ struct FwdArgs {
   const void *ident;  // BF16X3: identity matrix maxdim x ld8(maxdim) (hi; lo `ident_lo` further)
   int64_t ident_lo;
   int32_t ident_ld;
+  uint32_t tiles;     // tile table (phase A picks a task's tile from its T dimensions)
 };
 
 // --- per-precision tile parameters ---------------------------------------------
@@ -119,125 +120,87 @@ template <int P> struct __attribute__((aligned(16))) FwdSmem {
   E b[2][NH][GN * FP<P>::LDK];
 };
 
-// --- operand loads -------------------------------------------------------------
-// Thread t stages vectors (row t / NV + j * RP, k-vector t % NV) of a
-// 128 x BK tile, j < NL.
+// --- register-staged path (FP64, FP32): operand loads -----------------------------
+// A tile has 32 NT rows (NT = 1, 2, 4 MFMA tiles per wave along it).  Thread t
+// stages the vectors (row t / NV + j * RP, k-vector t % NV), j < 32 NT / RP.
 template <int P> struct Stage {
   static constexpr int NV = FP<P>::BK / FP<P>::VEC;
   static constexpr int RP = GTH / NV;
   static constexpr int NL = GM / RP;
-  static constexpr int NH = P == TNS_BF16X3 ? 2 : 1;
-  typename FP<P>::V r[NH][NL];
+  typename FP<P>::V r[NL];
 };
 
-template <int P>
+template <int P, int NT>
 __device__ inline void stage_load(Stage<P> &s, const Mat &m, int r0, int k0, int K, const void *zero) {
   typedef typename FP<P>::E E;
   typedef typename FP<P>::V V;
-  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, NL = Stage<P>::NL, VEC = FP<P>::VEC;
+  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, VEC = FP<P>::VEC, NLX = 32 * NT / RP;
+  static_assert(NLX >= 1 && 32 * NT % RP == 0, "tile rows cover whole load passes");
   if (m.ident) return;
   int t = threadIdx.x;
   asm volatile("" : "+v"(t));
   const int kk = k0 + (t % NV) * VEC;
   const E *base = reinterpret_cast<const E *>(m.p);
 #pragma unroll
-  for (int j = 0; j < NL; ++j) {
+  for (int j = 0; j < NLX; ++j) {
     const int row = r0 + t / NV + j * RP;
     const bool in = row < m.rows && kk < K;
     const E *ad = in ? base + (int64_t)row * m.ld + kk : reinterpret_cast<const E *>(zero);
-    s.r[0][j] = *reinterpret_cast<const V *>(ad);
-    if constexpr (P == TNS_BF16X3) {
-      const E *al = in ? base + m.lo + (int64_t)row * m.ld + kk : reinterpret_cast<const E *>(zero);
-      s.r[1][j] = *reinterpret_cast<const V *>(al);
-    }
+    s.r[j] = *reinterpret_cast<const V *>(ad);
   }
 }
 
-template <int P>
-__device__ inline void stage_store(typename FP<P>::E (*lds)[GM * FP<P>::LDK], Stage<P> &s, const Mat &m, int r0,
-                                   int k0, int K) {
+template <int P, int NT>
+__device__ inline void stage_store(typename FP<P>::E *lds, Stage<P> &s, const Mat &m, int r0, int k0, int K) {
   typedef typename FP<P>::E E;
   typedef typename FP<P>::V V;
-  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, NL = Stage<P>::NL, VEC = FP<P>::VEC, LDK = FP<P>::LDK;
+  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, VEC = FP<P>::VEC, LDK = FP<P>::LDK, NLX = 32 * NT / RP;
   const int t = threadIdx.x;
   const int kv = (t % NV) * VEC, kk = k0 + kv;
 #pragma unroll
-  for (int j = 0; j < NL; ++j) {
+  for (int j = 0; j < NLX; ++j) {
     const int lrow = t / NV + j * RP, row = r0 + lrow;
-    V h, l;
+    V h;
     if (m.ident) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const bool one = row == kk + e && row < m.rows && kk + e < K;
-        if constexpr (P == TNS_BF16X3) {
-          h[e] = one ? (uint16_t)0x3f80 : (uint16_t)0;
-          l[e] = 0;
-        } else {
-          h[e] = one ? E(1) : E(0);
-        }
-      }
+      for (int e = 0; e < VEC; ++e) h[e] = (row == kk + e && row < m.rows && kk + e < K) ? E(1) : E(0);
     } else {
-      h = s.r[0][j];
-      if constexpr (P == TNS_BF16X3) l = s.r[1][j];
+      h = s.r[j];
       if (kk + VEC > K) {
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
-          if (kk + e >= K) {
-            h[e] = 0;
-            if constexpr (P == TNS_BF16X3) l[e] = 0;
-          }
+          if (kk + e >= K) h[e] = 0;
       }
     }
-    *reinterpret_cast<V *>(&lds[0][lrow * LDK + kv]) = h;
-    if constexpr (P == TNS_BF16X3) *reinterpret_cast<V *>(&lds[1][lrow * LDK + kv]) = l;
+    *reinterpret_cast<V *>(&lds[lrow * LDK + kv]) = h;
   }
 }
 
 // --- MFMA on one LDS stage ------------------------------------------------------
-// Wave tile 64 x 64 at (wm, wn); acc[ti][tj] is the 16 x 16 tile
-// (16 ti, 16 tj).  Lane group g = lane / 16 owns k in [g BK/4, (g+1) BK/4).
-template <int P>
+// Wave tile (16 TM) x (16 TN) at (wm, wn); acc[i][j] is the 16 x 16 tile
+// (16 i, 16 j) of it.  Lane group g = lane / 16 owns k in [g BK/4, (g+1) BK/4).
+template <int P, int TM, int TN>
 __device__ inline void stage_mma(const FwdSmem<P> &sm, int buf, typename FP<P>::A4 (&acc)[4][4]) {
-  constexpr int LDK = FP<P>::LDK, BK = FP<P>::BK;
+  typedef typename FP<P>::E E;
+  typedef typename FP<P>::V V;
+  constexpr int LDK = FP<P>::LDK, BK = FP<P>::BK, VEC = FP<P>::VEC, KG = BK / 4;  // k per lane group
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
-  if constexpr (P == TNS_BF16X3) {
-    u16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ra = (wm * 64 + i * 16 + l16) * LDK + g * 8, rb = (wn * 64 + i * 16 + l16) * LDK + g * 8;
-      ah[i] = *reinterpret_cast<const u16x8 *>(&sm.a[buf][0][ra]);
-      al[i] = *reinterpret_cast<const u16x8 *>(&sm.a[buf][1][ra]);
-      bh[i] = *reinterpret_cast<const u16x8 *>(&sm.b[buf][0][rb]);
-      bl[i] = *reinterpret_cast<const u16x8 *>(&sm.b[buf][1][rb]);
-    }
+  for (int h = 0; h < KG / VEC; ++h) {
+    V a[TM], b[TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
+      a[i] = *reinterpret_cast<const V *>(&sm.a[buf][0][(wm * 16 * TM + i * 16 + l16) * LDK + g * KG + h * VEC]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[i][j] = mfma_bf(al[i], bh[j], acc[i][j]);
-        acc[i][j] = mfma_bf(ah[i], bl[j], acc[i][j]);
-        acc[i][j] = mfma_bf(ah[i], bh[j], acc[i][j]);
-      }
-  } else {
-    typedef typename FP<P>::E E;
-    typedef typename FP<P>::V V;
-    constexpr int VEC = FP<P>::VEC, KG = BK / 4;  // k per lane group
+    for (int j = 0; j < TN; ++j)
+      b[j] = *reinterpret_cast<const V *>(&sm.b[buf][0][(wn * 16 * TN + j * 16 + l16) * LDK + g * KG + h * VEC]);
 #pragma unroll
-    for (int h = 0; h < KG / VEC; ++h) {
-      V a[4], b[4];
+    for (int e = 0; e < VEC; ++e)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = *reinterpret_cast<const V *>(&sm.a[buf][0][(wm * 64 + i * 16 + l16) * LDK + g * KG + h * VEC]);
-        b[i] = *reinterpret_cast<const V *>(&sm.b[buf][0][(wn * 64 + i * 16 + l16) * LDK + g * KG + h * VEC]);
-      }
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int e = 0; e < VEC; ++e)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mfma((E)a[i][e], (E)b[j][e], acc[i][j]);
-    }
+        for (int j = 0; j < TN; ++j) acc[i][j] = mfma((E)a[i][e], (E)b[j][e], acc[i][j]);
   }
 }
 
@@ -322,10 +285,10 @@ __device__ inline int pop_work(const FwdArgs &g) {
   return -1;
 }
 
-// --- the kernel -----------------------------------------------------------------------
-// One output tile: acc = sum over segments [sb, se) of A_seg B_seg^T on rows
-// [r0, r0+128) of A and [c0, c0+128) of B.
-template <int P, int PH>
+// --- the register-staged kernel ---------------------------------------------------------
+// One output tile of (32 TM) x (32 TN): acc = sum over segments [sb, se) of
+// A_seg B_seg^T on rows [r0, r0 + 32 TM) of A and [c0, c0 + 32 TN) of B.
+template <int P, int PH, int TM, int TN>
 __device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int se, int r0, int c0,
                                  typename FP<P>::A4 (&acc)[4][4]) {
   typedef typename FP<P>::A4 A4;
@@ -339,10 +302,10 @@ __device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int s
   int K;
   seg_ops<P, PH>(g, seg_task(sb), A, B, K, nullptr);
   Stage<P> sa, sb_;
-  stage_load<P>(sa, A, r0, 0, K, g.zero);
-  stage_load<P>(sb_, B, c0, 0, K, g.zero);
-  stage_store<P>(sm.a[0], sa, A, r0, 0, K);
-  stage_store<P>(sm.b[0], sb_, B, c0, 0, K);
+  stage_load<P, TM>(sa, A, r0, 0, K, g.zero);
+  stage_load<P, TN>(sb_, B, c0, 0, K, g.zero);
+  stage_store<P, TM>(sm.a[0][0], sa, A, r0, 0, K);
+  stage_store<P, TN>(sm.b[0][0], sb_, B, c0, 0, K);
   __syncthreads();
   int s = sb, k0 = 0, cur = 0;
   for (;;) {
@@ -355,13 +318,13 @@ __device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int s
     }
     const bool more = ns < se;
     if (more) {
-      stage_load<P>(sa, nA, r0, nk, nK, g.zero);
-      stage_load<P>(sb_, nB, c0, nk, nK, g.zero);
+      stage_load<P, TM>(sa, nA, r0, nk, nK, g.zero);
+      stage_load<P, TN>(sb_, nB, c0, nk, nK, g.zero);
     }
-    stage_mma<P>(sm, cur, acc);
+    stage_mma<P, TM, TN>(sm, cur, acc);
     if (more) {
-      stage_store<P>(sm.a[cur ^ 1], sa, nA, r0, nk, nK);
-      stage_store<P>(sm.b[cur ^ 1], sb_, nB, c0, nk, nK);
+      stage_store<P, TM>(sm.a[cur ^ 1][0], sa, nA, r0, nk, nK);
+      stage_store<P, TN>(sm.b[cur ^ 1][0], sb_, nB, c0, nk, nK);
     }
     __syncthreads();
     if (!more) break;
@@ -374,74 +337,103 @@ __device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int s
   }
 }
 
-// One work item of the register-staged path: phase A = all tiles of task
-// wk, phase B = item wk of the phase-B schedule.
-template <int P, int PH>
-__device__ inline void fwd_item(const FwdArgs &g, FwdSmem<P> &sm, int wk) {
+// Phase A, task t: every (32 TM) x (32 TN) tile of T_t, row strips in turn.
+template <int P, int TM, int TN>
+__device__ inline void phase_a_task(const FwdArgs &g, FwdSmem<P> &sm, int t) {
+  typedef typename FP<P>::A4 A4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  Mat A, B;
+  int K;
+  double alpha;
+  seg_ops<P, 0>(g, t, A, B, K, &alpha);
+  const int rows = A.rows, cols = B.rows, ld = ld8(cols);
+  typedef typename FP<P>::Acc Acc;
+  Acc *Tt = reinterpret_cast<Acc *>(g.T) + cld(&g.t_off[t]);
+  const Acc alf = (Acc)alpha;
+  A4 acc[4][4];
+  for (int r0 = 0; r0 < rows; r0 += 32 * TM)
+    for (int c0 = 0; c0 < cols; c0 += 32 * TN) {
+      tile_gemm<P, 0, TM, TN>(g, sm, t, t + 1, r0, c0, acc);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int col = c0 + wn * 16 * TN + j * 16 + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = r0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
+            if (row < rows && col < ld) Tt[(int64_t)row * ld + col] = alf * acc[i][j][v];
+          }
+        }
+    }
+}
+
+// Phase B, one item: its (32 TM) x (32 TN) output tile over its chunk of tasks.
+template <int P, int TM, int TN>
+__device__ inline void phase_b_item(const FwdArgs &g, FwdSmem<P> &sm, const Item &it, int mode) {
   typedef typename FP<P>::A4 A4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
   A4 acc[4][4];
-  if (PH == 0) {
-    // every tile of task wk, row strips in turn
-    const int t = (int)wk;
-    Mat A, B;
-    int K;
-    double alpha;
-    seg_ops<P, 0>(g, t, A, B, K, &alpha);
-    const int rows = A.rows, cols = B.rows, ld = ld8(cols);
-    for (int r0 = 0; r0 < rows; r0 += GM)
-      for (int c0 = 0; c0 < cols; c0 += GN) {
-        tile_gemm<P, 0>(g, sm, t, t + 1, r0, c0, acc);
-        const float alf = (float)alpha;
+  tile_gemm<P, 1, TM, TN>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
+  const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
+  typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int col = c0 + wn * 64 + j * 16 + l16;
+    for (int j = 0; j < TN; ++j) {
+      const int col = it.c0 + wn * 16 * TN + j * 16 + l16;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int row = r0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
-              if (row < rows && col < ld) {
-                const int64_t o = cld(&g.t_off[t]) + (int64_t)row * ld + col;
-                if constexpr (P == TNS_BF16X3) {
-                  const float x = alf * acc[i][j][v];
-                  const uint16_t h = f32_to_bf16_rne(x);
-                  reinterpret_cast<uint16_t *>(g.T)[o] = h;
-                  reinterpret_cast<uint16_t *>(g.T)[g.T_lo + o] = f32_to_bf16_rne(x - bf16_to_f32(h));
-                } else if constexpr (P == TNS_F32) {
-                  reinterpret_cast<float *>(g.T)[o] = alf * acc[i][j][v];
-                } else {
-                  reinterpret_cast<double *>(g.T)[o] = alpha * acc[i][j][v];
-                }
-              }
-            }
-          }
-      }
-  } else {
-    const Item it = load_item(g.items + wk);
-    tile_gemm<P, 1>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
-    const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
-    typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int col = it.c0 + wn * 64 + j * 16 + l16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
-          if (row < R && col < C) {
-            const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
-            slot[o] = acc[i][j][v];
-          }
+      for (int v = 0; v < 4; ++v) {
+        const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
+        if (row < R && col < C) {
+          const int64_t o = mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
+          slot[o] = acc[i][j][v];
         }
       }
+    }
+}
+
+// Runs F<TM, TN> for tile extents (32 tm) x (32 tn), tm, tn in {1, 2, 4}.
+#define TNS_TILE_SWITCH(tm, tn, CALL)                  \
+  switch ((tm) * 8 + (tn)) {                             \
+    case 9: CALL(1, 1); break;                           \
+    case 10: CALL(1, 2); break;                          \
+    case 12: CALL(1, 4); break;                          \
+    case 17: CALL(2, 1); break;                          \
+    case 18: CALL(2, 2); break;                          \
+    case 20: CALL(2, 4); break;                          \
+    case 33: CALL(4, 1); break;                          \
+    case 34: CALL(4, 2); break;                          \
+    default: CALL(4, 4); break;                          \
+  }
+
+// One work item of the register-staged path: phase A = all tiles of task
+// wk, phase B = item wk of the phase-B schedule.
+template <int P, int PH>
+__device__ inline void fwd_item(const FwdArgs &g, FwdSmem<P> &sm, int wk) {
+  if (PH == 0) {
+    const tns_task *tp = g.tasks + wk;
+    const int out = cld(&tp->out), in = cld(&tp->in), order = cld(&tp->order);
+    const int rows = order == 0 ? cld(&g.dimL[cld(&g.psi_sec[4 * out])]) : cld(&g.dimR[cld(&g.psi_sec[4 * out + 3])]);
+    const int cols = order == 0 ? cld(&g.dimR[cld(&g.psi_sec[4 * in + 3])]) : cld(&g.dimL[cld(&g.psi_sec[4 * in])]);
+    const int tm = tile_ext(g.tiles, rows) / 32, tn = tile_ext(g.tiles, cols) / 32;
+#define TNS_CALL_A(a, b) phase_a_task<P, a, b>(g, sm, wk)
+    TNS_TILE_SWITCH(tm, tn, TNS_CALL_A)
+#undef TNS_CALL_A
+  } else {
+    const Item it = load_item(g.items + wk);
+    const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
+#define TNS_CALL_B(a, b) phase_b_item<P, a, b>(g, sm, it, mode)
+    TNS_TILE_SWITCH(tm, tn, TNS_CALL_B)
+#undef TNS_CALL_B
   }
 }
 
+// FP32: two workgroups per CU (the register budget of 256 per lane)
 template <int P, int PH>
-__global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
+__global__ __launch_bounds__(GTH, P == TNS_F32 ? 2 : 1) void k_fwd(FwdArgs g) {
   __shared__ FwdSmem<P> sm;
   __shared__ int s_work;
   for (;;) {
@@ -466,6 +458,7 @@ __global__ __launch_bounds__(GTH) void k_fwd(FwdArgs g) {
 // count wait and one barrier.  Out-of-range rows and whole k-vectors beyond
 // K read the zero region; the library's own operands (T, padded psi, the
 // identity) are zero beyond K, so the k-tail of an operator row meets zeros.
+typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
 constexpr int BNS = 4, BBK = 32;
 constexpr int BLOADS = 8;  // global_load_lds per wave and stage
 __device__ inline int bswz(int r) { return (r >> 1) & 3; }
@@ -515,22 +508,28 @@ __device__ inline void bf_issue(BfRing &rg, int buf, const Mat &A, const Mat &B,
   }
 }
 
+// MFMA on one ring stage for a (32 TM) x (32 TN) tile: wave (wm, wn) owns rows
+// chunks wm TM + i and column chunks wn TN + j.
+template <int TM, int TN>
 __device__ inline void bf_mma(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
   const int off = (l16 * 4 + (g ^ bswz(l16))) * 8;
-  u16x8 ah[4], al[4], bh[4], bl[4];
+  u16x8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ah[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * 4 + i) * 512 + off]);
-    al[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * 4 + i) * 512 + off]);
-    bh[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * 4 + i) * 512 + off]);
-    bl[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * 4 + i) * 512 + off]);
+  for (int i = 0; i < TM; ++i) {
+    ah[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * TM + i) * 512 + off]);
+    al[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * TM + i) * 512 + off]);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int j = 0; j < TN; ++j) {
+    bh[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * TN + j) * 512 + off]);
+    bl[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * TN + j) * 512 + off]);
+  }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
       acc[i][j] = mfma_bf(al[i], bh[j], acc[i][j]);
       acc[i][j] = mfma_bf(ah[i], bl[j], acc[i][j]);
       acc[i][j] = mfma_bf(ah[i], bh[j], acc[i][j]);
@@ -539,7 +538,8 @@ __device__ inline void bf_mma(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
 
 // Phase B of the BF16x3 path: one item (output tile, chunk of tasks), the
 // tasks' K steps streamed through the ring.
-__device__ inline void bf_item_b(const FwdArgs &g, BfRing &rg, int wk) {
+template <int TM, int TN>
+__device__ inline void bf_item_b_t(const FwdArgs &g, BfRing &rg, const Item &it, int mode) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
   f4 acc[4][4];
@@ -547,7 +547,6 @@ __device__ inline void bf_item_b(const FwdArgs &g, BfRing &rg, int wk) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
-  const Item it = load_item(g.items + wk);
   int ls = it.tb, lj = 0, lK, issued = 0;
   bool ldone = false;
   Mat LA, LB;
@@ -565,24 +564,32 @@ __device__ inline void bf_item_b(const FwdArgs &g, BfRing &rg, int wk) {
   for (int s = 0; s < issued; ++s) {
     ring_sync(issued - 1 - s);
     if (!ldone) issue_next();
-    bf_mma(rg, s % BNS, acc);
+    bf_mma<TM, TN>(rg, s % BNS, acc);
   }
   const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
   float *slot = reinterpret_cast<float *>(g.partial) + cld(&g.slot_off[it.slot]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = it.c0 + wn * 64 + j * 16 + l16;
+    for (int j = 0; j < TN; ++j) {
+      const int col = it.c0 + wn * 16 * TN + j * 16 + l16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = it.p0 + wm * 64 + i * 16 + mrow(acc[i][j], lg, v);
+        const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
         if (row < R && col < C) {
-          const int64_t o = it.mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
+          const int64_t o = mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
           slot[o] = acc[i][j][v];
         }
       }
     }
+}
+
+__device__ inline void bf_item_b(const FwdArgs &g, BfRing &rg, int wk) {
+  const Item it = load_item(g.items + wk);
+  const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
+#define TNS_CALL_B(a, b) bf_item_b_t<a, b>(g, rg, it, mode)
+  TNS_TILE_SWITCH(tm, tn, TNS_CALL_B)
+#undef TNS_CALL_B
 }
 
 __global__ __launch_bounds__(GTH) void k_fwd_bfb(FwdArgs g) {
@@ -619,59 +626,98 @@ __device__ inline int pop_block(const FwdArgs &g, int64_t nblk) {
   return -1;
 }
 
+template <int TM, int TN>
 __device__ inline void bf_mma_t(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
   const int off = (l16 * 4 + (g ^ bswz(l16))) * 8;
-  u16x8 ah[4], al[4], bh[4], bl[4];
+  u16x8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ah[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * 4 + i) * 512 + off]);
-    al[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * 4 + i) * 512 + off]);
-    bh[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * 4 + i) * 512 + off]);
-    bl[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * 4 + i) * 512 + off]);
+  for (int j = 0; j < TM; ++j) {
+    ah[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * TM + j) * 512 + off]);
+    al[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * TM + j) * 512 + off]);
   }
-  // acc[i][j]: rows = T columns wn*64 + 16 i + .., columns = T rows wm*64 + 16 j + ..
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TN; ++i) {
+    bh[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * TN + i) * 512 + off]);
+    bl[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * TN + i) * 512 + off]);
+  }
+  // acc[i][j]: rows = T columns wn*16*TN + 16 i + .., columns = T rows wm*16*TM + 16 j + ..
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+  for (int i = 0; i < TN; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
       acc[i][j] = mfma_bf(bl[i], ah[j], acc[i][j]);
       acc[i][j] = mfma_bf(bh[i], al[j], acc[i][j]);
       acc[i][j] = mfma_bf(bh[i], ah[j], acc[i][j]);
     }
 }
 
-typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
-
-// Phase A of the BF16x3 path: block b of ABT tasks as one stream.
-__device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
+// Epilogue of a phase-A BF16x3 tile: T = alpha * acc as 8-byte groups of the
+// high and low halves.
+template <int TM, int TN>
+__device__ inline void bf_store_t(const FwdArgs &g, f4 (&acc)[4][4], int t, int r0, int c0, int rows, int ld,
+                                  float alf) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[t]);
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    const int row = r0 + wm * 16 * TM + j * 16 + l16;
+#pragma unroll
+    for (int i = 0; i < TN; ++i) {
+      const int col = c0 + wn * 16 * TN + i * 16 + 4 * lg;
+      if (row < rows && col < ld) {
+        const f4 x = alf * acc[i][j];
+        const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+        const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]), (__bf16)(x[2] - (float)h[2]),
+                        (__bf16)(x[3] - (float)h[3])};
+        const int64_t o = (int64_t)row * ld + col;
+        *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
+        *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+      }
+      acc[i][j] = vzero<f4>();
+    }
+  }
+}
+
+// Phase A of the BF16x3 path: block b of ABT tasks as one stream; each task
+// uses the tile extents of its T dimensions.
+__device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
   const int t_end = (int)min((int64_t)(b + 1) * ABT, g.ntasks);
   // load cursor: (task, tile row, tile column, k) in stream order
-  int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0;
+  int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0, ltr, ltc;
   bool ldone = false;
   Mat LA, LB;
-  seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+  auto load_task = [&]() {
+    seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+    ltr = tile_ext(g.tiles, LA.rows);
+    ltc = tile_ext(g.tiles, LB.rows);
+  };
+  load_task();
   auto issue_next = [&]() {
     bf_issue(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
     ++issued;
     if ((lk0 += BBK) < lK) return;
     lk0 = 0;
-    if ((lc0 += GN) < LB.rows) return;
+    if ((lc0 += ltc) < LB.rows) return;
     lc0 = 0;
-    if ((lr0 += GM) < LA.rows) return;
+    if ((lr0 += ltr) < LA.rows) return;
     lr0 = 0;
-    if (++lt < t_end) seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+    if (++lt < t_end) load_task();
     else ldone = true;
   };
   while (!ldone && issued < BNS - 1) issue_next();
   // compute cursor, BNS - 1 steps behind
-  int ct = b * ABT, cr0 = 0, cc0 = 0, ck0 = 0, cK;
+  int ct = b * ABT, cr0 = 0, cc0 = 0, ck0 = 0, cK, ctm, ctn;
   double alpha;
   Mat CA, CB;
-  seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+  auto compute_task = [&]() {
+    seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+    ctm = tile_ext(g.tiles, CA.rows) / 32;
+    ctn = tile_ext(g.tiles, CB.rows) / 32;
+  };
+  compute_task();
   f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -680,38 +726,24 @@ __device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
   for (int s = 0; s < issued; ++s) {
     ring_sync(issued - 1 - s);
     if (!ldone) issue_next();
-    bf_mma_t(rg, s % BNS, acc);
+#define TNS_CALL_M(a, b) bf_mma_t<a, b>(rg, s % BNS, acc)
+    TNS_TILE_SWITCH(ctm, ctn, TNS_CALL_M)
+#undef TNS_CALL_M
     if ((ck0 += BBK) < cK) continue;
-    // tile (cr0, cc0) of task ct complete: T = alpha * acc as BF16 halves
+    // tile (cr0, cc0) of task ct complete
     {
       const int rows = CA.rows, ld = ld8(CB.rows);
-      uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[ct]);
       const float alf = (float)alpha;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = cr0 + wm * 64 + j * 16 + l16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int col = cc0 + wn * 64 + i * 16 + 4 * lg;
-          if (row < rows && col < ld) {
-            const f4 x = alf * acc[i][j];
-            const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
-            const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
-                            (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
-            const int64_t o = (int64_t)row * ld + col;
-            *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
-            *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
-          }
-          acc[i][j] = vzero<f4>();
-        }
-      }
+#define TNS_CALL_S(a, b) bf_store_t<a, b>(g, acc, ct, cr0, cc0, rows, ld, alf)
+      TNS_TILE_SWITCH(ctm, ctn, TNS_CALL_S)
+#undef TNS_CALL_S
     }
     ck0 = 0;
-    if ((cc0 += GN) < CB.rows) continue;
+    if ((cc0 += 32 * ctn) < CB.rows) continue;
     cc0 = 0;
-    if ((cr0 += GM) < CA.rows) continue;
+    if ((cr0 += 32 * ctm) < CA.rows) continue;
     cr0 = 0;
-    if (++ct < t_end) seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+    if (++ct < t_end) compute_task();
   }
 }
 
@@ -865,7 +897,7 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
 }
 
 template <int P, int PH>
-__global__ __launch_bounds__(GTH) void k_fwd_batch(BatchArgs b) {
+__global__ __launch_bounds__(GTH, P == TNS_F32 ? 2 : 1) void k_fwd_batch(BatchArgs b) {
   __shared__ FwdSmem<P> sm;
   __shared__ int s_w[2];
   for (;;) {
@@ -1007,6 +1039,7 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   g.queue = reinterpret_cast<int32_t *>(w); g.nq = S.nq;
   g.zero = w + 64;
   g.ident = id; g.ident_lo = lo_of(ident_elems(p)); g.ident_ld = ld8(p.maxdim);
+  g.tiles = p.tiles;
   return g;
 }
 
@@ -1025,14 +1058,14 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
                        g.pt_lo);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (p.ntasks > 0) {
-    if (P == TNS_BF16X3)
+    if constexpr (P == TNS_BF16X3)
       hipLaunchKernelGGL(k_fwd_bfa, dim3(grid_of(k_fwd_bfa, p.n_cu)), dim3(GTH), 0, st, g);
     else
       hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
   }
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
   if (p.ntasks > 0 && S.nitems > 0) {
-    if (P == TNS_BF16X3)
+    if constexpr (P == TNS_BF16X3)
       hipLaunchKernelGGL(k_fwd_bfb, dim3(grid_of(k_fwd_bfb, p.n_cu)), dim3(GTH), 0, st, g);
     else
       hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
@@ -1128,14 +1161,14 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
   hipLaunchKernelGGL((k_pad_psi_batch<In, P>), dim3(max_nS, 8, n), dim3(256), 0, st, tab);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (any_tasks) {
-    if (P == TNS_BF16X3)
+    if constexpr (P == TNS_BF16X3)
       hipLaunchKernelGGL(k_fwd_bf_batch<0>, dim3(grid_of(k_fwd_bf_batch<0>, n_cu)), dim3(GTH), 0, st, b);
     else
       hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);
   }
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
   if (any_tasks && any_items) {
-    if (P == TNS_BF16X3)
+    if constexpr (P == TNS_BF16X3)
       hipLaunchKernelGGL(k_fwd_bf_batch<1>, dim3(grid_of(k_fwd_bf_batch<1>, n_cu)), dim3(GTH), 0, st, b);
     else
       hipLaunchKernelGGL((k_fwd_batch<P, 1>), dim3(grid_of(k_fwd_batch<P, 1>, n_cu)), dim3(GTH), 0, st, b);
@@ -1166,6 +1199,70 @@ tns_status fwd_apply(const Plan &p, tns_prec prec, const void *ops, const void *
 
 using namespace tns;
 
+// Median time (ms) of `reps` runs of `run` (which enqueues one product on st)
+// after one warm-up run.
+template <class F>
+static tns_status time_median(F run, int reps, hipStream_t st, float *ms) {
+  hipEvent_t e0, e1;
+  TNS_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return TNS_ERR_HIP;
+  }
+  std::vector<float> t;
+  tns_status s = run();
+  for (int r = 0; r < reps && s == TNS_OK; ++r) {
+    float x = 0.f;
+    if (hipEventRecord(e0, st) != hipSuccess || (s = run()) != TNS_OK || hipEventRecord(e1, st) != hipSuccess ||
+        hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&x, e0, e1) != hipSuccess) {
+      if (s == TNS_OK) s = TNS_ERR_HIP;
+      break;
+    }
+    t.push_back(x);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != TNS_OK) return s;
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return TNS_OK;
+}
+
+// Coordinate descent over the four size buckets of the tile table (largest
+// dimensions first): for each bucket keep the extent (128, 64, 32) with the
+// shortest median product time, the other buckets fixed.  Leaves the best
+// table set on every task list.
+template <class F>
+static tns_status autotune(tns_tasklist *const *tls, int n, F run, hipStream_t st, uint32_t *best) {
+  uint32_t cur = plan_of(tls[0]).tiles;
+  static const int EXT[3] = {128, 64, 32};
+  for (int b = 3; b >= 0; --b) {
+    float tbest = 0.f;
+    uint32_t pick = cur;
+    for (int e = 0; e < 3; ++e) {
+      const uint32_t cand = (cur & ~(0xffu << (8 * b))) | ((uint32_t)EXT[e] << (8 * b));
+      for (int i = 0; i < n; ++i) {
+        const tns_status s = tns_set_tiles(tls[i], cand, st);
+        if (s != TNS_OK) return s;
+      }
+      float ms = 0.f;
+      const tns_status s = time_median(run, 3, st, &ms);
+      if (s != TNS_OK) return s;
+      if (e == 0 || ms < tbest) {
+        tbest = ms;
+        pick = cand;
+      }
+    }
+    cur = pick;
+  }
+  for (int i = 0; i < n; ++i) {
+    const tns_status s = tns_set_tiles(tls[i], cur, st);
+    if (s != TNS_OK) return s;
+  }
+  if (best) *best = cur;
+  return TNS_OK;
+}
+
 static bool batch_ok(const tns_tasklist *const *tls, int n, tns_prec prec) {
   if (!tls || n <= 0) return false;
   if (prec != TNS_F64 && prec != TNS_F32 && prec != TNS_BF16X3) return false;
@@ -1193,4 +1290,27 @@ extern "C" tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n
   if (prec == TNS_F64) return batch_launch<TNS_F64>(tls, n, op_vals, psi, sigma, ib, w, st, timed ? ev : nullptr);
   if (prec == TNS_F32) return batch_launch<TNS_F32>(tls, n, op_vals, psi, sigma, ib, w, st, timed ? ev : nullptr);
   return batch_launch<TNS_BF16X3>(tls, n, op_vals, psi, sigma, ib, w, st, timed ? ev : nullptr);
+}
+
+extern "C" tns_status tns_autotune_tiles(tns_tasklist *tl, tns_prec prec, const void *op_vals, const void *psi,
+                                         void *sigma, void *ws, size_t ws_bytes, uint32_t *tiles_out,
+                                         hipStream_t st) {
+  if (!tl || !op_vals || !psi || !sigma || !ws) return TNS_ERR_ARG;
+  if (prec != TNS_F64 && prec != TNS_F32 && prec != TNS_BF16X3) return TNS_ERR_ARG;
+  if (ws_bytes < fwd_workspace(plan_of(tl), prec)) return TNS_ERR_WORKSPACE;
+  auto run = [&]() { return fwd_apply(plan_of(tl), prec, op_vals, psi, sigma, 0.0, ws, ws_bytes, st, nullptr); };
+  tns_tasklist *one[1] = {tl};
+  return autotune(one, 1, run, st, tiles_out);
+}
+
+extern "C" tns_status tns_autotune_tiles_batch(tns_tasklist *const *tls, int n, tns_prec prec,
+                                               const void *const *op_vals, const void *const *psi,
+                                               void *const *sigma, void *ws, size_t ws_bytes, uint32_t *tiles_out,
+                                               hipStream_t st) {
+  if (!batch_ok(tls, n, prec) || !op_vals || !psi || !sigma || !ws) return TNS_ERR_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!op_vals[i] || !psi[i] || !sigma[i]) return TNS_ERR_ARG;
+  if (ws_bytes < batch_bytes(tls, n, prec)) return TNS_ERR_WORKSPACE;
+  auto run = [&]() { return tns_apply_heff_batch(tls, n, prec, op_vals, psi, sigma, 0.0, ws, ws_bytes, st); };
+  return autotune(tls, n, run, st, tiles_out);
 }

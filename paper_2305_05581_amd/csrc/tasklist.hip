@@ -221,11 +221,29 @@ __global__ __launch_bounds__(256) void k_group_cost(Plan p, Sched S) {
   }
 }
 
+// Tile extents of a group with a rows x cols output.
+__device__ inline void tile_dims(const Sched &S, int rows, int cols, int *tr, int *tc) {
+  if (S.tiles) {
+    *tr = tile_ext(S.tiles, rows);
+    *tc = tile_ext(S.tiles, cols);
+  } else {
+    *tr = S.tile_r;
+    *tc = S.tile_c > 0 ? S.tile_c : cols;
+  }
+}
+
 // Tiles (work items) of one chunk of a group with a rows x cols output.
 __device__ inline int n_tiles(const Sched &S, int rows, int cols) {
-  const int nr = (rows + S.tile_r - 1) / S.tile_r;
-  const int nc = S.tile_c > 0 ? (cols + S.tile_c - 1) / S.tile_c : 1;
-  return nr * nc;
+  int tr, tc;
+  tile_dims(S, rows, cols, &tr, &tc);
+  return ((rows + tr - 1) / tr) * ((cols + tc - 1) / tc);
+}
+
+// Chunk cap unit: the number of largest tiles of the output, so that chunking
+// does not depend on the tile table (partial slots stay the same).
+__device__ inline int cap_tiles(const Sched &S, int rows, int cols) {
+  if (!S.tiles) return n_tiles(S, rows, cols);
+  return ((rows + GM - 1) / GM) * ((cols + GN - 1) / GN);
 }
 
 // Greedy task chunks per group: a chunk closes before the task that would
@@ -240,7 +258,7 @@ __global__ void k_chunks(Plan p, Sched S) {
   if (n > 0) {
     const int64_t total = S.scalars[0];
     const int64_t target = total / ((int64_t)ITEMS_PER_CU * p.n_cu) + 1;
-    const int64_t cap = target * n_tiles(S, S.grp_rows[g], S.grp_cols[g]);
+    const int64_t cap = target * cap_tiles(S, S.grp_rows[g], S.grp_cols[g]);
     const int b = S.grp_begin[g], mode = S.grp_mode[g];
     int64_t cur = 0;
     int start = b;
@@ -278,16 +296,17 @@ __global__ void k_items(Sched S) {
   if (c >= nch) return;
   const Chunk ch = S.chunks[c];
   const int rows = S.grp_rows[ch.grp], cols = S.grp_cols[ch.grp];
-  const int tc = S.tile_c > 0 ? S.tile_c : cols;
+  int tr, tc;
+  tile_dims(S, rows, cols, &tr, &tc);
   const int ncol = (cols + tc - 1) / tc;
   const int nt = n_tiles(S, rows, cols);
   const int64_t ib = S.chunk_item_base[c];
   for (int k = 0; k < nt; ++k) {
     Item it;
     it.grp = ch.grp;
-    it.mode = S.grp_mode[ch.grp];
-    it.p0 = (k / ncol) * S.tile_r;
-    it.np = min(S.tile_r, rows - it.p0);
+    it.mode = S.grp_mode[ch.grp] | (S.tiles ? ((tr / 32) << 8) | ((tc / 32) << 16) : 0);
+    it.p0 = (k / ncol) * tr;
+    it.np = min(tr, rows - it.p0);
     it.c0 = (k % ncol) * tc;
     it.nc = min(tc, cols - it.c0);
     it.tb = ch.tb;
@@ -546,13 +565,16 @@ static size_t radix_tmp_i32(int64_t n) {
 
 // Carves one schedule's arrays; `idx` may be supplied by the caller.
 static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, int64_t chunks_cap, int maxdim,
-                         int tile_r, int tile_c, int nq, bool own_idx) {
+                         int tile_r, int tile_c, uint32_t tiles, int nq, bool own_idx) {
   S.ngroups = ngroups;
   S.ntcap = ntcap;
   S.chunks_cap = chunks_cap;
   S.tile_r = tile_r;
   S.tile_c = tile_c;
-  const int64_t tmax = (int64_t)((maxdim + tile_r - 1) / tile_r) * (tile_c > 0 ? (maxdim + tile_c - 1) / tile_c : 1);
+  S.tiles = tiles;
+  // items: up to the smallest tiles of the table (32 x 32) per chunk
+  const int er = tiles ? 32 : tile_r, ec = tiles ? 32 : tile_c;
+  const int64_t tmax = (int64_t)((maxdim + er - 1) / er) * (ec > 0 ? (maxdim + ec - 1) / ec : 1);
   S.items_cap = chunks_cap * tmax;
   S.nq = nq;
   if (own_idx) S.idx = cv.take<int32_t>(ntcap);
@@ -582,7 +604,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   Plan p;
   memset(&p, 0, sizeof(p));
   p.nL = P->nL; p.nR = P->nR; p.nS = P->nS; p.nOps = P->nOps; p.nBlk = P->nBlk; p.nTerms = P->nTerms;
-  p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals; p.maxdim = maxdim;
+  p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals; p.maxdim = maxdim; p.tiles = TILES_DEFAULT;
   p.psi_dim = P->psi_off[P->nS];
   const int64_t ntcap = std::max<int64_t>(1, (int64_t)P->nTerms * P->nS);
   p.qL = cv.take<int32_t>(2 * P->nL); p.dimL = cv.take<int32_t>(P->nL);
@@ -606,7 +628,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.pt_off = cv.take<int64_t>(P->nS + 1);
   // forward schedule: 2 groups per sector, output tiles GM x GN
   const int64_t fchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 4 * (int64_t)P->nS + 16;
-  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, maxdim, GM, GN, n_xcd, true);
+  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, maxdim, GM, GN, TILES_DEFAULT, n_xcd, true);
   // backward schedule: one group per sector (d psi) and one per block (d L / d R)
   const int64_t bent = 3 * ntcap;
   p.bkeys_in = cv.take<int32_t>(bent); p.bkeys_out = cv.take<int32_t>(bent); p.bvals_in = cv.take<int32_t>(bent);
@@ -615,7 +637,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.bsort_tmp = cv.take<char>(p.bsort_tmp_bytes + 256);
   const int32_t bgroups = P->nS + P->nBlk;
   const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
-  layout_sched(cv, p.bwd, bgroups, bent, bchunks, maxdim, TQ, 0, n_xcd, false);
+  layout_sched(cv, p.bwd, bgroups, bent, bchunks, maxdim, TQ, 0, 0u, n_xcd, false);
   if (pl) *pl = p;
   return cv.off + 256;
 }
@@ -625,6 +647,8 @@ static hipError_t up(T *dst, const T *src, size_t n, hipStream_t st) {
   if (n == 0 || !src) return hipSuccess;
   return hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
 }
+
+static tns_status sched_items(Sched &S, hipStream_t st);
 
 // Chunks, partial slots, work items and the longest-first order of a
 // schedule whose groups (begin, n, rows, cols, out, mode) are set.
@@ -644,6 +668,15 @@ static tns_status finish_sched(const Plan &p, Sched &S, hipStream_t st) {
   int64_t *item_n = reinterpret_cast<int64_t *>(S.keys_out);  // items_cap >= chunks_cap
   hipLaunchKernelGGL(k_chunk_sizes, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S, slot_sz, item_n);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, slot_sz, S.slot_off, S.chunks_cap);
+  return sched_items(S, st);
+}
+
+// Work items of a schedule whose chunks and slots are set: tiles per chunk,
+// longest first within each XCD queue, queue bounds and totals.
+static tns_status sched_items(Sched &S, hipStream_t st) {
+  const int B = 256;
+  int64_t *item_n = reinterpret_cast<int64_t *>(S.keys_out);
+  hipLaunchKernelGGL(k_chunk_sizes, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S, S.scratch, item_n);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, item_n, S.chunk_item_base, S.chunks_cap);
   hipLaunchKernelGGL(k_items, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S);
   hipLaunchKernelGGL(k_chunk_keys, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S);
@@ -797,6 +830,24 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   memcpy(out->opaque, &p, sizeof(p));
   return TNS_OK;
 }
+
+extern "C" tns_status tns_set_tiles(tns_tasklist *tl, uint32_t tiles, hipStream_t st) {
+  if (!tl || !tiles_valid(tiles)) return TNS_ERR_ARG;
+  Plan &p = plan_of(tl);
+  p.fwd.tiles = tiles;
+  p.tiles = tiles;
+  tns_status s = sched_items(p.fwd, st);
+  if (s != TNS_OK) return s;
+  int64_t h[8];
+  TNS_HIP(hipMemcpyAsync(h, p.fwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipStreamSynchronize(st));
+  read_sched(p.fwd, h);
+  if (p.fwd.nitems > p.fwd.items_cap) return TNS_ERR_WORKSPACE;
+  tl->nitems = p.fwd.nitems;
+  return TNS_OK;
+}
+
+extern "C" uint32_t tns_get_tiles(const tns_tasklist *tl) { return tl ? plan_of(tl).tiles : 0u; }
 
 extern "C" const char *tns_status_string(tns_status s) {
   switch (s) {

@@ -40,8 +40,23 @@ struct Item {
 };
 static_assert(sizeof(Item) == 48, "Item layout");
 
-// Output tile of the forward grouped GEMMs (both phases).
+// Largest output tile of the forward grouped GEMMs (both phases).
 constexpr int GM = 128, GN = 128;
+
+// Tile extents of the forward GEMMs chosen per dimension: a table of four
+// bytes, entry b the extent (32, 64 or 128) used along a dimension d in bucket
+// b = [d <= 32, d <= 64, d <= 128, d > 128].  Phase-B items carry their
+// extents in bits 8..15 (rows / 32) and 16..23 (columns / 32) of Item::mode.
+constexpr uint32_t TILES_DEFAULT = 0x80804020u;  // 32, 64, 128, 128
+__host__ __device__ inline int tile_bucket(int d) { return d <= 32 ? 0 : d <= 64 ? 1 : d <= 128 ? 2 : 3; }
+__host__ __device__ inline int tile_ext(uint32_t tab, int d) { return (int)((tab >> (8 * tile_bucket(d))) & 0xffu); }
+__host__ __device__ inline bool tiles_valid(uint32_t tab) {
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t e = (tab >> (8 * b)) & 0xffu;
+    if (e != 32 && e != 64 && e != 128) return false;
+  }
+  return true;
+}
 
 struct Chunk {
   int32_t grp, tb, te, xcd;  // xcd: queue the chunk's row panels go to
@@ -53,6 +68,7 @@ struct Chunk {
 struct Sched {
   int32_t ngroups, nq;  // nq: work queues (XCDs)
   int32_t tile_r, tile_c;  // item tile; tile_c == 0: all columns
+  uint32_t tiles, pad2_;   // non-zero: per-dimension tile table (overrides tile_r, tile_c)
   int64_t ntcap;        // capacity of idx
   int64_t chunks_cap, items_cap;
   int64_t nchunks, nitems, partial_elems, total_cost;
@@ -76,7 +92,8 @@ struct Sched {
 // workspace.
 struct Plan {
   int32_t nL, nR, nS, nOps, nBlk, nTerms, nmax, n_cu;
-  int32_t maxdim, pad_;  // largest sector dimension
+  int32_t maxdim;        // largest sector dimension
+  uint32_t tiles;        // forward tile table
   int64_t n_vals, psi_dim, ntasks;
   // copied tables
   int32_t *qL, *dimL, *qR, *dimR, *psi_sec;

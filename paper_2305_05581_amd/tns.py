@@ -96,6 +96,18 @@ def library(path=LIB_PATH):
     if hasattr(L, "tns_profile_events"):
         L.tns_profile_events.restype = None
         L.tns_profile_events.argtypes = [_P, _P, _P]
+    if hasattr(L, "tns_set_tiles"):
+        L.tns_set_tiles.restype = ctypes.c_int
+        L.tns_set_tiles.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_uint32, _P]
+        L.tns_get_tiles.restype = ctypes.c_uint32
+        L.tns_get_tiles.argtypes = [ctypes.POINTER(TnsTasklist)]
+        L.tns_autotune_tiles.restype = ctypes.c_int
+        L.tns_autotune_tiles.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int, _P, _P, _P, _P, sz,
+                                         ctypes.POINTER(ctypes.c_uint32), _P]
+        L.tns_autotune_tiles_batch.restype = ctypes.c_int
+        L.tns_autotune_tiles_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(TnsTasklist)), ctypes.c_int,
+                                               ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                               ctypes.POINTER(_P), _P, sz, ctypes.POINTER(ctypes.c_uint32), _P]
     if hasattr(L, "tns_apply_heff_batch"):
         L.tns_apply_batch_workspace_bytes.restype = sz
         L.tns_apply_batch_workspace_bytes.argtypes = [ctypes.POINTER(ctypes.POINTER(TnsTasklist)), ctypes.c_int,
@@ -237,6 +249,27 @@ class HeffProblem:
                                         float(beta), _ptr(ws), ws.numel(), _stream()), "tns_apply_heff")
         return out
 
+    # -- tile table (per sector-size bucket) ----------------------------------
+    @property
+    def tiles(self):
+        return int(library().tns_get_tiles(ctypes.byref(self.tl)))
+
+    def set_tiles(self, tiles):
+        _check(library().tns_set_tiles(ctypes.byref(self.tl), int(tiles), _stream()), "tns_set_tiles")
+
+    def autotune(self, psi, prec="f32"):
+        """Library autotuner of the tile table on products of ``psi``; returns the table."""
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        self._vec(psi, dt, "psi")
+        out = torch.empty_like(psi)
+        ws = self.workspace("apply", p)
+        best = ctypes.c_uint32(0)
+        _check(library().tns_autotune_tiles(ctypes.byref(self.tl), p, _ptr(self.operands(p)), _ptr(psi), _ptr(out),
+                                            _ptr(ws), ws.numel(), ctypes.byref(best), _stream()),
+               "tns_autotune_tiles")
+        return int(best.value)
+
     def backward(self, psi, grad_sigma, prec="f64", want_psi=True, want_ops=True, ops=None):
         """(grad_psi, grad_ops) of a loss with d loss / d sigma = grad_sigma."""
         p = prec_id(prec)
@@ -338,6 +371,23 @@ class HeffBatch:
                 raise ValueError("invalid batch")
             self._ws[p] = torch.empty(int(nb), dtype=torch.uint8, device=self.device)
         return self._ws[p]
+
+    def autotune(self, psis, prec="f32"):
+        """Library autotuner of one tile table for all instances; returns it."""
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        n = len(self.problems)
+        outs = [torch.empty(h.psi_dim, dtype=dt, device=self.device) for h in self.problems]
+        for h, x in zip(self.problems, psis):
+            h._vec(x, dt, "psi")
+        ops = (_P * n)(*[_ptr(h.operands(p)) for h in self.problems])
+        xs = (_P * n)(*[_ptr(x) for x in psis])
+        ys = (_P * n)(*[_ptr(o) for o in outs])
+        ws = self.workspace(p)
+        best = ctypes.c_uint32(0)
+        _check(library().tns_autotune_tiles_batch(self._tls, n, p, ops, xs, ys, _ptr(ws), ws.numel(),
+                                                  ctypes.byref(best), _stream()), "tns_autotune_tiles_batch")
+        return int(best.value)
 
     def apply(self, psis, prec="f32", outs=None, beta=0.0):
         p = prec_id(prec)

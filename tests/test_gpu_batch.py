@@ -92,3 +92,53 @@ def test_batch_rejects_bad_arguments(batch):
         B.apply(psis[:-1], "f32")
     with pytest.raises(TnsError):
         B.apply(psis, "f32", outs=[torch.empty_like(x) for x in psis], beta=0.5)
+
+
+TABLES = [0x80808080, 0x40404040, 0x20202020, 0x80404020, 0x20408080]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_tile_tables_give_identical_results(batch, prec):
+    """Every tile table computes every output element in the same order."""
+    Ps, Hs, B = batch
+    dt = torch.float64 if prec == "f64" else torch.float32
+    H = Hs[0]
+    x = to_dev(gaussian_psi(Ps[0], 41), dt)
+    ref = H.apply(x, prec)
+    default = H.tiles
+    try:
+        for tab in TABLES:
+            say("tiles %08x %s" % (tab, prec))
+            H.set_tiles(tab)
+            assert H.tiles == tab
+            assert torch.equal(H.apply(x, prec), ref)
+    finally:
+        H.set_tiles(default)
+
+
+def test_set_tiles_rejects_invalid(batch):
+    from paper_2305_05581_amd.tns import TnsError
+    Ps, Hs, B = batch
+    with pytest.raises(TnsError):
+        Hs[1].set_tiles(0x80804010)
+    with pytest.raises(TnsError):
+        Hs[1].set_tiles(0)
+
+
+def test_autotune_single_and_batch(batch):
+    Ps, Hs, B = batch
+    x = to_dev(gaussian_psi(Ps[0], 43), torch.float32)
+    ref = Hs[0].apply(x, "f32")
+    tab = Hs[0].autotune(x, "f32")
+    say("autotuned single table %08x" % tab)
+    assert all(((tab >> (8 * b)) & 0xff) in (32, 64, 128) for b in range(4))
+    assert Hs[0].tiles == tab
+    assert torch.equal(Hs[0].apply(x, "f32"), ref)
+    psis = [to_dev(gaussian_psi(P, 50 + i), torch.float32) for i, P in enumerate(Ps)]
+    refs = [H.apply(p, "f32") for H, p in zip(Hs, psis)]
+    tb = B.autotune(psis, "f32")
+    say("autotuned batch table %08x" % tb)
+    assert all(H.tiles == tb for H in Hs)
+    outs = B.apply(psis, "f32")
+    for o, r in zip(outs, refs):
+        assert torch.equal(o, r)
