@@ -9,20 +9,21 @@
 //
 // Phase A forms the intermediate of every task,
 //   T_k = alpha_k X_k M_k      (class 0: X = L, M = A;  class 1: X = R, M = A^T),
-// in 128 x 128 output tiles and stores it, row-major with leading dimension
-// ld8(K2), in the workspace.  Phase B forms, per chunk of the task list of an
-// output group,
+// and stores it, row-major with leading dimension ld8(K2), in the workspace.
+// Phase B forms, per chunk of the task list of an output group,
 //   slot = sum_k T_k Y_k^T     (class 0: Y = R;  class 1: Y = L)
-// as one GEMM whose inner dimension runs through all tasks of the chunk, in
-// 128 x 128 tiles of the group's output.  The epilogue adds the slots of each
-// sector in a fixed order.  This is the batched-GEMM arrangement of Alg. 2
-// (intermediates in device memory, one batched product per stage) with the
-// summation over terms folded into the inner dimension of the second GEMM.
+// as one GEMM whose inner dimension runs through all tasks of the chunk.  The
+// epilogue adds the slots of each sector in a fixed order.  This is the
+// batched-GEMM arrangement of Alg. 2 (intermediates in device memory, one
+// batched product per stage) with the summation over terms folded into the
+// inner dimension of the second GEMM.
 //
-// Both phases run one kernel: C(i, j) = sum over segments of
-// sum_k A(i, k) B(j, k) with every operand k-contiguous (rows of L, R, T and
-// of the padded copies of A and A^T), staged global -> registers -> LDS with
-// 16-byte loads and a double-buffered LDS pipeline, one barrier per K step.
+// Both phases compute tiles C(i, j) = sum over segments of sum_k A(i, k) B(j, k)
+// with every operand k-contiguous (rows of L, R, T, of the identity and of the
+// padded copies of A and A^T).  Tiles are 32, 64 or 128 rows / columns per the
+// tile table of the task list (per sector-size bucket).  Operands stream from
+// global memory straight into a 4-stage LDS ring (16-byte direct loads), the
+// MFMA work consuming one stage per barrier.
 #include <algorithm>
 #include <type_traits>
 #include <vector>
@@ -32,15 +33,15 @@
 
 namespace tns {
 
-constexpr int GTH = 256;  // threads per workgroup: 4 waves in a 2 x 2 grid of 64 x 64 wave tiles
+constexpr int GTH = 256;  // threads per workgroup: 4 waves in a 2 x 2 grid of wave tiles
 
 // Operand: element (i, k) at p[i * ld + k] for i < rows, k < K of the
-// segment; identity (i == k) when `ident`.  BF16X3: p is the high half, the
-// low half lies `lo` elements further.
+// segment.  BF16X3: p is the high half, the low half lies `lo` elements
+// further.  Identity operators are matrices in memory too.
 struct Mat {
   const void *p;
   int64_t lo;
-  int32_t ld, rows, ident;
+  int32_t ld, rows;
 };
 
 // Read of schedule / task metadata that no kernel of the product writes:
@@ -83,7 +84,7 @@ struct FwdArgs {
   int32_t *queue;  // [0, 8): phase A queues, [8, 16): phase B queues
   int32_t nq;
   const void *zero;  // 64 zero bytes
-  const void *ident;  // BF16X3: identity matrix maxdim x ld8(maxdim) (hi; lo `ident_lo` further)
+  const void *ident;  // identity matrix maxdim x ld8(maxdim) (BF16X3: hi; lo `ident_lo` further)
   int64_t ident_lo;
   int32_t ident_ld;
   uint32_t tiles;     // tile table (phase A picks a task's tile from its T dimensions)
@@ -96,129 +97,34 @@ template <> struct FP<TNS_F64> {
   typedef double E;  // element in memory and LDS
   typedef d2 V;      // 16-byte vector
   typedef d4 A4;     // MFMA accumulator
-  static constexpr int BK = 16, VEC = 2, LDK = BK + 2;
 };
 template <> struct FP<TNS_F32> {
   typedef float Acc;
   typedef float E;
   typedef f4 V;
   typedef f4 A4;
-  static constexpr int BK = 32, VEC = 4, LDK = BK + 4;
 };
 template <> struct FP<TNS_BF16X3> {
   typedef float Acc;
   typedef uint16_t E;
   typedef u16x8 V;
   typedef f4 A4;
-  static constexpr int BK = 32, VEC = 8, LDK = BK + 8;
 };
-
-template <int P> struct __attribute__((aligned(16))) FwdSmem {
-  typedef typename FP<P>::E E;
-  static constexpr int NH = P == TNS_BF16X3 ? 2 : 1;  // halves per operand
-  E a[2][NH][GM * FP<P>::LDK];
-  E b[2][NH][GN * FP<P>::LDK];
-};
-
-// --- register-staged path (FP64, FP32): operand loads -----------------------------
-// A tile has 32 NT rows (NT = 1, 2, 4 MFMA tiles per wave along it).  Thread t
-// stages the vectors (row t / NV + j * RP, k-vector t % NV), j < 32 NT / RP.
-template <int P> struct Stage {
-  static constexpr int NV = FP<P>::BK / FP<P>::VEC;
-  static constexpr int RP = GTH / NV;
-  static constexpr int NL = GM / RP;
-  typename FP<P>::V r[NL];
-};
-
-template <int P, int NT>
-__device__ inline void stage_load(Stage<P> &s, const Mat &m, int r0, int k0, int K, const void *zero) {
-  typedef typename FP<P>::E E;
-  typedef typename FP<P>::V V;
-  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, VEC = FP<P>::VEC, NLX = 32 * NT / RP;
-  static_assert(NLX >= 1 && 32 * NT % RP == 0, "tile rows cover whole load passes");
-  if (m.ident) return;
-  int t = threadIdx.x;
-  asm volatile("" : "+v"(t));
-  const int kk = k0 + (t % NV) * VEC;
-  const E *base = reinterpret_cast<const E *>(m.p);
-#pragma unroll
-  for (int j = 0; j < NLX; ++j) {
-    const int row = r0 + t / NV + j * RP;
-    const bool in = row < m.rows && kk < K;
-    const E *ad = in ? base + (int64_t)row * m.ld + kk : reinterpret_cast<const E *>(zero);
-    s.r[j] = *reinterpret_cast<const V *>(ad);
-  }
-}
-
-template <int P, int NT>
-__device__ inline void stage_store(typename FP<P>::E *lds, Stage<P> &s, const Mat &m, int r0, int k0, int K) {
-  typedef typename FP<P>::E E;
-  typedef typename FP<P>::V V;
-  constexpr int NV = Stage<P>::NV, RP = Stage<P>::RP, VEC = FP<P>::VEC, LDK = FP<P>::LDK, NLX = 32 * NT / RP;
-  const int t = threadIdx.x;
-  const int kv = (t % NV) * VEC, kk = k0 + kv;
-#pragma unroll
-  for (int j = 0; j < NLX; ++j) {
-    const int lrow = t / NV + j * RP, row = r0 + lrow;
-    V h;
-    if (m.ident) {
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) h[e] = (row == kk + e && row < m.rows && kk + e < K) ? E(1) : E(0);
-    } else {
-      h = s.r[j];
-      if (kk + VEC > K) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          if (kk + e >= K) h[e] = 0;
-      }
-    }
-    *reinterpret_cast<V *>(&lds[lrow * LDK + kv]) = h;
-  }
-}
-
-// --- MFMA on one LDS stage ------------------------------------------------------
-// Wave tile (16 TM) x (16 TN) at (wm, wn); acc[i][j] is the 16 x 16 tile
-// (16 i, 16 j) of it.  Lane group g = lane / 16 owns k in [g BK/4, (g+1) BK/4).
-template <int P, int TM, int TN>
-__device__ inline void stage_mma(const FwdSmem<P> &sm, int buf, typename FP<P>::A4 (&acc)[4][4]) {
-  typedef typename FP<P>::E E;
-  typedef typename FP<P>::V V;
-  constexpr int LDK = FP<P>::LDK, BK = FP<P>::BK, VEC = FP<P>::VEC, KG = BK / 4;  // k per lane group
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
-#pragma unroll
-  for (int h = 0; h < KG / VEC; ++h) {
-    V a[TM], b[TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-      a[i] = *reinterpret_cast<const V *>(&sm.a[buf][0][(wm * 16 * TM + i * 16 + l16) * LDK + g * KG + h * VEC]);
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-      b[j] = *reinterpret_cast<const V *>(&sm.b[buf][0][(wn * 16 * TN + j * 16 + l16) * LDK + g * KG + h * VEC]);
-#pragma unroll
-    for (int e = 0; e < VEC; ++e)
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = mfma((E)a[i][e], (E)b[j][e], acc[i][j]);
-  }
-}
 
 // --- segment operands -------------------------------------------------------------
+// Operator block `blk` of an output with `rows` rows; blk < 0 is the identity,
+// read from the identity matrix in the workspace like any other operand.
 template <int P>
 __device__ inline Mat op_mat(const FwdArgs &g, int blk, int rows) {
   typedef typename FP<P>::E E;
   Mat m;
   m.rows = rows;
-  m.lo = g.ops_lo;
-  if (P == TNS_BF16X3 && blk < 0) {  // the identity as a matrix in memory
-    m.p = g.ident; m.lo = g.ident_lo; m.ld = g.ident_ld; m.ident = 0;
-  } else if (blk < 0) {
-    m.p = g.zero; m.ld = 0; m.ident = 1;
+  if (blk < 0) {
+    m.p = g.ident; m.lo = g.ident_lo; m.ld = g.ident_ld;
   } else {
     m.p = reinterpret_cast<const E *>(g.ops) + cld(&g.blk_off[blk]);
+    m.lo = g.ops_lo;
     m.ld = cld(&g.blk_ld[blk]);
-    m.ident = 0;
   }
   return m;
 }
@@ -240,41 +146,43 @@ __device__ inline void seg_ops(const FwdArgs &g, int t, Mat &A, Mat &B, int &K, 
       K = m;
       A = op_mat<P>(g, lblk, q);
       B.p = reinterpret_cast<const E *>(g.pt) + cld(&g.pt_off[in]);
-      B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n; B.ident = 0;
+      B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n;
     } else {           // T = R A^T: B(j, k) = A(j, k)
       K = n;
       A = op_mat<P>(g, rblk, r);
       B.p = reinterpret_cast<const E *>(g.pp) + cld(&g.pp_off[in]);
-      B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m; B.ident = 0;
+      B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m;
     }
   } else {
     const int k2 = order == 0 ? n : m;
     K = k2;
     A.p = reinterpret_cast<const E *>(g.T) + cld(&g.t_off[t]);
-    A.lo = g.T_lo; A.ld = ld8(k2); A.rows = order == 0 ? q : r; A.ident = 0;
+    A.lo = g.T_lo; A.ld = ld8(k2); A.rows = order == 0 ? q : r;
     B = order == 0 ? op_mat<P>(g, rblk, r) : op_mat<P>(g, lblk, q);
   }
 }
 
 // --- work queues --------------------------------------------------------------------
-// Phase A: tasks in blocks of 4 consecutive ones, block b on queue b mod nq.
-__device__ inline int64_t qa_count(int64_t ntasks, int nq, int q) {
-  const int64_t per = 4 * (int64_t)nq, full = ntasks / per;
-  const int64_t rest = ntasks - full * per - 4 * (int64_t)q;
-  return full * 4 + (rest < 0 ? 0 : (rest > 4 ? 4 : rest));
-}
-__device__ inline int64_t qa_task(int nq, int q, int64_t j) { return (j / 4) * 4 * nq + 4 * q + (j % 4); }
+// Phase A: blocks of ABT consecutive tasks, block b on queue b mod nq.
+// Phase B: the schedule's items, queue q = items[qbase[q], qbase[q+1]).
+constexpr int ABT = 4;
 
+__device__ inline int64_t blk_count(int64_t ntasks, int nq, int q) {
+  const int64_t nblk = (ntasks + ABT - 1) / ABT;
+  return nblk > q ? (nblk - 1 - q) / nq + 1 : 0;
+}
+
+// Thread 0: next work id of phase PH (own XCD queue first), -1 when drained.
 template <int PH>
 __device__ inline int pop_work(const FwdArgs &g) {
   const int home = blockIdx.x % g.nq;
   for (int k = 0; k < g.nq; ++k) {
     const int q = home + k < g.nq ? home + k : home + k - g.nq;
     if (PH == 0) {
-      const int64_t n = qa_count(g.ntasks, g.nq, q);
+      const int64_t n = blk_count(g.ntasks, g.nq, q);
       if (n <= 0) continue;
       const int j = atomicAdd(g.queue + q, 1);
-      if (j < n) return (int)qa_task(g.nq, q, j);
+      if (j < n) return (int)((int64_t)j * g.nq + q);
     } else {
       const int64_t b = g.qbase[q], n = g.qbase[q + 1] - b;
       if (n <= 0) continue;
@@ -285,98 +193,217 @@ __device__ inline int pop_work(const FwdArgs &g) {
   return -1;
 }
 
-// --- the register-staged kernel ---------------------------------------------------------
-// One output tile of (32 TM) x (32 TN): acc = sum over segments [sb, se) of
-// A_seg B_seg^T on rows [r0, r0 + 32 TM) of A and [c0, c0 + 32 TN) of B.
-template <int P, int PH, int TM, int TN>
-__device__ inline void tile_gemm(const FwdArgs &g, FwdSmem<P> &sm, int sb, int se, int r0, int c0,
-                                 typename FP<P>::A4 (&acc)[4][4]) {
+// --- the LDS ring: direct global -> LDS loads, BNS stages ---------------------------
+// A stage holds the 128 x BK tiles of A and of B (BF16X3: high and low
+// halves) as arrays of eight 1 KB chunks; a chunk (16 rows of 64 bytes = 4
+// 16-byte k-vectors) is the target of one global_load_lds_dwordx4 of a wave.
+// Arrays: BF16X3 [A hi, A lo, B hi, B lo] (BK = 32, 32 KB per stage);
+// FP32 [A, B] (BK = 16) and FP64 [A, B] (BK = 8), 16 KB per stage, so that
+// two workgroups share a CU.  The k-vectors of row r sit at slots
+// kv ^ ((r >> 1) & 3), so that the 16 rows read by one MFMA operand fetch
+// fall into distinct LDS banks.  Loads run BNS - 1 stages ahead of the MFMA
+// work; a stage is consumed after a counted vector-memory wait and one
+// barrier (no fence, in-flight stages stay in flight).  Out-of-range rows and
+// whole k-vectors beyond K read the zero region; the library's own operands
+// (T, padded psi, the identity) hold zeros beyond K, so the k-tail of an
+// operator row always meets zeros.
+typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
+constexpr int BNS = 4;
+
+// KS: k-halves per stage of FP32 / FP64 (each half 4 k-vectors of 16 bytes
+// per row, one array of chunks per operand and half); BF16X3 uses KS = 1 and
+// two halves of precision instead.
+template <int P> struct RingP;
+template <> struct RingP<TNS_BF16X3> { static constexpr int VEC = 8; };
+template <> struct RingP<TNS_F32> { static constexpr int VEC = 4; };
+template <> struct RingP<TNS_F64> { static constexpr int VEC = 2; };
+template <int P, int KS> struct RingL {
+  static constexpr int ARR = P == TNS_BF16X3 ? 4 : 2 * KS;  // arrays of 8 chunks
+  static constexpr int CH = 8 * ARR;                        // chunks per stage
+  static constexpr int LOADS = CH / 4;                      // global_load_lds per wave and stage
+  static constexpr int BK = P == TNS_BF16X3 ? 32 : KS * 4 * RingP<P>::VEC;
+};
+template <int P, int KS> struct __attribute__((aligned(16))) Ring {
+  uint8_t s[BNS][RingL<P, KS>::CH * 1024];
+};
+__device__ inline int rswz(int rin) { return (rin >> 1) & 3; }
+
+__device__ inline void gl_lds(const void *src, void *dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                   (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+// Waits until at most n_after stages of this wave's ring loads are in flight
+// (vector-memory loads complete in order), then joins the workgroup.  No
+// fence: only the LDS written by this kernel's ring loads is exchanged here.
+template <int P, int KS>
+__device__ inline void ring_sync(int n_after) {
+  constexpr int E = (7 << 4) | (15 << 8), L = RingL<P, KS>::LOADS;  // expcnt, lgkmcnt: no wait
+  if (n_after >= 2)
+    __builtin_amdgcn_s_waitcnt(E | (2 * L & 15) | ((2 * L >> 4) << 14));
+  else if (n_after == 1)
+    __builtin_amdgcn_s_waitcnt(E | (L & 15) | ((L >> 4) << 14));
+  else
+    __builtin_amdgcn_s_waitcnt(E);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+static_assert(BNS == 4, "ring_sync covers up to two stages in flight after the awaited one");
+
+// Stage `buf` <- rows [r0, r0 + 128) of A and [c0, c0 + 128) of B, k in [k0, k0 + BK).
+template <int P, int KS>
+__device__ inline void ring_issue(Ring<P, KS> &rg, int buf, const Mat &A, const Mat &B, int r0, int c0, int k0,
+                                  int K, const void *zero) {
+  typedef typename FP<P>::E E;
+  constexpr int VEC = RingP<P>::VEC, L = RingL<P, KS>::LOADS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rin = lane >> 2;
+  const int kl = VEC * ((lane & 3) ^ rswz(rin));
+  const E *z = reinterpret_cast<const E *>(zero);
+#pragma unroll
+  for (int u = 0; u < L; ++u) {
+    const int c = w + 4 * u;  // chunk of the stage; array h = c / 8 = u / 2
+    const int h = u / 2;
+    bool isB, lo;
+    int k = k0 + kl;
+    if (P == TNS_BF16X3) {
+      isB = h >= 2;
+      lo = h & 1;
+    } else {
+      isB = h >= KS;
+      lo = false;
+      k += (h - KS * (int)isB) * 4 * VEC;  // k-half
+    }
+    const int row = (isB ? c0 : r0) + 16 * (c - 8 * h) + rin;
+    const Mat &M = isB ? B : A;
+    const bool in = k < K && row < M.rows;
+    const E *src = reinterpret_cast<const E *>(M.p) + (lo ? M.lo : 0) + (int64_t)row * M.ld + k;
+    gl_lds(in ? src : z, &rg.s[buf][c * 1024]);
+  }
+}
+
+// Byte offset in a stage of 16-byte k-vector kv of row `row` of array arr.
+__device__ inline int ring_off(int arr, int row, int kv) {
+  const int rin = row & 15;
+  return (8 * arr + (row >> 4)) * 1024 + (rin * 4 + (kv ^ rswz(rin))) * 16;
+}
+
+// MFMA fragment of one 16-row tile for lane (l16, g): the 16-byte k-vector of
+// k-group g (BF16X3: of both halves; FP32 / FP64: of every k-half).
+template <int P, int KS> struct Frag;
+template <int KS> struct Frag<TNS_BF16X3, KS> { u16x8 h, l; };
+template <int KS> struct Frag<TNS_F32, KS> { f4 v[KS]; };
+template <int KS> struct Frag<TNS_F64, KS> { d2 v[KS]; };
+
+template <int P, int KS>
+__device__ inline Frag<P, KS> ring_frag(const Ring<P, KS> &rg, int buf, int isB, int row0, int l16, int g) {
+  Frag<P, KS> f;
+  const uint8_t *base = rg.s[buf];
+  if constexpr (P == TNS_BF16X3) {
+    f.h = *reinterpret_cast<const u16x8 *>(base + ring_off(2 * isB, row0 + l16, g));
+    f.l = *reinterpret_cast<const u16x8 *>(base + ring_off(2 * isB + 1, row0 + l16, g));
+  } else {
+#pragma unroll
+    for (int kh = 0; kh < KS; ++kh)
+      f.v[kh] = *reinterpret_cast<const typename FP<P>::V *>(base + ring_off(KS * isB + kh, row0 + l16, g));
+  }
+  return f;
+}
+
+// acc += x y^T over the stage's k for one 16 x 16 tile (x: rows, y: columns).
+template <int P, int KS, class A4>
+__device__ inline void frag_mma(const Frag<P, KS> &x, const Frag<P, KS> &y, A4 &acc) {
+  if constexpr (P == TNS_BF16X3) {
+    acc = mfma_bf(x.l, y.h, acc);
+    acc = mfma_bf(x.h, y.l, acc);
+    acc = mfma_bf(x.h, y.h, acc);
+  } else {
+#pragma unroll
+    for (int kh = 0; kh < KS; ++kh)
+#pragma unroll
+      for (int e = 0; e < RingP<P>::VEC; ++e) acc = mfma(x.v[kh][e], y.v[kh][e], acc);
+  }
+}
+
+// One stage of MFMA for a (32 TM) x (32 TN) tile; wave (wm, wn) owns rows
+// wm 16 TM + 16 i and columns wn 16 TN + 16 j.  SWAP: acc[i][j] holds the
+// transposed tile (rows = B rows wn 16 TN + 16 i, columns = A rows wm 16 TM + 16 j).
+template <int P, int KS, int TM, int TN, bool SWAP>
+__device__ inline void ring_mma(const Ring<P, KS> &rg, int buf, typename FP<P>::A4 (&acc)[4][4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
+  Frag<P, KS> a[TM], b[TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) a[i] = ring_frag<P, KS>(rg, buf, 0, wm * 16 * TM + 16 * i, l16, g);
+#pragma unroll
+  for (int j = 0; j < TN; ++j) b[j] = ring_frag<P, KS>(rg, buf, 1, wn * 16 * TN + 16 * j, l16, g);
+  if (SWAP) {
+#pragma unroll
+    for (int i = 0; i < TN; ++i)
+#pragma unroll
+      for (int j = 0; j < TM; ++j) frag_mma<P, KS>(b[i], a[j], acc[i][j]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) frag_mma<P, KS>(a[i], b[j], acc[i][j]);
+  }
+}
+
+// Ring geometry and workgroups per CU of each (precision, phase): FP32 and
+// FP64 phase B 16 KB stages, two workgroups per CU; FP64 phase A 32 KB stages
+// (its swapped-accumulator epilogue needs more than 256 registers per lane),
+// BF16X3 32 KB stages, one workgroup per CU.
+template <int P, int PH> struct Geo {
+  static constexpr int KS = (P == TNS_F64 && PH == 0) ? 2 : 1;
+  static constexpr int WG = (P == TNS_BF16X3 || (P == TNS_F64 && PH == 0)) ? 1 : 2;
+};
+
+// Runs CALL(TM, TN) for tile extents (32 tm) x (32 tn), tm, tn in {1, 2, 4}.
+#define TNS_TILE_SWITCH(tm, tn, CALL)                  \
+  switch ((tm) * 8 + (tn)) {                             \
+    case 9: CALL(1, 1); break;                           \
+    case 10: CALL(1, 2); break;                          \
+    case 12: CALL(1, 4); break;                          \
+    case 17: CALL(2, 1); break;                          \
+    case 18: CALL(2, 2); break;                          \
+    case 20: CALL(2, 4); break;                          \
+    case 33: CALL(4, 1); break;                          \
+    case 34: CALL(4, 2); break;                          \
+    default: CALL(4, 4); break;                          \
+  }
+
+// --- phase B: one item (output tile, chunk of tasks) ------------------------------------
+template <int P, int KS, int TM, int TN>
+__device__ inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it, int mode) {
   typedef typename FP<P>::A4 A4;
-  constexpr int BK = FP<P>::BK;
+  constexpr int BK = RingL<P, KS>::BK;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  A4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  auto seg_task = [&](int s) { return PH == 0 ? s : cld(&g.idx[s]); };
-  Mat A, B;
-  int K;
-  seg_ops<P, PH>(g, seg_task(sb), A, B, K, nullptr);
-  Stage<P> sa, sb_;
-  stage_load<P, TM>(sa, A, r0, 0, K, g.zero);
-  stage_load<P, TN>(sb_, B, c0, 0, K, g.zero);
-  stage_store<P, TM>(sm.a[0][0], sa, A, r0, 0, K);
-  stage_store<P, TN>(sm.b[0][0], sb_, B, c0, 0, K);
-  __syncthreads();
-  int s = sb, k0 = 0, cur = 0;
-  for (;;) {
-    int ns = s, nk = k0 + BK, nK = K;
-    Mat nA = A, nB = B;
-    if (nk >= K) {
-      ns = s + 1;
-      nk = 0;
-      if (ns < se) seg_ops<P, PH>(g, seg_task(ns), nA, nB, nK, nullptr);
+  int ls = it.tb, lj = 0, lK, issued = 0;
+  bool ldone = false;
+  Mat LA, LB;
+  seg_ops<P, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+  auto issue_next = [&]() {
+    ring_issue<P, KS>(rg, issued % BNS, LA, LB, it.p0, it.c0, lj * BK, lK, g.zero);
+    ++issued;
+    if (++lj * BK >= lK) {
+      lj = 0;
+      if (++ls < it.te) seg_ops<P, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+      else ldone = true;
     }
-    const bool more = ns < se;
-    if (more) {
-      stage_load<P, TM>(sa, nA, r0, nk, nK, g.zero);
-      stage_load<P, TN>(sb_, nB, c0, nk, nK, g.zero);
-    }
-    stage_mma<P, TM, TN>(sm, cur, acc);
-    if (more) {
-      stage_store<P, TM>(sm.a[cur ^ 1][0], sa, nA, r0, nk, nK);
-      stage_store<P, TN>(sm.b[cur ^ 1][0], sb_, nB, c0, nk, nK);
-    }
-    __syncthreads();
-    if (!more) break;
-    cur ^= 1;
-    s = ns;
-    k0 = nk;
-    K = nK;
-    A = nA;
-    B = nB;
+  };
+  while (!ldone && issued < BNS - 1) issue_next();
+  for (int s = 0; s < issued; ++s) {
+    ring_sync<P, KS>(issued - 1 - s);
+    if (!ldone) issue_next();
+    ring_mma<P, KS, TM, TN, false>(rg, s % BNS, acc);
   }
-}
-
-// Phase A, task t: every (32 TM) x (32 TN) tile of T_t, row strips in turn.
-template <int P, int TM, int TN>
-__device__ inline void phase_a_task(const FwdArgs &g, FwdSmem<P> &sm, int t) {
-  typedef typename FP<P>::A4 A4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
-  Mat A, B;
-  int K;
-  double alpha;
-  seg_ops<P, 0>(g, t, A, B, K, &alpha);
-  const int rows = A.rows, cols = B.rows, ld = ld8(cols);
-  typedef typename FP<P>::Acc Acc;
-  Acc *Tt = reinterpret_cast<Acc *>(g.T) + cld(&g.t_off[t]);
-  const Acc alf = (Acc)alpha;
-  A4 acc[4][4];
-  for (int r0 = 0; r0 < rows; r0 += 32 * TM)
-    for (int c0 = 0; c0 < cols; c0 += 32 * TN) {
-      tile_gemm<P, 0, TM, TN>(g, sm, t, t + 1, r0, c0, acc);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int col = c0 + wn * 16 * TN + j * 16 + l16;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = r0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
-            if (row < rows && col < ld) Tt[(int64_t)row * ld + col] = alf * acc[i][j][v];
-          }
-        }
-    }
-}
-
-// Phase B, one item: its (32 TM) x (32 TN) output tile over its chunk of tasks.
-template <int P, int TM, int TN>
-__device__ inline void phase_b_item(const FwdArgs &g, FwdSmem<P> &sm, const Item &it, int mode) {
-  typedef typename FP<P>::A4 A4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
-  A4 acc[4][4];
-  tile_gemm<P, 1, TM, TN>(g, sm, it.tb, it.te, it.p0, it.c0, acc);
   const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
   typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
 #pragma unroll
@@ -395,310 +422,86 @@ __device__ inline void phase_b_item(const FwdArgs &g, FwdSmem<P> &sm, const Item
     }
 }
 
-// Runs F<TM, TN> for tile extents (32 tm) x (32 tn), tm, tn in {1, 2, 4}.
-#define TNS_TILE_SWITCH(tm, tn, CALL)                  \
-  switch ((tm) * 8 + (tn)) {                             \
-    case 9: CALL(1, 1); break;                           \
-    case 10: CALL(1, 2); break;                          \
-    case 12: CALL(1, 4); break;                          \
-    case 17: CALL(2, 1); break;                          \
-    case 18: CALL(2, 2); break;                          \
-    case 20: CALL(2, 4); break;                          \
-    case 33: CALL(4, 1); break;                          \
-    case 34: CALL(4, 2); break;                          \
-    default: CALL(4, 4); break;                          \
-  }
-
-// One work item of the register-staged path: phase A = all tiles of task
-// wk, phase B = item wk of the phase-B schedule.
-template <int P, int PH>
-__device__ inline void fwd_item(const FwdArgs &g, FwdSmem<P> &sm, int wk) {
-  if (PH == 0) {
-    const tns_task *tp = g.tasks + wk;
-    const int out = cld(&tp->out), in = cld(&tp->in), order = cld(&tp->order);
-    const int rows = order == 0 ? cld(&g.dimL[cld(&g.psi_sec[4 * out])]) : cld(&g.dimR[cld(&g.psi_sec[4 * out + 3])]);
-    const int cols = order == 0 ? cld(&g.dimR[cld(&g.psi_sec[4 * in + 3])]) : cld(&g.dimL[cld(&g.psi_sec[4 * in])]);
-    const int tm = tile_ext(g.tiles, rows) / 32, tn = tile_ext(g.tiles, cols) / 32;
-#define TNS_CALL_A(a, b) phase_a_task<P, a, b>(g, sm, wk)
-    TNS_TILE_SWITCH(tm, tn, TNS_CALL_A)
-#undef TNS_CALL_A
-  } else {
-    const Item it = load_item(g.items + wk);
-    const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
-#define TNS_CALL_B(a, b) phase_b_item<P, a, b>(g, sm, it, mode)
-    TNS_TILE_SWITCH(tm, tn, TNS_CALL_B)
-#undef TNS_CALL_B
-  }
-}
-
-// FP32: two workgroups per CU (the register budget of 256 per lane)
-template <int P, int PH>
-__global__ __launch_bounds__(GTH, P == TNS_F32 ? 2 : 1) void k_fwd(FwdArgs g) {
-  __shared__ FwdSmem<P> sm;
-  __shared__ int s_work;
-  for (;;) {
-    if (threadIdx.x == 0) s_work = pop_work<PH>(g);
-    __syncthreads();
-    // uniform: the item's metadata then comes through scalar loads, which
-    // leave the vector-memory count (operand loads in flight) alone
-    const int wk = __builtin_amdgcn_readfirstlane(s_work);
-    __syncthreads();
-    if (wk < 0) break;
-    fwd_item<P, PH>(g, sm, wk);
-  }
-}
-
-// --- BF16x3: direct global -> LDS loads into a ring of stages ---------------------
-// A stage holds 128 x 32 tiles of A and of B, high and low halves: four
-// arrays of eight 16-row chunks of 1 KB.  Row r of a chunk keeps its four
-// 16-byte k-vectors at slots kv ^ bswz(r), so that the 16 rows read by one
-// MFMA operand fetch fall into distinct LDS banks.  Loads go straight from
-// global memory into the ring (global_load_lds, 16 bytes per lane), BNS - 1
-// stages ahead of the MFMA work; a stage is consumed after a vector-memory
-// count wait and one barrier.  Out-of-range rows and whole k-vectors beyond
-// K read the zero region; the library's own operands (T, padded psi, the
-// identity) are zero beyond K, so the k-tail of an operator row meets zeros.
-typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
-constexpr int BNS = 4, BBK = 32;
-constexpr int BLOADS = 8;  // global_load_lds per wave and stage
-__device__ inline int bswz(int r) { return (r >> 1) & 3; }
-struct __attribute__((aligned(16))) BfRing {
-  uint16_t s[BNS][4][GM * BBK];  // [stage][A hi, A lo, B hi, B lo][chunk * 512 + slot]
-};
-
-__device__ inline void gl_lds(const void *src, void *dst) {
-  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
-                                   (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
-}
-
-// Waits until at most n_after stages of this wave's ring loads are in flight
-// (vector-memory loads complete in order), then joins the workgroup.  No
-// fence: only the LDS written by this kernel's ring loads is exchanged here.
-__device__ inline void ring_sync(int n_after) {
-  constexpr int E = (7 << 4) | (15 << 8);  // expcnt, lgkmcnt: no wait
-  if (n_after >= 2)
-    __builtin_amdgcn_s_waitcnt(E | (2 * BLOADS & 15) | ((2 * BLOADS >> 4) << 14));
-  else if (n_after == 1)
-    __builtin_amdgcn_s_waitcnt(E | (BLOADS & 15) | ((BLOADS >> 4) << 14));
-  else
-    __builtin_amdgcn_s_waitcnt(E);
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-static_assert(BNS == 4, "ring_sync covers up to two stages in flight after the awaited one");
-
-__device__ inline void bf_issue(BfRing &rg, int buf, const Mat &A, const Mat &B, int r0, int c0, int k0, int K,
-                                const void *zero) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int rin = lane >> 2;
-  const int k = k0 + 8 * ((lane & 3) ^ bswz(rin));
-  const uint16_t *z = reinterpret_cast<const uint16_t *>(zero);
-  const bool kin = k < K;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int chunk = 2 * w + h;
-    const int ra = r0 + 16 * chunk + rin, rb = c0 + 16 * chunk + rin;
-    const bool ia = kin && ra < A.rows, ib = kin && rb < B.rows;
-    const uint16_t *pa = reinterpret_cast<const uint16_t *>(A.p) + (int64_t)ra * A.ld + k;
-    const uint16_t *pb = reinterpret_cast<const uint16_t *>(B.p) + (int64_t)rb * B.ld + k;
-    gl_lds(ia ? pa : z, &rg.s[buf][0][chunk * 512]);
-    gl_lds(ia ? pa + A.lo : z, &rg.s[buf][1][chunk * 512]);
-    gl_lds(ib ? pb : z, &rg.s[buf][2][chunk * 512]);
-    gl_lds(ib ? pb + B.lo : z, &rg.s[buf][3][chunk * 512]);
-  }
-}
-
-// MFMA on one ring stage for a (32 TM) x (32 TN) tile: wave (wm, wn) owns rows
-// chunks wm TM + i and column chunks wn TN + j.
-template <int TM, int TN>
-__device__ inline void bf_mma(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
-  const int off = (l16 * 4 + (g ^ bswz(l16))) * 8;
-  u16x8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    ah[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * TM + i) * 512 + off]);
-    al[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * TM + i) * 512 + off]);
-  }
-#pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    bh[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * TN + j) * 512 + off]);
-    bl[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * TN + j) * 512 + off]);
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      acc[i][j] = mfma_bf(al[i], bh[j], acc[i][j]);
-      acc[i][j] = mfma_bf(ah[i], bl[j], acc[i][j]);
-      acc[i][j] = mfma_bf(ah[i], bh[j], acc[i][j]);
-    }
-}
-
-// Phase B of the BF16x3 path: one item (output tile, chunk of tasks), the
-// tasks' K steps streamed through the ring.
-template <int TM, int TN>
-__device__ inline void bf_item_b_t(const FwdArgs &g, BfRing &rg, const Item &it, int mode) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
-  f4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
-  int ls = it.tb, lj = 0, lK, issued = 0;
-  bool ldone = false;
-  Mat LA, LB;
-  seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
-  auto issue_next = [&]() {
-    bf_issue(rg, issued % BNS, LA, LB, it.p0, it.c0, lj * BBK, lK, g.zero);
-    ++issued;
-    if (++lj * BBK >= lK) {
-      lj = 0;
-      if (++ls < it.te) seg_ops<TNS_BF16X3, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
-      else ldone = true;
-    }
-  };
-  while (!ldone && issued < BNS - 1) issue_next();
-  for (int s = 0; s < issued; ++s) {
-    ring_sync(issued - 1 - s);
-    if (!ldone) issue_next();
-    bf_mma<TM, TN>(rg, s % BNS, acc);
-  }
-  const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
-  float *slot = reinterpret_cast<float *>(g.partial) + cld(&g.slot_off[it.slot]);
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = it.c0 + wn * 16 * TN + j * 16 + l16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
-        if (row < R && col < C) {
-          const int64_t o = mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
-          slot[o] = acc[i][j][v];
-        }
-      }
-    }
-}
-
-__device__ inline void bf_item_b(const FwdArgs &g, BfRing &rg, int wk) {
+template <int P, int KS>
+__device__ inline void ring_item_b(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
   const Item it = load_item(g.items + wk);
   const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
-#define TNS_CALL_B(a, b) bf_item_b_t<a, b>(g, rg, it, mode)
+#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode)
   TNS_TILE_SWITCH(tm, tn, TNS_CALL_B)
 #undef TNS_CALL_B
 }
 
-__global__ __launch_bounds__(GTH) void k_fwd_bfb(FwdArgs g) {
-  __shared__ BfRing rg;
-  __shared__ int s_work;
-  for (;;) {
-    if (threadIdx.x == 0) s_work = pop_work<1>(g);
-    __syncthreads();
-    const int wk = __builtin_amdgcn_readfirstlane(s_work);
-    __syncthreads();
-    if (wk < 0) break;
-    bf_item_b(g, rg, wk);
-  }
-}
-
-
-// Phase A of the BF16x3 path.  A work item is a block of ABT consecutive
-// tasks; all tiles of all its tasks form one stream of K steps, so the ring
-// keeps loading across tile and task boundaries.  The MFMA operand roles are
-// swapped (D = M-side x X-side^T), which gives every lane four consecutive
-// columns of one row of T: the epilogue writes 8-byte groups of the high and
-// low halves.
-constexpr int ABT = 4;
-
-__device__ inline int pop_block(const FwdArgs &g, int64_t nblk) {
-  const int home = blockIdx.x % g.nq;
-  for (int k = 0; k < g.nq; ++k) {
-    const int q = home + k < g.nq ? home + k : home + k - g.nq;
-    const int64_t n = nblk > q ? (nblk - 1 - q) / g.nq + 1 : 0;
-    if (n <= 0) continue;
-    const int j = atomicAdd(g.queue + q, 1);
-    if (j < n) return (int)((int64_t)j * g.nq + q);
-  }
-  return -1;
-}
-
-template <int TM, int TN>
-__device__ inline void bf_mma_t(const BfRing &rg, int buf, f4 (&acc)[4][4]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
-  const int off = (l16 * 4 + (g ^ bswz(l16))) * 8;
-  u16x8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-  for (int j = 0; j < TM; ++j) {
-    ah[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][0][(wm * TM + j) * 512 + off]);
-    al[j] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][1][(wm * TM + j) * 512 + off]);
-  }
-#pragma unroll
-  for (int i = 0; i < TN; ++i) {
-    bh[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][2][(wn * TN + i) * 512 + off]);
-    bl[i] = *reinterpret_cast<const u16x8 *>(&rg.s[buf][3][(wn * TN + i) * 512 + off]);
-  }
-  // acc[i][j]: rows = T columns wn*16*TN + 16 i + .., columns = T rows wm*16*TM + 16 j + ..
-#pragma unroll
-  for (int i = 0; i < TN; ++i)
-#pragma unroll
-    for (int j = 0; j < TM; ++j) {
-      acc[i][j] = mfma_bf(bl[i], ah[j], acc[i][j]);
-      acc[i][j] = mfma_bf(bh[i], al[j], acc[i][j]);
-      acc[i][j] = mfma_bf(bh[i], ah[j], acc[i][j]);
-    }
-}
-
-// Epilogue of a phase-A BF16x3 tile: T = alpha * acc as 8-byte groups of the
-// high and low halves.
-template <int TM, int TN>
-__device__ inline void bf_store_t(const FwdArgs &g, f4 (&acc)[4][4], int t, int r0, int c0, int rows, int ld,
-                                  float alf) {
+// --- phase A: a block of ABT tasks as one stream of K steps ----------------------------
+// Epilogue of a T tile (swapped accumulator: acc[i][j] rows = T columns
+// c0 + wn 16 TN + 16 i + .., columns = T rows r0 + wm 16 TM + 16 j + ..):
+// T = alpha acc, BF16X3 as high / low halves; FP32 and BF16X3 write 4
+// consecutive columns per lane as one vector.
+template <int P, int TM, int TN>
+__device__ inline void ring_store_t(const FwdArgs &g, typename FP<P>::A4 (&acc)[4][4], int t, int r0, int c0,
+                                    int rows, int ld, double alpha) {
+  typedef typename FP<P>::A4 A4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
-  uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + cld(&g.t_off[t]);
+  const int64_t toff = cld(&g.t_off[t]);
 #pragma unroll
   for (int j = 0; j < TM; ++j) {
     const int row = r0 + wm * 16 * TM + j * 16 + l16;
 #pragma unroll
     for (int i = 0; i < TN; ++i) {
-      const int col = c0 + wn * 16 * TN + i * 16 + 4 * lg;
-      if (row < rows && col < ld) {
-        const f4 x = alf * acc[i][j];
-        const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
-        const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]), (__bf16)(x[2] - (float)h[2]),
-                        (__bf16)(x[3] - (float)h[3])};
-        const int64_t o = (int64_t)row * ld + col;
-        *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
-        *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+      const int col0 = c0 + wn * 16 * TN + i * 16;
+      if (row < rows) {
+        if constexpr (P == TNS_F64) {
+          double *Tt = reinterpret_cast<double *>(g.T) + toff + (int64_t)row * ld;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int col = col0 + mrow(acc[i][j], lg, v);
+            if (col < ld) Tt[col] = alpha * acc[i][j][v];
+          }
+        } else {
+          const int col = col0 + 4 * lg;  // FP32 / BF16 accumulators: rows 4 lg .. 4 lg + 3
+          if (col < ld) {
+            const f4 x = (float)alpha * acc[i][j];
+            const int64_t o = toff + (int64_t)row * ld + col;
+            if constexpr (P == TNS_F32) {
+              *reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o) = x;
+            } else {
+              const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+              const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                              (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+              uint16_t *Th = reinterpret_cast<uint16_t *>(g.T);
+              *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
+              *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+            }
+          }
+        }
       }
-      acc[i][j] = vzero<f4>();
+      acc[i][j] = vzero<A4>();
     }
   }
 }
 
-// Phase A of the BF16x3 path: block b of ABT tasks as one stream; each task
-// uses the tile extents of its T dimensions.
-__device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
+// Block b of ABT tasks: all tiles of all its tasks form one stream of K steps,
+// so the ring keeps loading across tile and task boundaries; each task uses
+// the tile extents of its T dimensions.
+template <int P, int KS>
+__device__ inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int b) {
+  typedef typename FP<P>::A4 A4;
+  constexpr int BK = RingL<P, KS>::BK;
   const int t_end = (int)min((int64_t)(b + 1) * ABT, g.ntasks);
   // load cursor: (task, tile row, tile column, k) in stream order
   int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0, ltr, ltc;
   bool ldone = false;
   Mat LA, LB;
   auto load_task = [&]() {
-    seg_ops<TNS_BF16X3, 0>(g, lt, LA, LB, lK, nullptr);
+    seg_ops<P, 0>(g, lt, LA, LB, lK, nullptr);
     ltr = tile_ext(g.tiles, LA.rows);
     ltc = tile_ext(g.tiles, LB.rows);
   };
   load_task();
   auto issue_next = [&]() {
-    bf_issue(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
+    ring_issue<P, KS>(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
     ++issued;
-    if ((lk0 += BBK) < lK) return;
+    if ((lk0 += BK) < lK) return;
     lk0 = 0;
     if ((lc0 += ltc) < LB.rows) return;
     lc0 = 0;
@@ -713,28 +516,26 @@ __device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
   double alpha;
   Mat CA, CB;
   auto compute_task = [&]() {
-    seg_ops<TNS_BF16X3, 0>(g, ct, CA, CB, cK, &alpha);
+    seg_ops<P, 0>(g, ct, CA, CB, cK, &alpha);
     ctm = tile_ext(g.tiles, CA.rows) / 32;
     ctn = tile_ext(g.tiles, CB.rows) / 32;
   };
   compute_task();
-  f4 acc[4][4];
+  A4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<f4>();
+    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
   for (int s = 0; s < issued; ++s) {
-    ring_sync(issued - 1 - s);
+    ring_sync<P, KS>(issued - 1 - s);
     if (!ldone) issue_next();
-#define TNS_CALL_M(a, b) bf_mma_t<a, b>(rg, s % BNS, acc)
+#define TNS_CALL_M(a, b) ring_mma<P, KS, a, b, true>(rg, s % BNS, acc)
     TNS_TILE_SWITCH(ctm, ctn, TNS_CALL_M)
 #undef TNS_CALL_M
-    if ((ck0 += BBK) < cK) continue;
-    // tile (cr0, cc0) of task ct complete
-    {
+    if ((ck0 += BK) < cK) continue;
+    {  // tile (cr0, cc0) of task ct complete
       const int rows = CA.rows, ld = ld8(CB.rows);
-      const float alf = (float)alpha;
-#define TNS_CALL_S(a, b) bf_store_t<a, b>(g, acc, ct, cr0, cc0, rows, ld, alf)
+#define TNS_CALL_S(a, b) ring_store_t<P, a, b>(g, acc, ct, cr0, cc0, rows, ld, alpha)
       TNS_TILE_SWITCH(ctm, ctn, TNS_CALL_S)
 #undef TNS_CALL_S
     }
@@ -747,25 +548,36 @@ __device__ inline void bf_item_a(const FwdArgs &g, BfRing &rg, int b) {
   }
 }
 
-__global__ __launch_bounds__(GTH) void k_fwd_bfa(FwdArgs g) {
-  __shared__ BfRing rg;
+template <int P, int PH>
+__global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
+  __shared__ Ring<P, Geo<P, PH>::KS> rg;
   __shared__ int s_work;
-  const int64_t nblk = (g.ntasks + ABT - 1) / ABT;
   for (;;) {
-    if (threadIdx.x == 0) s_work = pop_block(g, nblk);
+    if (threadIdx.x == 0) s_work = pop_work<PH>(g);
     __syncthreads();
-    const int b = __builtin_amdgcn_readfirstlane(s_work);
+    // uniform: the item's metadata then comes through scalar loads, which
+    // leave the vector-memory count (ring loads in flight) alone
+    const int wk = __builtin_amdgcn_readfirstlane(s_work);
     __syncthreads();
-    if (b < 0) break;
-    bf_item_a(g, rg, b);
+    if (wk < 0) break;
+    if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
+    else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
   }
 }
 
-__global__ void k_ident_bf(uint16_t *p, int n, int ld, int64_t lo) {
+// Identity matrix n x ld (BF16X3: high halves, low halves `lo` further).
+template <int P>
+__global__ void k_ident(void *p, int n, int ld, int64_t lo) {
+  typedef typename FP<P>::E E;
+  E *q = reinterpret_cast<E *>(p);
   GRID_STRIDE(e, (int64_t)n * ld) {
     const int64_t i = e / ld, j = e % ld;
-    p[e] = i == j ? (uint16_t)0x3f80 : (uint16_t)0;
-    p[lo + e] = 0;
+    if constexpr (P == TNS_BF16X3) {
+      q[e] = i == j ? (uint16_t)0x3f80 : (uint16_t)0;
+      q[lo + e] = 0;
+    } else {
+      q[e] = i == j ? E(1) : E(0);
+    }
   }
 }
 
@@ -835,8 +647,7 @@ struct BatchArgs {
   const InstArgs *tab;
   int64_t *cum;     // [2][NQ_MAX][n + 1] work prefix per phase and queue
   int32_t *queue;   // [0, 8) phase A, [8, 16) phase B
-  int32_t n, nq, blocks;  // blocks: phase-A unit is a block of ABT tasks (BF16X3)
-  int32_t pad_;
+  int32_t n, nq;
 };
 
 template <class T>
@@ -849,10 +660,6 @@ __device__ inline T load_words(const T *p) {
   return v;
 }
 
-__device__ inline int64_t blk_count(int64_t ntasks, int nq, int q) {
-  const int64_t nblk = (ntasks + ABT - 1) / ABT;
-  return nblk > q ? (nblk - 1 - q) / nq + 1 : 0;
-}
 
 // Work of instance i on queue q of phase ph (16 threads: one per (ph, q)).
 __global__ void k_batch_cum(BatchArgs b) {
@@ -864,7 +671,7 @@ __global__ void k_batch_cum(BatchArgs b) {
     c[i] = run;
     if (q < b.nq) {
       const FwdArgs &g = b.tab[i].g;
-      if (ph == 0) run += b.blocks ? blk_count(g.ntasks, b.nq, q) : qa_count(g.ntasks, b.nq, q);
+      if (ph == 0) run += blk_count(g.ntasks, b.nq, q);
       else run += g.qbase[q + 1] - g.qbase[q];
     }
   }
@@ -889,7 +696,7 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
     const int64_t loc = j - c[lo];
     *inst = lo;
     if (ph == 1) *wk = (int)(b.tab[lo].g.qbase[q] + loc);
-    else *wk = b.blocks ? (int)(loc * b.nq + q) : (int)qa_task(b.nq, q, loc);
+    else *wk = (int)(loc * b.nq + q);
     return;
   }
   *inst = -1;
@@ -897,8 +704,8 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
 }
 
 template <int P, int PH>
-__global__ __launch_bounds__(GTH, P == TNS_F32 ? 2 : 1) void k_fwd_batch(BatchArgs b) {
-  __shared__ FwdSmem<P> sm;
+__global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b) {
+  __shared__ Ring<P, Geo<P, PH>::KS> rg;
   __shared__ int s_w[2];
   for (;;) {
     if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
@@ -907,23 +714,8 @@ __global__ __launch_bounds__(GTH, P == TNS_F32 ? 2 : 1) void k_fwd_batch(BatchAr
     __syncthreads();
     if (inst < 0) break;
     const FwdArgs g = load_words(&b.tab[inst].g);
-    fwd_item<P, PH>(g, sm, wk);
-  }
-}
-
-template <int PH>
-__global__ __launch_bounds__(GTH) void k_fwd_bf_batch(BatchArgs b) {
-  __shared__ BfRing rg;
-  __shared__ int s_w[2];
-  for (;;) {
-    if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
-    __syncthreads();
-    const int inst = __builtin_amdgcn_readfirstlane(s_w[0]), wk = __builtin_amdgcn_readfirstlane(s_w[1]);
-    __syncthreads();
-    if (inst < 0) break;
-    const FwdArgs g = load_words(&b.tab[inst].g);
-    if (PH == 0) bf_item_a(g, rg, wk);
-    else bf_item_b(g, rg, wk);
+    if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
+    else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
   }
 }
 
@@ -980,15 +772,15 @@ static size_t region(int64_t n, tns_prec p) {
   return align_up(b + 64, 256);
 }
 
-// Identity matrix of the BF16X3 path: maxdim x ld8(maxdim).
+// Identity matrix operand (blocks of identity operators): maxdim x ld8(maxdim).
 static int64_t ident_elems(const Plan &p) { return (int64_t)p.maxdim * ld8(p.maxdim); }
 
 // Workspace of the forward product: [queue counters, zero bytes | partial
-// slots | T | padded psi | padded psi^T | (BF16X3) identity].
+// slots | T | padded psi | padded psi^T | identity].
 size_t fwd_workspace(const Plan &p, tns_prec prec) {
   return 256 + align_up((size_t)std::max<int64_t>(p.fwd.partial_elems, 1) * (prec == TNS_F64 ? 8 : 4), 256) +
          region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec) +
-         (prec == TNS_BF16X3 ? region(ident_elems(p), prec) : 0);
+         region(ident_elems(p), prec);
 }
 
 // queue counters (bytes 0..63) and the 64-byte zero region that out-of-range
@@ -1049,27 +841,17 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   const Sched &S = p.fwd;
   const FwdArgs g = fwd_args<P>(p, ops, w);
   hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, g.queue);
-  if (P == TNS_BF16X3)
-    hipLaunchKernelGGL(k_ident_bf, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, (uint16_t *)g.ident, p.maxdim,
-                       ld8(p.maxdim), g.ident_lo);
+  hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, const_cast<void *>(g.ident),
+                     p.maxdim, ld8(p.maxdim), g.ident_lo);
   if (p.nS > 0)
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
                        p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt), g.pp_lo,
                        g.pt_lo);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
-  if (p.ntasks > 0) {
-    if constexpr (P == TNS_BF16X3)
-      hipLaunchKernelGGL(k_fwd_bfa, dim3(grid_of(k_fwd_bfa, p.n_cu)), dim3(GTH), 0, st, g);
-    else
-      hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
-  }
+  if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
-  if (p.ntasks > 0 && S.nitems > 0) {
-    if constexpr (P == TNS_BF16X3)
-      hipLaunchKernelGGL(k_fwd_bfb, dim3(grid_of(k_fwd_bfb, p.n_cu)), dim3(GTH), 0, st, g);
-    else
-      hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
-  }
+  if (p.ntasks > 0 && S.nitems > 0)
+    hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[2], st));
   return launch_epilogue_psi(p, P == TNS_F64, g.partial, sigma, beta, st);
 }
@@ -1081,12 +863,12 @@ static int max_maxdim(const tns_tasklist *const *tls, int n) {
   return md;
 }
 
-// [queue counters, zero bytes | argument table | prefix sums | (BF16X3) shared
+// [queue counters, zero bytes | argument table | prefix sums | shared
 // identity | one forward workspace per instance]
 static size_t batch_bytes(const tns_tasklist *const *tls, int n, tns_prec prec) {
   size_t b = 256 + align_up((size_t)n * sizeof(InstArgs), 256) + align_up((size_t)2 * NQ_MAX * (n + 1) * 8, 256);
   const int md = max_maxdim(tls, n);
-  if (prec == TNS_BF16X3) b += region((int64_t)md * ld8(md), prec);
+  b += region((int64_t)md * ld8(md), prec);
   for (int i = 0; i < n; ++i) b += fwd_workspace(plan_of(tls[i]), prec);
   return b;
 }
@@ -1106,7 +888,7 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
   const int md = max_maxdim(tls, n);
   const int64_t id_elems = (int64_t)md * ld8(md);
   void *ident = c;
-  if (P == TNS_BF16X3) c += region(id_elems, prec);
+  c += region(id_elems, prec);
   // instances by descending cost: the big ones start first, the small ones fill the tail
   std::vector<int> perm(n);
   for (int i = 0; i < n; ++i) perm[i] = i;
@@ -1142,7 +924,6 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
   BatchArgs b;
   memset(&b, 0, sizeof(b));
   b.tab = tab; b.cum = cum; b.queue = queue; b.n = n; b.nq = plan_of(tls[0]).fwd.nq;
-  b.blocks = P == TNS_BF16X3;
 
   hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, queue);
   for (int k0 = 0; k0 < n; k0 += ARGS_PER_PUT) {
@@ -1154,25 +935,15 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
     hipLaunchKernelGGL(k_put_args, dim3(1), dim3(64), 0, st, pa, tab);
   }
   hipLaunchKernelGGL(k_batch_cum, dim3(1), dim3(2 * NQ_MAX), 0, st, b);
-  if (P == TNS_BF16X3)
-    hipLaunchKernelGGL(k_ident_bf, dim3(nblocks(id_elems)), dim3(256), 0, st, (uint16_t *)ident, md, ld8(md),
-                       lo_of(id_elems));
+  hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(id_elems)), dim3(256), 0, st, ident, md, ld8(md), lo_of(id_elems));
   typedef typename std::conditional<P == TNS_F64, double, float>::type In;
   hipLaunchKernelGGL((k_pad_psi_batch<In, P>), dim3(max_nS, 8, n), dim3(256), 0, st, tab);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
-  if (any_tasks) {
-    if constexpr (P == TNS_BF16X3)
-      hipLaunchKernelGGL(k_fwd_bf_batch<0>, dim3(grid_of(k_fwd_bf_batch<0>, n_cu)), dim3(GTH), 0, st, b);
-    else
-      hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);
-  }
+  if (any_tasks)
+    hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
-  if (any_tasks && any_items) {
-    if constexpr (P == TNS_BF16X3)
-      hipLaunchKernelGGL(k_fwd_bf_batch<1>, dim3(grid_of(k_fwd_bf_batch<1>, n_cu)), dim3(GTH), 0, st, b);
-    else
-      hipLaunchKernelGGL((k_fwd_batch<P, 1>), dim3(grid_of(k_fwd_batch<P, 1>, n_cu)), dim3(GTH), 0, st, b);
-  }
+  if (any_tasks && any_items)
+    hipLaunchKernelGGL((k_fwd_batch<P, 1>), dim3(grid_of(k_fwd_batch<P, 1>, n_cu)), dim3(GTH), 0, st, b);
   if (ev) TNS_HIP(hipEventRecord(ev[2], st));
   const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_dim + 255) / 256);
   hipLaunchKernelGGL(k_epilogue_batch<Acc>, dim3(gx, n), dim3(256), 0, st, tab);
