@@ -87,7 +87,12 @@ struct FwdArgs {
   const void *ident;  // identity matrix maxdim x ld8(maxdim) (BF16X3: hi; lo `ident_lo` further)
   int64_t ident_lo;
   int32_t ident_ld;
-  uint32_t tiles;     // tile table (phase A picks a task's tile from its T dimensions)
+  uint32_t tiles;     // tile table
+  // phase-A panels
+  const Item *a_items;
+  const int64_t *a_qbase, *a_tb, *a_gch, *a_ch;
+  const int32_t *a_idx;
+  const ChunkRec *recs;  // chunk sources, written before phase A
 };
 
 // --- per-precision tile parameters ---------------------------------------------
@@ -163,32 +168,19 @@ __device__ inline void seg_ops(const FwdArgs &g, int t, Mat &A, Mat &B, int &K, 
 }
 
 // --- work queues --------------------------------------------------------------------
-// Phase A: blocks of ABT consecutive tasks, block b on queue b mod nq.
-// Phase B: the schedule's items, queue q = items[qbase[q], qbase[q+1]).
-constexpr int ABT = 4;
-
-__device__ inline int64_t blk_count(int64_t ntasks, int nq, int q) {
-  const int64_t nblk = (ntasks + ABT - 1) / ABT;
-  return nblk > q ? (nblk - 1 - q) / nq + 1 : 0;
-}
-
+// Phase A: panel items, phase B: the schedule's items; queue q of a phase is
+// items[qbase[q], qbase[q+1]).
 // Thread 0: next work id of phase PH (own XCD queue first), -1 when drained.
 template <int PH>
 __device__ inline int pop_work(const FwdArgs &g) {
   const int home = blockIdx.x % g.nq;
+  const int64_t *qb = PH == 0 ? g.a_qbase : g.qbase;
   for (int k = 0; k < g.nq; ++k) {
     const int q = home + k < g.nq ? home + k : home + k - g.nq;
-    if (PH == 0) {
-      const int64_t n = blk_count(g.ntasks, g.nq, q);
-      if (n <= 0) continue;
-      const int j = atomicAdd(g.queue + q, 1);
-      if (j < n) return (int)((int64_t)j * g.nq + q);
-    } else {
-      const int64_t b = g.qbase[q], n = g.qbase[q + 1] - b;
-      if (n <= 0) continue;
-      const int j = atomicAdd(g.queue + 8 + q, 1);
-      if (j < n) return (int)(b + j);
-    }
+    const int64_t b = qb[q], n = qb[q + 1] - b;
+    if (n <= 0) continue;
+    const int j = atomicAdd(g.queue + 8 * PH + q, 1);
+    if (j < n) return (int)(b + j);
   }
   return -1;
 }
@@ -250,10 +242,35 @@ __device__ inline void ring_sync(int n_after) {
 }
 static_assert(BNS == 4, "ring_sync covers up to two stages in flight after the awaited one");
 
-// Stage `buf` <- rows [r0, r0 + 128) of A and [c0, c0 + 128) of B, k in [k0, k0 + BK).
+// Source of one 16-row chunk of the A operand: rows p + i * ld, i < vrows
+// (BF16X3: low halves `lo` elements further).
+struct CSrc {
+  const void *p;
+  int64_t lo;
+  int32_t ld, vrows;
+};
+
+// The two A chunks a wave loads (chunks w and w + 4 of the 8) from rows
+// [r0, rlim) of M.
+template <int P>
+__device__ inline void mat_srcs(const Mat &M, int r0, int rlim, CSrc (&as)[2]) {
+  typedef typename FP<P>::E E;
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int r = r0 + 16 * (w + 4 * u);
+    as[u].p = reinterpret_cast<const E *>(M.p) + (int64_t)r * M.ld;
+    as[u].lo = M.lo;
+    as[u].ld = M.ld;
+    as[u].vrows = min(16, rlim - r);
+  }
+}
+
+// Stage `buf` <- the A chunks of `as` and rows [c0, blim) of B (rows of the
+// 128-row window beyond blim read zeros), k in [k0, k0 + BK).
 template <int P, int KS>
-__device__ inline void ring_issue(Ring<P, KS> &rg, int buf, const Mat &A, const Mat &B, int r0, int c0, int k0,
-                                  int K, const void *zero) {
+__device__ inline void ring_issue(Ring<P, KS> &rg, int buf, const CSrc (&as)[2], const Mat &B, int c0, int blim,
+                                  int k0, int K, const void *zero) {
   typedef typename FP<P>::E E;
   constexpr int VEC = RingP<P>::VEC, L = RingL<P, KS>::LOADS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -274,10 +291,17 @@ __device__ inline void ring_issue(Ring<P, KS> &rg, int buf, const Mat &A, const 
       lo = false;
       k += (h - KS * (int)isB) * 4 * VEC;  // k-half
     }
-    const int row = (isB ? c0 : r0) + 16 * (c - 8 * h) + rin;
-    const Mat &M = isB ? B : A;
-    const bool in = k < K && row < M.rows;
-    const E *src = reinterpret_cast<const E *>(M.p) + (lo ? M.lo : 0) + (int64_t)row * M.ld + k;
+    const E *src;
+    bool in;
+    if (!isB) {  // chunk c - 8 h = w + 4 (u & 1) of A
+      const CSrc &S = as[u & 1];
+      in = k < K && rin < S.vrows;
+      src = reinterpret_cast<const E *>(S.p) + (lo ? S.lo : 0) + (int64_t)rin * S.ld + k;
+    } else {
+      const int row = c0 + 16 * (c - 8 * h) + rin;
+      in = k < K && row < blim;
+      src = reinterpret_cast<const E *>(B.p) + (lo ? B.lo : 0) + (int64_t)row * B.ld + k;
+    }
     gl_lds(in ? src : z, &rg.s[buf][c * 1024]);
   }
 }
@@ -385,16 +409,22 @@ __device__ inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const It
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  int ls = it.tb, lj = 0, lK, issued = 0;
+  int ls = it.tb, lj = 0, lK, issued = 0, blim;
   bool ldone = false;
   Mat LA, LB;
-  seg_ops<P, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+  CSrc as[2];
+  auto load_seg = [&]() {
+    seg_ops<P, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+    mat_srcs<P>(LA, it.p0, min(LA.rows, it.p0 + 32 * TM), as);
+    blim = min(LB.rows, it.c0 + 32 * TN);
+  };
+  load_seg();
   auto issue_next = [&]() {
-    ring_issue<P, KS>(rg, issued % BNS, LA, LB, it.p0, it.c0, lj * BK, lK, g.zero);
+    ring_issue<P, KS>(rg, issued % BNS, as, LB, it.c0, blim, lj * BK, lK, g.zero);
     ++issued;
     if (++lj * BK >= lK) {
       lj = 0;
-      if (++ls < it.te) seg_ops<P, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
+      if (++ls < it.te) load_seg();
       else ldone = true;
     }
   };
@@ -431,96 +461,132 @@ __device__ inline void ring_item_b(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
 #undef TNS_CALL_B
 }
 
-// --- phase A: a block of ABT tasks as one stream of K steps ----------------------------
-// Epilogue of a T tile (swapped accumulator: acc[i][j] rows = T columns
-// c0 + wn 16 TN + 16 i + .., columns = T rows r0 + wm 16 TM + 16 j + ..):
-// T = alpha acc, BF16X3 as high / low halves; FP32 and BF16X3 write 4
-// consecutive columns per lane as one vector.
-template <int P, int TM, int TN>
-__device__ inline void ring_store_t(const FwdArgs &g, typename FP<P>::A4 (&acc)[4][4], int t, int r0, int c0,
-                                    int rows, int ld, double alpha) {
-  typedef typename FP<P>::A4 A4;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
-  const int64_t toff = cld(&g.t_off[t]);
+// --- phase A: row tiles of a panel as one stream of K steps ---------------------------
+// A panel item covers chunks [p0, p0 + np) of its panel's stacked rows (whole
+// 128-row tiles) and columns [c0, c0 + 32 TN) of T; its row tiles share the
+// right operand (the padded psi sector), and the ring keeps loading across
+// tile boundaries.
+
+// Sources of the two A chunks of this wave in the tile starting at chunk ch
+// (chunks at or beyond ch_end are empty).
+template <int P>
+__device__ inline void chunk_srcs(const FwdArgs &g, int ch, int ch_end, CSrc (&as)[2]) {
+  typedef typename FP<P>::E E;
+  const int w = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < TM; ++j) {
-    const int row = r0 + wm * 16 * TM + j * 16 + l16;
-#pragma unroll
-    for (int i = 0; i < TN; ++i) {
-      const int col0 = c0 + wn * 16 * TN + i * 16;
-      if (row < rows) {
-        if constexpr (P == TNS_F64) {
-          double *Tt = reinterpret_cast<double *>(g.T) + toff + (int64_t)row * ld;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int col = col0 + mrow(acc[i][j], lg, v);
-            if (col < ld) Tt[col] = alpha * acc[i][j][v];
-          }
-        } else {
-          const int col = col0 + 4 * lg;  // FP32 / BF16 accumulators: rows 4 lg .. 4 lg + 3
-          if (col < ld) {
-            const f4 x = (float)alpha * acc[i][j];
-            const int64_t o = toff + (int64_t)row * ld + col;
-            if constexpr (P == TNS_F32) {
-              *reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o) = x;
-            } else {
-              const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
-              const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
-                              (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
-              uint16_t *Th = reinterpret_cast<uint16_t *>(g.T);
-              *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
-              *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
-            }
-          }
-        }
+  for (int u = 0; u < 2; ++u) {
+    const int c = __builtin_amdgcn_readfirstlane(ch + w + 4 * u);  // uniform: scalar loads
+    as[u].p = g.zero;
+    as[u].lo = 0;
+    as[u].ld = 0;
+    as[u].vrows = 0;
+    if (c < ch_end) {
+      const ChunkRec *r = g.recs + c;
+      const int64_t off = cld(&r->off);
+      as[u].vrows = cld(&r->vrows);
+      if (off >= 0) {
+        as[u].p = reinterpret_cast<const E *>(g.ops) + off;
+        as[u].lo = g.ops_lo;
+        as[u].ld = cld(&r->ld);
+      } else {  // identity side: rows of the identity matrix
+        as[u].p = reinterpret_cast<const E *>(g.ident) + (-1 - off) * g.ident_ld;
+        as[u].lo = g.ident_lo;
+        as[u].ld = g.ident_ld;
       }
-      acc[i][j] = vzero<A4>();
     }
   }
 }
 
-// Block b of ABT tasks: all tiles of all its tasks form one stream of K steps,
-// so the ring keeps loading across tile and task boundaries; each task uses
-// the tile extents of its T dimensions.
-template <int P, int KS>
-__device__ inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int b) {
+// Epilogue of a stacked T tile starting at chunk ch (swapped accumulator:
+// acc[i][j] rows = T columns c0 + wn 16 TN + 16 i + .., columns = the rows of
+// chunk ch + 4 wm + j).  Row r of chunk c lies at tbase + (16 c + r) ldT;
+// rows beyond the chunk's task are not stored.  FP32 and BF16X3 write 4
+// consecutive columns per lane as one vector.
+template <int P, int TN>
+__device__ inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[4][4], int ch, int ch_end,
+                                      int64_t tbase, int c0, int ldT) {
   typedef typename FP<P>::A4 A4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = __builtin_amdgcn_readfirstlane(ch + 4 * wm + j);
+    if (c < ch_end) {
+      const ChunkRec *r = g.recs + c;
+      const int vr = cld(&r->vrows);
+      const double alpha = cld(&r->alpha);
+      const int64_t orow = tbase + ((int64_t)c * PCH + l16) * ldT;
+      if (l16 < vr) {
+#pragma unroll
+        for (int i = 0; i < TN; ++i) {
+          const int col0 = c0 + wn * 16 * TN + i * 16;
+          if constexpr (P == TNS_F64) {
+            double *Tt = reinterpret_cast<double *>(g.T) + orow;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int col = col0 + mrow(acc[i][j], lg, v);
+              if (col < ldT) Tt[col] = alpha * acc[i][j][v];
+            }
+          } else {
+            const int col = col0 + 4 * lg;  // FP32 / BF16 accumulators: rows 4 lg .. 4 lg + 3
+            if (col < ldT) {
+              const f4 x = (float)alpha * acc[i][j];
+              const int64_t o = orow + col;
+              if constexpr (P == TNS_F32) {
+                *reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o) = x;
+              } else {
+                const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+                const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                                (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+                uint16_t *Th = reinterpret_cast<uint16_t *>(g.T);
+                *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
+                *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i][j] = vzero<A4>();
+  }
+}
+
+template <int P, int KS, int TN>
+__device__ inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it) {
+  typedef typename FP<P>::A4 A4;
+  typedef typename FP<P>::E E;
   constexpr int BK = RingL<P, KS>::BK;
-  const int t_end = (int)min((int64_t)(b + 1) * ABT, g.ntasks);
-  // load cursor: (task, tile row, tile column, k) in stream order
-  int lt = b * ABT, lr0 = 0, lc0 = 0, lk0 = 0, lK, issued = 0, ltr, ltc;
+  const int G = it.grp, sec = G >> 1, cls = G & 1;
+  const int m = cld(&g.dimL[cld(&g.psi_sec[4 * sec])]), n = cld(&g.dimR[cld(&g.psi_sec[4 * sec + 3])]);
+  const int K = cls ? n : m, N = cls ? m : n, ldT = ld8(N);
+  Mat B;  // B(j, k) = M(k, j): class 0 A_s^T rows, class 1 A_s rows
+  if (cls == 0) {
+    B.p = reinterpret_cast<const E *>(g.pt) + cld(&g.pt_off[sec]);
+    B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n;
+  } else {
+    B.p = reinterpret_cast<const E *>(g.pp) + cld(&g.pp_off[sec]);
+    B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m;
+  }
+  const int blim = min(B.rows, it.c0 + 32 * TN);
+  const int ch_end = it.p0 + it.np;
+  const int64_t tbase = cld(&g.a_tb[G]) - cld(&g.a_gch[G]) * PCH * ldT;
+  // load cursor: (tile's first chunk, k)
+  int lch = it.p0, lk0 = 0, issued = 0;
   bool ldone = false;
-  Mat LA, LB;
-  auto load_task = [&]() {
-    seg_ops<P, 0>(g, lt, LA, LB, lK, nullptr);
-    ltr = tile_ext(g.tiles, LA.rows);
-    ltc = tile_ext(g.tiles, LB.rows);
-  };
-  load_task();
+  CSrc as[2];
+  chunk_srcs<P>(g, lch, ch_end, as);
   auto issue_next = [&]() {
-    ring_issue<P, KS>(rg, issued % BNS, LA, LB, lr0, lc0, lk0, lK, g.zero);
+    ring_issue<P, KS>(rg, issued % BNS, as, B, it.c0, blim, lk0, K, g.zero);
     ++issued;
-    if ((lk0 += BK) < lK) return;
+    if ((lk0 += BK) < K) return;
     lk0 = 0;
-    if ((lc0 += ltc) < LB.rows) return;
-    lc0 = 0;
-    if ((lr0 += ltr) < LA.rows) return;
-    lr0 = 0;
-    if (++lt < t_end) load_task();
+    if ((lch += PTILE_CH) < ch_end) chunk_srcs<P>(g, lch, ch_end, as);
     else ldone = true;
   };
   while (!ldone && issued < BNS - 1) issue_next();
   // compute cursor, BNS - 1 steps behind
-  int ct = b * ABT, cr0 = 0, cc0 = 0, ck0 = 0, cK, ctm, ctn;
-  double alpha;
-  Mat CA, CB;
-  auto compute_task = [&]() {
-    seg_ops<P, 0>(g, ct, CA, CB, cK, &alpha);
-    ctm = tile_ext(g.tiles, CA.rows) / 32;
-    ctn = tile_ext(g.tiles, CB.rows) / 32;
-  };
-  compute_task();
+  int cch = it.p0, ck0 = 0;
   A4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -529,23 +595,47 @@ __device__ inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int b) {
   for (int s = 0; s < issued; ++s) {
     ring_sync<P, KS>(issued - 1 - s);
     if (!ldone) issue_next();
-#define TNS_CALL_M(a, b) ring_mma<P, KS, a, b, true>(rg, s % BNS, acc)
-    TNS_TILE_SWITCH(ctm, ctn, TNS_CALL_M)
-#undef TNS_CALL_M
-    if ((ck0 += BK) < cK) continue;
-    {  // tile (cr0, cc0) of task ct complete
-      const int rows = CA.rows, ld = ld8(CB.rows);
-#define TNS_CALL_S(a, b) ring_store_t<P, a, b>(g, acc, ct, cr0, cc0, rows, ld, alpha)
-      TNS_TILE_SWITCH(ctm, ctn, TNS_CALL_S)
-#undef TNS_CALL_S
-    }
+    ring_mma<P, KS, 4, TN, true>(rg, s % BNS, acc);
+    if ((ck0 += BK) < K) continue;
     ck0 = 0;
-    if ((cc0 += 32 * ctn) < CB.rows) continue;
-    cc0 = 0;
-    if ((cr0 += 32 * ctm) < CA.rows) continue;
-    cr0 = 0;
-    if (++ct < t_end) compute_task();
+    ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, ldT);
+    cch += PTILE_CH;
   }
+}
+
+template <int P, int KS>
+__device__ inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
+  const Item it = load_item(g.a_items + wk);
+  switch ((it.mode >> 16) & 0xff) {
+    case 1: ring_item_a_t<P, KS, 1>(g, rg, it); break;
+    case 2: ring_item_a_t<P, KS, 2>(g, rg, it); break;
+    default: ring_item_a_t<P, KS, 4>(g, rg, it); break;
+  }
+}
+
+// Chunk sources of the panel-order position i (one thread per task).
+__device__ inline void chunk_recs_of(const FwdArgs &g, int64_t i) {
+  const int t = g.a_idx[i];
+  const tns_task &k = g.tasks[t];
+  const int *so = g.psi_sec + 4 * k.out;
+  const int rows = k.order == 0 ? g.dimL[so[0]] : g.dimR[so[3]];
+  const int blk = k.order == 0 ? k.lblk : k.rblk;
+  ChunkRec *r = const_cast<ChunkRec *>(g.recs) + g.a_ch[i];
+  const int64_t bo = blk >= 0 ? g.blk_off[blk] : 0;
+  const int ld = blk >= 0 ? g.blk_ld[blk] : 0;
+  for (int j = 0; j * PCH < rows; ++j) {
+    ChunkRec x;
+    x.off = blk >= 0 ? bo + (int64_t)j * PCH * ld : -1 - (int64_t)j * PCH;
+    x.ld = ld;
+    x.vrows = min(PCH, rows - j * PCH);
+    x.alpha = k.alpha;
+    x.pad_ = 0;
+    r[j] = x;
+  }
+}
+
+__global__ void k_chunk_recs(FwdArgs g) {
+  GRID_STRIDE(i, g.ntasks) chunk_recs_of(g, i);
 }
 
 template <int P, int PH>
@@ -670,9 +760,8 @@ __global__ void k_batch_cum(BatchArgs b) {
   for (int i = 0; i < b.n; ++i) {
     c[i] = run;
     if (q < b.nq) {
-      const FwdArgs &g = b.tab[i].g;
-      if (ph == 0) run += blk_count(g.ntasks, b.nq, q);
-      else run += g.qbase[q + 1] - g.qbase[q];
+      const int64_t *qb = ph == 0 ? b.tab[i].g.a_qbase : b.tab[i].g.qbase;
+      run += qb[q + 1] - qb[q];
     }
   }
   c[b.n] = run;
@@ -695,8 +784,7 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
     }
     const int64_t loc = j - c[lo];
     *inst = lo;
-    if (ph == 1) *wk = (int)(b.tab[lo].g.qbase[q] + loc);
-    else *wk = (int)(loc * b.nq + q);
+    *wk = (int)((ph == 0 ? b.tab[lo].g.a_qbase : b.tab[lo].g.qbase)[q] + loc);
     return;
   }
   *inst = -1;
@@ -717,6 +805,12 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b
     if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
     else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
   }
+}
+
+__global__ void k_chunk_recs_batch(const InstArgs *tab) {
+  const FwdArgs &g = tab[blockIdx.y].g;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.ntasks; i += (int64_t)gridDim.x * blockDim.x)
+    chunk_recs_of(g, i);
 }
 
 template <class In, int P>
@@ -776,11 +870,12 @@ static size_t region(int64_t n, tns_prec p) {
 static int64_t ident_elems(const Plan &p) { return (int64_t)p.maxdim * ld8(p.maxdim); }
 
 // Workspace of the forward product: [queue counters, zero bytes | partial
-// slots | T | padded psi | padded psi^T | identity].
+// slots | T | padded psi | padded psi^T | identity | chunk sources].
+static size_t recs_bytes(const Plan &p) { return align_up((size_t)std::max<int64_t>(p.pa.nchunks, 1) * sizeof(ChunkRec), 256); }
 size_t fwd_workspace(const Plan &p, tns_prec prec) {
   return 256 + align_up((size_t)std::max<int64_t>(p.fwd.partial_elems, 1) * (prec == TNS_F64 ? 8 : 4), 256) +
          region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec) +
-         region(ident_elems(p), prec);
+         region(ident_elems(p), prec) + recs_bytes(p);
 }
 
 // queue counters (bytes 0..63) and the 64-byte zero region that out-of-range
@@ -817,6 +912,8 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   void *pt = c;
   c += region(p.pt_elems, prec);
   void *id = c;
+  c += region(ident_elems(p), prec);
+  void *recs = c;
   FwdArgs g;
   memset(&g, 0, sizeof(g));
   g.tasks = p.tasks; g.ntasks = p.ntasks;
@@ -832,6 +929,9 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   g.zero = w + 64;
   g.ident = id; g.ident_lo = lo_of(ident_elems(p)); g.ident_ld = ld8(p.maxdim);
   g.tiles = p.tiles;
+  g.a_items = p.pa.items; g.a_qbase = p.pa.qbase; g.a_tb = p.pa.tb; g.a_gch = p.pa.gch;
+  g.a_ch = p.pa.ch; g.a_idx = p.pa.idx;
+  g.recs = reinterpret_cast<const ChunkRec *>(recs);
   return g;
 }
 
@@ -847,6 +947,7 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
                        p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt), g.pp_lo,
                        g.pt_lo);
+  if (p.ntasks > 0) hipLaunchKernelGGL(k_chunk_recs, dim3(nblocks(p.ntasks)), dim3(256), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
@@ -938,6 +1039,7 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
   hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(id_elems)), dim3(256), 0, st, ident, md, ld8(md), lo_of(id_elems));
   typedef typename std::conditional<P == TNS_F64, double, float>::type In;
   hipLaunchKernelGGL((k_pad_psi_batch<In, P>), dim3(max_nS, 8, n), dim3(256), 0, st, tab);
+  hipLaunchKernelGGL(k_chunk_recs_batch, dim3(64, n), dim3(256), 0, st, tab);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (any_tasks)
     hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);

@@ -379,16 +379,181 @@ __global__ void k_sched_totals(Sched S) {
   S.scalars[3] = S.slot_off[nch];
 }
 
-// Sizes of the forward intermediates T_k (output rows x ld8(K2), K2 = n for
-// class 0 and m for class 1), scanned in place into offsets afterwards.
-__global__ void k_t_sizes(Plan p, int64_t ntasks) {
+// --- phase-A panels ----------------------------------------------------------------
+// Inner dimension K and columns N of panel G (= 2 s + class): class 0 forms
+// L_k A_s (K = m, N = n), class 1 R_k A_s^T (K = n, N = m).
+__device__ inline void panel_dims(const Plan &p, int G, int *K, int *N) {
+  const int s = G >> 1;
+  const int m = p.dimL[p.psi_sec[4 * s]], n = p.dimR[p.psi_sec[4 * s + 3]];
+  *K = (G & 1) ? n : m;
+  *N = (G & 1) ? m : n;
+}
+
+// Rows of T_k: the output's left dimension (class 0) or right dimension (class 1).
+__device__ inline int task_t_rows(const Plan &p, const tns_task &t) {
+  return t.order == 0 ? p.dimL[p.psi_sec[4 * t.out]] : p.dimR[p.psi_sec[4 * t.out + 3]];
+}
+
+__global__ void k_pan_keys(Plan p, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntasks) return;
-  const tns_task k = p.tasks[t];
-  const int *so = p.psi_sec + 4 * k.out, *si = p.psi_sec + 4 * k.in;
-  const int64_t rows = k.order == 0 ? p.dimL[so[0]] : p.dimR[so[3]];
-  const int k2 = k.order == 0 ? p.dimR[si[3]] : p.dimL[si[0]];
-  p.t_off[t] = rows * ld8(k2);
+  if (t >= n) return;
+  p.pa.keys_in[t] = 2 * p.tasks[t].in + p.tasks[t].order;
+  p.pa.vals_in[t] = (int32_t)t;
+}
+
+// grp[G] = first panel-order position of panel G (from the sorted keys).
+__global__ void k_pan_bounds(Plan p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  const int prev = i == 0 ? -1 : p.pa.keys_out[i - 1];
+  const int cur = i == n ? p.pa.ngroups : p.pa.keys_out[i];
+  for (int G = prev + 1; G <= cur; ++G) p.pa.grp[G] = i;
+}
+
+// Chunks of each panel-order position (scanned into ch afterwards).
+__global__ void k_pan_nch(Plan p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p.pa.scratch[i] = (task_t_rows(p, p.tasks[p.pa.idx[i]]) + PCH - 1) / PCH;
+}
+
+// Per panel: first chunk, intermediate size (scanned into tb afterwards), cost.
+__global__ void k_pan_sizes(Plan p) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (G > A.ngroups) return;
+  A.gch[G] = A.ch[A.grp[G]];
+  if (G == A.ngroups) return;
+  int K, N;
+  panel_dims(p, G, &K, &N);
+  const int64_t nch = A.ch[A.grp[G + 1]] - A.ch[A.grp[G]];
+  A.scratch[G] = nch * PCH * ld8(N);
+  A.cost[G] = 2 * nch * PCH * (int64_t)N * K;
+}
+
+// Offsets of the intermediates: T_k at its chunk rows inside its panel's matrix.
+__global__ void k_pan_toff(Plan p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Panels &A = p.pa;
+  const int G = A.keys_out[i];
+  int K, N;
+  panel_dims(p, G, &K, &N);
+  p.t_off[A.idx[i]] = A.tb[G] + (A.ch[i] - A.gch[G]) * PCH * ld8(N);
+}
+
+// Panel cost order (descending) and work queue: boustrophedon over the ranks.
+__global__ void k_pan_rank_keys(Plan p) {
+  const int64_t G = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (G >= A.ngroups) return;
+  A.ikeys_in[G] = ~(uint64_t)A.cost[G];
+  A.ivals_in[G] = (int32_t)G;
+}
+__global__ void k_pan_rank(Plan p) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (r >= A.ngroups) return;
+  const int G = A.ivals_out[r];
+  const int64_t round = r / A.nq, pos = r % A.nq;
+  A.rank[G] = (int32_t)r;
+  A.xcd[G] = (int32_t)((round & 1) ? A.nq - 1 - pos : pos);
+}
+
+// Work items of a panel: column tiles (extent from the tile table) x row
+// pieces of whole GM-row tiles, so that an item costs about `target`.
+__device__ inline void pan_split(const Plan &p, int G, int *tc, int *ncol, int *nrt, int *pieces) {
+  const Panels &A = p.pa;
+  int K, N;
+  panel_dims(p, G, &K, &N);
+  const int64_t nch = A.gch[G + 1] - A.gch[G];
+  *tc = tile_ext(A.tiles, N);
+  *ncol = nch > 0 ? (N + *tc - 1) / *tc : 0;
+  *nrt = (int)((nch + PTILE_CH - 1) / PTILE_CH);
+  const int64_t cost_col = 2 * (int64_t)*nrt * GM * *tc * K;
+  const int64_t target = A.scalars[1];
+  int64_t pc = target > 0 ? (cost_col + target - 1) / target : 1;
+  if (pc > *nrt) pc = *nrt;
+  *pieces = pc < 1 ? 1 : (int)pc;
+}
+
+__global__ void k_pan_total(Plan p) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (G >= A.ngroups) return;
+  int K, N;
+  panel_dims(p, G, &K, &N);
+  const int64_t nch = A.gch[G + 1] - A.gch[G];
+  if (nch == 0) return;
+  const int tc = tile_ext(A.tiles, N), ncol = (N + tc - 1) / tc;
+  const int64_t nrt = (nch + PTILE_CH - 1) / PTILE_CH;
+  atomicAdd((unsigned long long *)&A.scalars[0], (unsigned long long)(2 * nrt * GM * (int64_t)tc * K * ncol));
+}
+
+__global__ void k_pan_target(Plan p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    p.pa.scalars[1] = p.pa.scalars[0] / ((int64_t)ITEMS_PER_CU * p.n_cu) + 1;
+}
+
+__global__ void k_pan_count(Plan p) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (G >= A.items_cap) return;
+  int tc = 0, ncol = 0, nrt = 0, pieces = 0;
+  if (G < A.ngroups) pan_split(p, G, &tc, &ncol, &nrt, &pieces);
+  A.scratch[G] = (int64_t)ncol * pieces;
+}
+
+__global__ void k_pan_items(Plan p) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (G >= A.ngroups) return;
+  int tc, ncol, nrt, pieces, K, N;
+  pan_split(p, G, &tc, &ncol, &nrt, &pieces);
+  panel_dims(p, G, &K, &N);
+  const int64_t nch = A.gch[G + 1] - A.gch[G], ib = A.item_base[G];
+  constexpr uint64_t LM = (1ull << 28) - 1;
+  for (int c = 0; c < ncol; ++c)
+    for (int k = 0; k < pieces; ++k) {
+      const int64_t r0 = (int64_t)k * nrt / pieces * PTILE_CH;
+      int64_t r1 = (int64_t)(k + 1) * nrt / pieces * PTILE_CH;
+      if (r1 > nch) r1 = nch;
+      Item it;
+      memset(&it, 0, sizeof(it));
+      it.grp = G;
+      it.mode = (tc / 32) << 16;
+      it.p0 = (int32_t)(A.gch[G] + r0);
+      it.np = (int32_t)(r1 - r0);
+      it.c0 = c * tc;
+      it.nc = min(tc, N - c * tc);
+      it.cost = 2 * (r1 - r0) * PCH * (int64_t)it.nc * K;
+      const int64_t j = ib + (int64_t)c * pieces + k;
+      A.items_unsorted[j] = it;
+      A.ikeys_in[j] = ((uint64_t)A.xcd[G] << 56) | ((uint64_t)A.rank[G] << 28) | ((uint64_t)(j - ib) & LM);
+      A.ivals_in[j] = (int32_t)j;
+    }
+}
+
+__global__ void k_pan_pad_keys(Plan p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  if (i >= A.items_cap) return;
+  if (i >= A.item_base[A.ngroups]) {
+    A.ikeys_in[i] = ~0ull;
+    A.ivals_in[i] = (int32_t)i;
+  }
+}
+
+__global__ void k_pan_gather(Plan p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Panels &A = p.pa;
+  const int64_t nit = A.item_base[A.ngroups];
+  if (i > nit) return;
+  if (i < nit) A.items[i] = A.items_unsorted[A.ivals_out[i]];
+  const int prev = i == 0 ? -1 : (int)(A.ikeys_out[i - 1] >> 56);
+  const int cur = i == nit ? A.nq : (int)(A.ikeys_out[i] >> 56);
+  for (int q = prev + 1; q <= cur; ++q) A.qbase[q] = i;
+  if (i == nit) A.scalars[2] = nit;
 }
 
 // Sizes of the padded copies of psi: sector s as m x ld8(n) and as its
@@ -597,6 +762,33 @@ static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, in
   S.scalars = cv.take<int64_t>(8);
 }
 
+// Carves the phase-A panel arrays.
+static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int maxdim, int n_cu, int nq) {
+  A.ngroups = ng;
+  A.nq = nq;
+  A.ntcap = ntcap;
+  A.tiles = TILES_DEFAULT;
+  // items: a panel's column tiles (smallest extent 32) plus one extra row
+  // piece per ITEMS_PER_CU share of the work
+  A.items_cap = std::max<int64_t>(2 * (int64_t)ITEMS_PER_CU * n_cu + (int64_t)ng * ((maxdim + 31) / 32) + 16, ng);
+  const size_t g1 = (size_t)ng + 1;
+  A.keys_in = cv.take<int32_t>(ntcap); A.keys_out = cv.take<int32_t>(ntcap);
+  A.vals_in = cv.take<int32_t>(ntcap); A.idx = cv.take<int32_t>(ntcap);
+  A.ch = cv.take<int64_t>(ntcap + 1);
+  A.grp = cv.take<int64_t>(g1); A.gch = cv.take<int64_t>(g1); A.tb = cv.take<int64_t>(g1);
+  A.cost = cv.take<int64_t>(g1);
+  A.rank = cv.take<int32_t>(g1); A.xcd = cv.take<int32_t>(g1);
+  A.item_base = cv.take<int64_t>(g1);
+  A.items_unsorted = cv.take<Item>(A.items_cap); A.items = cv.take<Item>(A.items_cap);
+  A.ikeys_in = cv.take<uint64_t>(A.items_cap); A.ikeys_out = cv.take<uint64_t>(A.items_cap);
+  A.ivals_in = cv.take<int32_t>(A.items_cap); A.ivals_out = cv.take<int32_t>(A.items_cap);
+  A.sort_tmp_bytes = std::max(radix_tmp_u64(A.items_cap), radix_tmp_i32(ntcap));
+  A.sort_tmp = cv.take<char>(A.sort_tmp_bytes + 256);
+  A.qbase = cv.take<int64_t>(NQ_MAX + 1);
+  A.scratch = cv.take<int64_t>(std::max<int64_t>(std::max<int64_t>(ng, ntcap), A.items_cap) + 1);
+  A.scalars = cv.take<int64_t>(8);
+}
+
 // Lays out (or, with base == nullptr, sizes) the build workspace.
 static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_cu, int n_xcd, char *base,
                      Plan *pl) {
@@ -638,6 +830,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   const int32_t bgroups = P->nS + P->nBlk;
   const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
   layout_sched(cv, p.bwd, bgroups, bent, bchunks, maxdim, TQ, 0, 0u, n_xcd, false);
+  layout_panels(cv, p.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
   if (pl) *pl = p;
   return cv.off + 256;
 }
@@ -695,6 +888,58 @@ static tns_status sched_items(Sched &S, hipStream_t st) {
   hipLaunchKernelGGL(k_sched_totals, dim3(1), dim3(1), 0, st, S);
   TNS_HIP(hipGetLastError());
   return TNS_OK;
+}
+
+// Work items of the phase-A panels for the current tile table, grouped by
+// panel in descending panel cost inside each XCD queue.
+static tns_status pan_items(const Plan &p, hipStream_t st) {
+  const int B = 256;
+  const Panels &A = p.pa;
+  const int ng = A.ngroups;
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(8), 0, st, A.scalars, (int64_t)8, (int64_t)0);
+  if (ng > 0) hipLaunchKernelGGL(k_pan_total, dim3(nblk(ng, B)), dim3(B), 0, st, p);
+  hipLaunchKernelGGL(k_pan_target, dim3(1), dim3(1), 0, st, p);
+  hipLaunchKernelGGL(k_pan_count, dim3(nblk(A.items_cap, B)), dim3(B), 0, st, p);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, A.scratch, A.item_base, (int64_t)ng);
+  if (ng > 0) hipLaunchKernelGGL(k_pan_items, dim3(nblk(ng, B)), dim3(B), 0, st, p);
+  hipLaunchKernelGGL(k_pan_pad_keys, dim3(nblk(A.items_cap, B)), dim3(B), 0, st, p);
+  TNS_HIP(hipGetLastError());
+  size_t tmp = A.sort_tmp_bytes;
+  TNS_HIP(hipcub::DeviceRadixSort::SortPairs(A.sort_tmp, tmp, A.ikeys_in, A.ikeys_out, A.ivals_in, A.ivals_out,
+                                             (int)A.items_cap, 0, 64, st));
+  hipLaunchKernelGGL(k_pan_gather, dim3(nblk(A.items_cap + 1, B)), dim3(B), 0, st, p);
+  TNS_HIP(hipGetLastError());
+  return TNS_OK;
+}
+
+// Phase-A panels of a built task list: panel order of the tasks, chunks,
+// offsets of the intermediates (t_off), panel queues and work items.
+static tns_status build_panels(const Plan &p, hipStream_t st) {
+  const int B = 256;
+  const Panels &A = p.pa;
+  const int64_t n = p.ntasks;
+  const int ng = A.ngroups;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_pan_keys, dim3(nblk(n, B)), dim3(B), 0, st, p, n);
+    size_t tmp = A.sort_tmp_bytes;
+    TNS_HIP(hipcub::DeviceRadixSort::SortPairs(A.sort_tmp, tmp, A.keys_in, A.keys_out, A.vals_in, A.idx, (int)n, 0,
+                                               32, st));
+  }
+  hipLaunchKernelGGL(k_pan_bounds, dim3(nblk(n + 1, B)), dim3(B), 0, st, p, n);
+  if (n > 0) hipLaunchKernelGGL(k_pan_nch, dim3(nblk(n, B)), dim3(B), 0, st, p, n);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, A.scratch, A.ch, n);
+  hipLaunchKernelGGL(k_pan_sizes, dim3(nblk(ng + 1, B)), dim3(B), 0, st, p);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, A.scratch, A.tb, (int64_t)ng);
+  if (n > 0) hipLaunchKernelGGL(k_pan_toff, dim3(nblk(n, B)), dim3(B), 0, st, p, n);
+  if (ng > 0) {
+    hipLaunchKernelGGL(k_pan_rank_keys, dim3(nblk(ng, B)), dim3(B), 0, st, p);
+    size_t tmp = A.sort_tmp_bytes;
+    TNS_HIP(hipcub::DeviceRadixSort::SortPairs(A.sort_tmp, tmp, A.ikeys_in, A.ikeys_out, A.ivals_in, A.ivals_out,
+                                               ng, 0, 64, st));
+    hipLaunchKernelGGL(k_pan_rank, dim3(nblk(ng, B)), dim3(B), 0, st, p);
+  }
+  TNS_HIP(hipGetLastError());
+  return pan_items(p, st);
 }
 
 static void read_sched(Sched &S, const int64_t *h) {
@@ -786,9 +1031,9 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   read_sched(p.fwd, h);
   if (p.fwd.nchunks > p.fwd.chunks_cap || p.fwd.nitems > p.fwd.items_cap) return TNS_ERR_WORKSPACE;
 
-  // forward intermediates
-  if (p.ntasks > 0) hipLaunchKernelGGL(k_t_sizes, dim3(nblk(p.ntasks, B)), dim3(B), 0, st, p, p.ntasks);
-  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.t_off, p.t_off, p.ntasks);
+  // phase-A panels and the offsets of the forward intermediates
+  s = build_panels(p, st);
+  if (s != TNS_OK) return s;
 
   // backward grouping: stable sort of (key, task) entries by key
   const int64_t nent = 3 * p.ntasks;
@@ -807,16 +1052,22 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   s = finish_sched(p, p.bwd, st);
   if (s != TNS_OK) return s;
   TNS_HIP(hipMemcpyAsync(h, p.bwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
-  int64_t ext[3];
-  TNS_HIP(hipMemcpyAsync(ext, p.t_off + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  int64_t ext[5];
+  TNS_HIP(hipMemcpyAsync(ext, p.pa.tb + p.pa.ngroups, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 1, p.pp_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 2, p.pt_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 3, p.pa.ch + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 4, p.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   read_sched(p.bwd, h);
   p.t_elems = ext[0];
   p.pp_elems = ext[1];
   p.pt_elems = ext[2];
+  p.pa.t_elems = ext[0];
+  p.pa.nchunks = ext[3];
+  p.pa.nitems = ext[4];
   if (p.bwd.nchunks > p.bwd.chunks_cap || p.bwd.nitems > p.bwd.items_cap) return TNS_ERR_WORKSPACE;
+  if (p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
 
   memset(out, 0, sizeof(*out));
   out->ntasks = p.ntasks;
@@ -835,14 +1086,19 @@ extern "C" tns_status tns_set_tiles(tns_tasklist *tl, uint32_t tiles, hipStream_
   if (!tl || !tiles_valid(tiles)) return TNS_ERR_ARG;
   Plan &p = plan_of(tl);
   p.fwd.tiles = tiles;
+  p.pa.tiles = tiles;
   p.tiles = tiles;
   tns_status s = sched_items(p.fwd, st);
   if (s != TNS_OK) return s;
-  int64_t h[8];
+  s = pan_items(p, st);
+  if (s != TNS_OK) return s;
+  int64_t h[8], na = 0;
   TNS_HIP(hipMemcpyAsync(h, p.fwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(&na, p.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   read_sched(p.fwd, h);
-  if (p.fwd.nitems > p.fwd.items_cap) return TNS_ERR_WORKSPACE;
+  p.pa.nitems = na;
+  if (p.fwd.nitems > p.fwd.items_cap || p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
   tl->nitems = p.fwd.nitems;
   return TNS_OK;
 }

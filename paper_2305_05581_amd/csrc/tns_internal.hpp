@@ -87,6 +87,51 @@ struct Sched {
   int64_t *scalars;     // [8]
 };
 
+// Phase-A panels.  Panel 2 s + c holds the tasks with input sector s and
+// evaluation class c; their intermediates T_k = alpha_k X_k M share the right
+// operand M (A_s or A_s^T), so the panel is one GEMM [X_k1; X_k2; ...] M with
+// the X blocks stacked along the rows.  Every task occupies whole chunks of
+// PCH rows (its last chunk padded), so each chunk belongs to one task; the
+// intermediates of a panel form one row-major matrix (chunk rows x ld8(N)).
+constexpr int PCH = 16;
+// Rows of the stacked operand per tile (chunks of a tile: GM / PCH).
+constexpr int PTILE_CH = GM / PCH;
+
+// Source of one stacked chunk, written before each product: element offset
+// of the chunk's first row in the operator values (off >= 0, leading
+// dimension ld) or, for an identity side, -(1 + first row) of the identity
+// matrix; vrows = rows of the chunk inside its task (1..16); alpha of the task.
+struct ChunkRec {
+  int64_t off;
+  int32_t ld, vrows;
+  double alpha;
+  int64_t pad_;
+};
+static_assert(sizeof(ChunkRec) == 32, "ChunkRec layout");
+
+struct Panels {
+  int32_t ngroups, nq;
+  uint32_t tiles, pad_;
+  int64_t ntcap, items_cap;
+  int64_t nchunks, nitems, t_elems;
+  int32_t *keys_in, *keys_out, *vals_in, *idx;  // [ntcap]: idx = tasks in panel order
+  int64_t *ch;         // [ntcap + 1] first chunk of each panel-order position
+  int64_t *grp;        // [ngroups + 1] first panel-order position of each panel
+  int64_t *gch;        // [ngroups + 1] first chunk of each panel
+  int64_t *tb;         // [ngroups + 1] element offset of each panel's intermediates
+  int64_t *cost;       // [ngroups] stacked rows x N x K (balance weight)
+  int32_t *rank, *xcd; // [ngroups] position by descending cost, work queue
+  int64_t *item_base;  // [ngroups + 1]
+  Item *items_unsorted, *items;
+  uint64_t *ikeys_in, *ikeys_out;
+  int32_t *ivals_in, *ivals_out;
+  void *sort_tmp;
+  size_t sort_tmp_bytes;
+  int64_t *qbase;      // [NQ_MAX + 1]: queue q = items[qbase[q], qbase[q+1])
+  int64_t *scratch;    // [max(ngroups, ntcap, items_cap) + 1]
+  int64_t *scalars;    // [8]
+};
+
 // Host-side record of everything the compute calls need; lives in
 // tns_tasklist::opaque, all pointers are device pointers into the build
 // workspace.
@@ -112,8 +157,9 @@ struct Plan {
   int64_t *scan_tmp;     // [nS+1]
   int64_t *scalars;      // [8]
   // forward intermediates T_k = alpha X_k M_k (one per task, row-major,
-  // leading dimension K2 rounded up to 8) and the padded copies of psi
-  int64_t *t_off;        // [ntcap + 1] element offset of T_k
+  // leading dimension K2 rounded up to 8, stacked per phase-A panel) and the
+  // padded copies of psi
+  int64_t *t_off;        // [ntcap] element offset of T_k
   int64_t t_elems;
   int64_t *pp_off, *pt_off;  // [nS + 1] sector offsets: m x ld8(n) and n x ld8(m)
   int64_t pp_elems, pt_elems;
@@ -122,6 +168,7 @@ struct Plan {
   void *bsort_tmp;
   size_t bsort_tmp_bytes;
   Sched fwd, bwd;
+  Panels pa;
 };
 static_assert(sizeof(Plan) <= sizeof(((tns_tasklist *)0)->opaque), "Plan too large");
 
