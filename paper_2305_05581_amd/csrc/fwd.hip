@@ -215,32 +215,51 @@ template <int P, int KS> struct RingL {
   static constexpr int LOADS = CH / 4;                      // global_load_lds per wave and stage
   static constexpr int BK = P == TNS_BF16X3 ? 32 : KS * 4 * RingP<P>::VEC;
 };
-template <int P, int KS> struct __attribute__((aligned(16))) Ring {
-  uint8_t s[BNS][RingL<P, KS>::CH * 1024];
+// The stages are separate LDS arrays and every access names its stage at
+// compile time (the stage loop is unrolled BNS times): the compiler then
+// tells the direct loads into one stage from the operand reads of another
+// and does not drain the ring before each stage's reads.
+template <int P, int KS> struct __attribute__((aligned(16))) Stage {
+  uint8_t b[RingL<P, KS>::CH * 1024];
 };
+template <int P, int KS> struct Ring {
+  Stage<P, KS> &s0, &s1, &s2, &s3;
+};
+template <int J, int P, int KS>
+__device__ inline Stage<P, KS> &stage(Ring<P, KS> &r) {
+  if constexpr (J == 0) return r.s0;
+  else if constexpr (J == 1) return r.s1;
+  else if constexpr (J == 2) return r.s2;
+  else return r.s3;
+}
 __device__ inline int rswz(int rin) { return (rin >> 1) & 3; }
+
+// Output pointers as global-memory pointers: stores through them are global
+// stores (not flat ones, which the compiler orders after LDS traffic).
+template <class T>
+__device__ inline __attribute__((address_space(1))) T *gptr(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
 
 __device__ inline void gl_lds(const void *src, void *dst) {
   __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
                                    (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
 }
 
-// Waits until at most n_after stages of this wave's ring loads are in flight
+// Waits until at most two stages of this wave's ring loads are in flight
 // (vector-memory loads complete in order), then joins the workgroup.  No
 // fence: only the LDS written by this kernel's ring loads is exchanged here.
 template <int P, int KS>
-__device__ inline void ring_sync(int n_after) {
+__device__ inline void ring_sync() {
   constexpr int E = (7 << 4) | (15 << 8), L = RingL<P, KS>::LOADS;  // expcnt, lgkmcnt: no wait
-  if (n_after >= 2)
-    __builtin_amdgcn_s_waitcnt(E | (2 * L & 15) | ((2 * L >> 4) << 14));
-  else if (n_after == 1)
-    __builtin_amdgcn_s_waitcnt(E | (L & 15) | ((L >> 4) << 14));
-  else
-    __builtin_amdgcn_s_waitcnt(E);
+  __builtin_amdgcn_s_waitcnt(E | (2 * L & 15) | ((2 * L >> 4) << 14));
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
 }
-static_assert(BNS == 4, "ring_sync covers up to two stages in flight after the awaited one");
+
+// Waits for every ring load of this wave (before the workgroup exits).
+__device__ inline void ring_drain() { __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8)); }
+static_assert(BNS == 4, "ring_sync and ring_run assume four stages");
 
 // Source of one 16-row chunk of the A operand: rows p + i * ld, i < vrows
 // (BF16X3: low halves `lo` elements further).
@@ -253,7 +272,7 @@ struct CSrc {
 // The two A chunks a wave loads (chunks w and w + 4 of the 8) from rows
 // [r0, rlim) of M.
 template <int P>
-__device__ inline void mat_srcs(const Mat &M, int r0, int rlim, CSrc (&as)[2]) {
+__device__ __attribute__((always_inline)) inline void mat_srcs(const Mat &M, int r0, int rlim, CSrc (&as)[2]) {
   typedef typename FP<P>::E E;
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -269,8 +288,8 @@ __device__ inline void mat_srcs(const Mat &M, int r0, int rlim, CSrc (&as)[2]) {
 // Stage `buf` <- the A chunks of `as` and rows [c0, blim) of B (rows of the
 // 128-row window beyond blim read zeros), k in [k0, k0 + BK).
 template <int P, int KS>
-__device__ inline void ring_issue(Ring<P, KS> &rg, int buf, const CSrc (&as)[2], const Mat &B, int c0, int blim,
-                                  int k0, int K, const void *zero) {
+__device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &st, const CSrc (&as)[2], const Mat &B, int c0, int blim, int k0,
+                                  int K, const void *zero) {
   typedef typename FP<P>::E E;
   constexpr int VEC = RingP<P>::VEC, L = RingL<P, KS>::LOADS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -302,7 +321,7 @@ __device__ inline void ring_issue(Ring<P, KS> &rg, int buf, const CSrc (&as)[2],
       in = k < K && row < blim;
       src = reinterpret_cast<const E *>(B.p) + (lo ? B.lo : 0) + (int64_t)row * B.ld + k;
     }
-    gl_lds(in ? src : z, &rg.s[buf][c * 1024]);
+    gl_lds(in ? src : z, &st.b[c * 1024]);
   }
 }
 
@@ -320,9 +339,9 @@ template <int KS> struct Frag<TNS_F32, KS> { f4 v[KS]; };
 template <int KS> struct Frag<TNS_F64, KS> { d2 v[KS]; };
 
 template <int P, int KS>
-__device__ inline Frag<P, KS> ring_frag(const Ring<P, KS> &rg, int buf, int isB, int row0, int l16, int g) {
+__device__ __attribute__((always_inline)) inline Frag<P, KS> ring_frag(const Stage<P, KS> &st, int isB, int row0, int l16, int g) {
   Frag<P, KS> f;
-  const uint8_t *base = rg.s[buf];
+  const uint8_t *base = st.b;
   if constexpr (P == TNS_BF16X3) {
     f.h = *reinterpret_cast<const u16x8 *>(base + ring_off(2 * isB, row0 + l16, g));
     f.l = *reinterpret_cast<const u16x8 *>(base + ring_off(2 * isB + 1, row0 + l16, g));
@@ -336,7 +355,7 @@ __device__ inline Frag<P, KS> ring_frag(const Ring<P, KS> &rg, int buf, int isB,
 
 // acc += x y^T over the stage's k for one 16 x 16 tile (x: rows, y: columns).
 template <int P, int KS, class A4>
-__device__ inline void frag_mma(const Frag<P, KS> &x, const Frag<P, KS> &y, A4 &acc) {
+__device__ __attribute__((always_inline)) inline void frag_mma(const Frag<P, KS> &x, const Frag<P, KS> &y, A4 &acc) {
   if constexpr (P == TNS_BF16X3) {
     acc = mfma_bf(x.l, y.h, acc);
     acc = mfma_bf(x.h, y.l, acc);
@@ -353,14 +372,14 @@ __device__ inline void frag_mma(const Frag<P, KS> &x, const Frag<P, KS> &y, A4 &
 // wm 16 TM + 16 i and columns wn 16 TN + 16 j.  SWAP: acc[i][j] holds the
 // transposed tile (rows = B rows wn 16 TN + 16 i, columns = A rows wm 16 TM + 16 j).
 template <int P, int KS, int TM, int TN, bool SWAP>
-__device__ inline void ring_mma(const Ring<P, KS> &rg, int buf, typename FP<P>::A4 (&acc)[4][4]) {
+__device__ __attribute__((always_inline)) inline void ring_mma(const Stage<P, KS> &st, typename FP<P>::A4 (&acc)[4][4]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
   Frag<P, KS> a[TM], b[TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = ring_frag<P, KS>(rg, buf, 0, wm * 16 * TM + 16 * i, l16, g);
+  for (int i = 0; i < TM; ++i) a[i] = ring_frag<P, KS>(st, 0, wm * 16 * TM + 16 * i, l16, g);
 #pragma unroll
-  for (int j = 0; j < TN; ++j) b[j] = ring_frag<P, KS>(rg, buf, 1, wn * 16 * TN + 16 * j, l16, g);
+  for (int j = 0; j < TN; ++j) b[j] = ring_frag<P, KS>(st, 1, wn * 16 * TN + 16 * j, l16, g);
   if (SWAP) {
 #pragma unroll
     for (int i = 0; i < TN; ++i)
@@ -383,6 +402,34 @@ template <int P, int PH> struct Geo {
   static constexpr int WG = (P == TNS_BF16X3 || (P == TNS_F64 && PH == 0)) ? 1 : 2;
 };
 
+// Drives the ring over one stream of K steps: issue(stage) fills a stage
+// with the next step and advances the load cursor, returning false (after
+// filling the stage with zeros) once the stream is exhausted; compute(stage)
+// consumes one step.  Loads run BNS - 1 steps ahead; step s uses stage
+// s mod BNS, written BNS - 1 steps earlier.  Every step issues a stage and
+// only the computation is conditional: with the direct loads on every path
+// of a loop without early exits, the compiler keeps track of which stage
+// each operand read depends on.
+template <int P, int KS, class Issue, class Compute>
+__device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS> &rg, Issue &&issue, Compute &&compute) {
+  int issued = 0;
+  issued += issue(rg.s0);
+  issued += issue(rg.s1);
+  issued += issue(rg.s2);
+  auto step = [&](auto J, int s) {
+    constexpr int j = decltype(J)::value;
+    ring_sync<P, KS>();
+    issued += issue(stage<(j + BNS - 1) % BNS>(rg));
+    if (s < issued) compute(stage<j>(rg));
+  };
+  for (int s = 0; s < issued; s += BNS) {
+    step(std::integral_constant<int, 0>{}, s);
+    step(std::integral_constant<int, 1>{}, s + 1);
+    step(std::integral_constant<int, 2>{}, s + 2);
+    step(std::integral_constant<int, 3>{}, s + 3);
+  }
+}
+
 // Runs CALL(TM, TN) for tile extents (32 tm) x (32 tn), tm, tn in {1, 2, 4}.
 #define TNS_TILE_SWITCH(tm, tn, CALL)                  \
   switch ((tm) * 8 + (tn)) {                             \
@@ -399,7 +446,7 @@ template <int P, int PH> struct Geo {
 
 // --- phase B: one item (output tile, chunk of tasks) ------------------------------------
 template <int P, int KS, int TM, int TN>
-__device__ inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it, int mode) {
+__device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it, int mode) {
   typedef typename FP<P>::A4 A4;
   constexpr int BK = RingL<P, KS>::BK;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -409,8 +456,8 @@ __device__ inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const It
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  int ls = it.tb, lj = 0, lK, issued = 0, blim;
-  bool ldone = false;
+  int ls = it.tb, lj = 0, lK, blim;
+  bool ldone = false;  // every segment has lK >= 1
   Mat LA, LB;
   CSrc as[2];
   auto load_seg = [&]() {
@@ -419,23 +466,22 @@ __device__ inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const It
     blim = min(LB.rows, it.c0 + 32 * TN);
   };
   load_seg();
-  auto issue_next = [&]() {
-    ring_issue<P, KS>(rg, issued % BNS, as, LB, it.c0, blim, lj * BK, lK, g.zero);
-    ++issued;
-    if (++lj * BK >= lK) {
-      lj = 0;
-      if (++ls < it.te) load_seg();
-      else ldone = true;
-    }
-  };
-  while (!ldone && issued < BNS - 1) issue_next();
-  for (int s = 0; s < issued; ++s) {
-    ring_sync<P, KS>(issued - 1 - s);
-    if (!ldone) issue_next();
-    ring_mma<P, KS, TM, TN, false>(rg, s % BNS, acc);
-  }
+  ring_run<P, KS>(
+      rg,
+      [&](Stage<P, KS> &st) {
+        const bool live = !ldone;
+        ring_issue<P, KS>(st, as, LB, it.c0, blim, lj * BK, live ? lK : 0, g.zero);
+        if (!live) return false;
+        if (++lj * BK >= lK) {
+          lj = 0;
+          if (++ls < it.te) load_seg();
+          else ldone = true;
+        }
+        return true;
+      },
+      [&](const Stage<P, KS> &st) { ring_mma<P, KS, TM, TN, false>(st, acc); });
   const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
-  typename FP<P>::Acc *slot = reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]);
+  auto slot = gptr(reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]));
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -453,7 +499,7 @@ __device__ inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const It
 }
 
 template <int P, int KS>
-__device__ inline void ring_item_b(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
+__device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
   const Item it = load_item(g.items + wk);
   const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
 #define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode)
@@ -470,7 +516,7 @@ __device__ inline void ring_item_b(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
 // Sources of the two A chunks of this wave in the tile starting at chunk ch
 // (chunks at or beyond ch_end are empty).
 template <int P>
-__device__ inline void chunk_srcs(const FwdArgs &g, int ch, int ch_end, CSrc (&as)[2]) {
+__device__ __attribute__((always_inline)) inline void chunk_srcs(const FwdArgs &g, int ch, int ch_end, CSrc (&as)[2]) {
   typedef typename FP<P>::E E;
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -503,7 +549,7 @@ __device__ inline void chunk_srcs(const FwdArgs &g, int ch, int ch_end, CSrc (&a
 // rows beyond the chunk's task are not stored.  FP32 and BF16X3 write 4
 // consecutive columns per lane as one vector.
 template <int P, int TN>
-__device__ inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[4][4], int ch, int ch_end,
+__device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[4][4], int ch, int ch_end,
                                       int64_t tbase, int c0, int ldT) {
   typedef typename FP<P>::A4 A4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -521,7 +567,7 @@ __device__ inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc
         for (int i = 0; i < TN; ++i) {
           const int col0 = c0 + wn * 16 * TN + i * 16;
           if constexpr (P == TNS_F64) {
-            double *Tt = reinterpret_cast<double *>(g.T) + orow;
+            auto Tt = gptr(reinterpret_cast<double *>(g.T) + orow);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int col = col0 + mrow(acc[i][j], lg, v);
@@ -533,14 +579,14 @@ __device__ inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc
               const f4 x = (float)alpha * acc[i][j];
               const int64_t o = orow + col;
               if constexpr (P == TNS_F32) {
-                *reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o) = x;
+                *gptr(reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o)) = x;
               } else {
                 const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
                 const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
                                 (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
                 uint16_t *Th = reinterpret_cast<uint16_t *>(g.T);
-                *reinterpret_cast<uint64_t *>(Th + o) = __builtin_bit_cast(uint64_t, h);
-                *reinterpret_cast<uint64_t *>(Th + g.T_lo + o) = __builtin_bit_cast(uint64_t, l);
+                *gptr(reinterpret_cast<uint64_t *>(Th + o)) = __builtin_bit_cast(uint64_t, h);
+                *gptr(reinterpret_cast<uint64_t *>(Th + g.T_lo + o)) = __builtin_bit_cast(uint64_t, l);
               }
             }
           }
@@ -553,7 +599,7 @@ __device__ inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc
 }
 
 template <int P, int KS, int TN>
-__device__ inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it) {
+__device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it) {
   typedef typename FP<P>::A4 A4;
   typedef typename FP<P>::E E;
   constexpr int BK = RingL<P, KS>::BK;
@@ -571,40 +617,39 @@ __device__ inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS> &rg, const It
   const int blim = min(B.rows, it.c0 + 32 * TN);
   const int ch_end = it.p0 + it.np;
   const int64_t tbase = cld(&g.a_tb[G]) - cld(&g.a_gch[G]) * PCH * ldT;
-  // load cursor: (tile's first chunk, k)
-  int lch = it.p0, lk0 = 0, issued = 0;
+  // load cursor: (tile's first chunk, k); compute cursor BNS - 1 steps behind
+  int lch = it.p0, lk0 = 0, cch = it.p0, ck0 = 0;
   bool ldone = false;
   CSrc as[2];
   chunk_srcs<P>(g, lch, ch_end, as);
-  auto issue_next = [&]() {
-    ring_issue<P, KS>(rg, issued % BNS, as, B, it.c0, blim, lk0, K, g.zero);
-    ++issued;
-    if ((lk0 += BK) < K) return;
-    lk0 = 0;
-    if ((lch += PTILE_CH) < ch_end) chunk_srcs<P>(g, lch, ch_end, as);
-    else ldone = true;
-  };
-  while (!ldone && issued < BNS - 1) issue_next();
-  // compute cursor, BNS - 1 steps behind
-  int cch = it.p0, ck0 = 0;
   A4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  for (int s = 0; s < issued; ++s) {
-    ring_sync<P, KS>(issued - 1 - s);
-    if (!ldone) issue_next();
-    ring_mma<P, KS, 4, TN, true>(rg, s % BNS, acc);
-    if ((ck0 += BK) < K) continue;
-    ck0 = 0;
-    ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, ldT);
-    cch += PTILE_CH;
-  }
+  ring_run<P, KS>(
+      rg,
+      [&](Stage<P, KS> &st) {
+        const bool live = !ldone;
+        ring_issue<P, KS>(st, as, B, it.c0, blim, lk0, live ? K : 0, g.zero);
+        if (!live) return false;
+        if ((lk0 += BK) < K) return true;
+        lk0 = 0;
+        if ((lch += PTILE_CH) < ch_end) chunk_srcs<P>(g, lch, ch_end, as);
+        else ldone = true;
+        return true;
+      },
+      [&](const Stage<P, KS> &st) {
+        ring_mma<P, KS, 4, TN, true>(st, acc);
+        if ((ck0 += BK) < K) return;
+        ck0 = 0;
+        ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, ldT);
+        cch += PTILE_CH;
+      });
 }
 
 template <int P, int KS>
-__device__ inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
+__device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
   const Item it = load_item(g.a_items + wk);
   switch ((it.mode >> 16) & 0xff) {
     case 1: ring_item_a_t<P, KS, 1>(g, rg, it); break;
@@ -640,7 +685,9 @@ __global__ void k_chunk_recs(FwdArgs g) {
 
 template <int P, int PH>
 __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
-  __shared__ Ring<P, Geo<P, PH>::KS> rg;
+  constexpr int KS = Geo<P, PH>::KS;
+  __shared__ Stage<P, KS> st0, st1, st2, st3;
+  Ring<P, KS> rg{st0, st1, st2, st3};
   __shared__ int s_work;
   for (;;) {
     if (threadIdx.x == 0) s_work = pop_work<PH>(g);
@@ -653,6 +700,7 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
     if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
     else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
   }
+  ring_drain();
 }
 
 // Identity matrix n x ld (BF16X3: high halves, low halves `lo` further).
@@ -793,7 +841,9 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
 
 template <int P, int PH>
 __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b) {
-  __shared__ Ring<P, Geo<P, PH>::KS> rg;
+  constexpr int KS = Geo<P, PH>::KS;
+  __shared__ Stage<P, KS> st0, st1, st2, st3;
+  Ring<P, KS> rg{st0, st1, st2, st3};
   __shared__ int s_w[2];
   for (;;) {
     if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
@@ -805,6 +855,7 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b
     if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
     else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
   }
+  ring_drain();
 }
 
 __global__ void k_chunk_recs_batch(const InstArgs *tab) {
