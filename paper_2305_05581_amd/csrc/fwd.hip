@@ -247,11 +247,12 @@ __device__ inline void gl_lds(const void *src, void *dst) {
 }
 
 // Waits until at most two stages of this wave's ring loads are in flight
-// (vector-memory loads complete in order), then joins the workgroup.  No
-// fence: only the LDS written by this kernel's ring loads is exchanged here.
-template <int P, int KS>
+// (vector-memory loads complete in order) and, with LGKM, until its LDS reads
+// are complete, then joins the workgroup.  No fence: only the LDS written by
+// this kernel's ring loads is exchanged here.
+template <int P, int KS, bool LGKM>
 __device__ inline void ring_sync() {
-  constexpr int E = (7 << 4) | (15 << 8), L = RingL<P, KS>::LOADS;  // expcnt, lgkmcnt: no wait
+  constexpr int E = (7 << 4) | ((LGKM ? 0 : 15) << 8), L = RingL<P, KS>::LOADS;  // expcnt: no wait
   __builtin_amdgcn_s_waitcnt(E | (2 * L & 15) | ((2 * L >> 4) << 14));
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
@@ -371,25 +372,34 @@ __device__ __attribute__((always_inline)) inline void frag_mma(const Frag<P, KS>
 // One stage of MFMA for a (32 TM) x (32 TN) tile; wave (wm, wn) owns rows
 // wm 16 TM + 16 i and columns wn 16 TN + 16 j.  SWAP: acc[i][j] holds the
 // transposed tile (rows = B rows wn 16 TN + 16 i, columns = A rows wm 16 TM + 16 j).
-template <int P, int KS, int TM, int TN, bool SWAP>
-__device__ __attribute__((always_inline)) inline void ring_mma(const Stage<P, KS> &st, typename FP<P>::A4 (&acc)[4][4]) {
+// The operand fragments of one stage for this wave's tile.
+template <int P, int KS, int TM, int TN> struct Frags {
+  Frag<P, KS> a[TM], b[TN];
+};
+
+template <int P, int KS, int TM, int TN>
+__device__ __attribute__((always_inline)) inline void ring_read(const Stage<P, KS> &st, Frags<P, KS, TM, TN> &f) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
-  Frag<P, KS> a[TM], b[TN];
 #pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = ring_frag<P, KS>(st, 0, wm * 16 * TM + 16 * i, l16, g);
+  for (int i = 0; i < TM; ++i) f.a[i] = ring_frag<P, KS>(st, 0, wm * 16 * TM + 16 * i, l16, g);
 #pragma unroll
-  for (int j = 0; j < TN; ++j) b[j] = ring_frag<P, KS>(st, 1, wn * 16 * TN + 16 * j, l16, g);
+  for (int j = 0; j < TN; ++j) f.b[j] = ring_frag<P, KS>(st, 1, wn * 16 * TN + 16 * j, l16, g);
+}
+
+template <int P, int KS, int TM, int TN, bool SWAP>
+__device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS, TM, TN> &f,
+                                                               typename FP<P>::A4 (&acc)[4][4]) {
   if (SWAP) {
 #pragma unroll
     for (int i = 0; i < TN; ++i)
 #pragma unroll
-      for (int j = 0; j < TM; ++j) frag_mma<P, KS>(b[i], a[j], acc[i][j]);
+      for (int j = 0; j < TM; ++j) frag_mma<P, KS>(f.b[i], f.a[j], acc[i][j]);
   } else {
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) frag_mma<P, KS>(a[i], b[j], acc[i][j]);
+      for (int j = 0; j < TN; ++j) frag_mma<P, KS>(f.a[i], f.b[j], acc[i][j]);
   }
 }
 
@@ -397,9 +407,12 @@ __device__ __attribute__((always_inline)) inline void ring_mma(const Stage<P, KS
 // FP64 phase B 16 KB stages, two workgroups per CU; FP64 phase A 32 KB stages
 // (its swapped-accumulator epilogue needs more than 256 registers per lane),
 // BF16X3 32 KB stages, one workgroup per CU.
+// PF: operand fragments of the next stage are read while the MFMA work of
+// the current one runs (two fragment sets in registers).
 template <int P, int PH> struct Geo {
   static constexpr int KS = (P == TNS_F64 && PH == 0) ? 2 : 1;
   static constexpr int WG = (P == TNS_BF16X3 || (P == TNS_F64 && PH == 0)) ? 1 : 2;
+  static constexpr bool PF = !(P == TNS_F64 && PH == 0);
 };
 
 // Drives the ring over one stream of K steps: issue(stage) fills a stage
@@ -410,23 +423,53 @@ template <int P, int PH> struct Geo {
 // only the computation is conditional: with the direct loads on every path
 // of a loop without early exits, the compiler keeps track of which stage
 // each operand read depends on.
-template <int P, int KS, class Issue, class Compute>
+//
+// PF (prefetch): the fragments of stage s + 1 are read into registers during
+// step s, while the MFMA work of stage s (read one step earlier) runs; the
+// slot of stage s is then free at step s and receives stage s + BNS.  Each
+// step waits for this wave's outstanding LDS reads before the barrier, so no
+// slot is overwritten while a read of it is in flight.
+template <int P, int KS, bool PF, class FR, class Issue, class Compute>
 __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS> &rg, Issue &&issue, Compute &&compute) {
   int issued = 0;
   issued += issue(rg.s0);
   issued += issue(rg.s1);
   issued += issue(rg.s2);
-  auto step = [&](auto J, int s) {
-    constexpr int j = decltype(J)::value;
-    ring_sync<P, KS>();
-    issued += issue(stage<(j + BNS - 1) % BNS>(rg));
-    if (s < issued) compute(stage<j>(rg));
-  };
-  for (int s = 0; s < issued; s += BNS) {
-    step(std::integral_constant<int, 0>{}, s);
-    step(std::integral_constant<int, 1>{}, s + 1);
-    step(std::integral_constant<int, 2>{}, s + 2);
-    step(std::integral_constant<int, 3>{}, s + 3);
+  if constexpr (PF) {
+    FR f0, f1;
+    ring_sync<P, KS, false>();
+    issued += issue(rg.s3);
+    ring_read(rg.s0, f0);
+    auto step = [&](auto J, int s, FR &cur, FR &nxt) {
+      constexpr int j = decltype(J)::value;
+      ring_sync<P, KS, true>();
+      issued += issue(stage<j>(rg));
+      if (s + 1 < issued) ring_read(stage<(j + 1) % BNS>(rg), nxt);
+      if (s < issued) compute(cur);
+    };
+    for (int s = 0; s < issued; s += BNS) {
+      step(std::integral_constant<int, 0>{}, s, f0, f1);
+      step(std::integral_constant<int, 1>{}, s + 1, f1, f0);
+      step(std::integral_constant<int, 2>{}, s + 2, f0, f1);
+      step(std::integral_constant<int, 3>{}, s + 3, f1, f0);
+    }
+  } else {
+    FR f;
+    auto step = [&](auto J, int s) {
+      constexpr int j = decltype(J)::value;
+      ring_sync<P, KS, false>();
+      issued += issue(stage<(j + BNS - 1) % BNS>(rg));
+      if (s < issued) {
+        ring_read(stage<j>(rg), f);
+        compute(f);
+      }
+    };
+    for (int s = 0; s < issued; s += BNS) {
+      step(std::integral_constant<int, 0>{}, s);
+      step(std::integral_constant<int, 1>{}, s + 1);
+      step(std::integral_constant<int, 2>{}, s + 2);
+      step(std::integral_constant<int, 3>{}, s + 3);
+    }
   }
 }
 
@@ -466,7 +509,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     blim = min(LB.rows, it.c0 + 32 * TN);
   };
   load_seg();
-  ring_run<P, KS>(
+  typedef Frags<P, KS, TM, TN> FR;
+  ring_run<P, KS, Geo<P, 1>::PF, FR>(
       rg,
       [&](Stage<P, KS> &st) {
         const bool live = !ldone;
@@ -479,7 +523,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
         }
         return true;
       },
-      [&](const Stage<P, KS> &st) { ring_mma<P, KS, TM, TN, false>(st, acc); });
+      [&](const FR &f) { ring_mma<P, KS, TM, TN, false>(f, acc); });
   const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
   auto slot = gptr(reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]));
 #pragma unroll
@@ -627,7 +671,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  ring_run<P, KS>(
+  typedef Frags<P, KS, 4, TN> FR;
+  ring_run<P, KS, Geo<P, 0>::PF, FR>(
       rg,
       [&](Stage<P, KS> &st) {
         const bool live = !ldone;
@@ -639,8 +684,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
         else ldone = true;
         return true;
       },
-      [&](const Stage<P, KS> &st) {
-        ring_mma<P, KS, 4, TN, true>(st, acc);
+      [&](const FR &f) {
+        ring_mma<P, KS, 4, TN, true>(f, acc);
         if ((ck0 += BK) < K) return;
         ck0 = 0;
         ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, ldT);

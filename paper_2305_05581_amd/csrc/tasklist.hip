@@ -304,11 +304,12 @@ __global__ void k_items(Sched S) {
   for (int k = 0; k < nt; ++k) {
     Item it;
     it.grp = ch.grp;
-    it.mode = S.grp_mode[ch.grp] | (S.tiles ? ((tr / 32) << 8) | ((tc / 32) << 16) : 0);
     it.p0 = (k / ncol) * tr;
     it.np = min(tr, rows - it.p0);
     it.c0 = (k % ncol) * tc;
     it.nc = min(tc, cols - it.c0);
+    it.mode = S.grp_mode[ch.grp] |
+              (S.tiles ? ((tail_ext(it.np, tr) / 32) << 8) | ((tail_ext(it.nc, tc) / 32) << 16) : 0);
     it.tb = ch.tb;
     it.te = ch.te;
     it.slot = (int32_t)c;
@@ -521,11 +522,11 @@ __global__ void k_pan_items(Plan p) {
       Item it;
       memset(&it, 0, sizeof(it));
       it.grp = G;
-      it.mode = (tc / 32) << 16;
       it.p0 = (int32_t)(A.gch[G] + r0);
       it.np = (int32_t)(r1 - r0);
       it.c0 = c * tc;
       it.nc = min(tc, N - c * tc);
+      it.mode = (tail_ext(it.nc, tc) / 32) << 16;
       it.cost = 2 * (r1 - r0) * PCH * (int64_t)it.nc * K;
       const int64_t j = ib + (int64_t)c * pieces + k;
       A.items_unsorted[j] = it;

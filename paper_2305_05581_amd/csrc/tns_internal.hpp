@@ -45,11 +45,19 @@ constexpr int GM = 128, GN = 128;
 
 // Tile extents of the forward GEMMs chosen per dimension: a table of four
 // bytes, entry b the extent (32, 64 or 128) used along a dimension d in bucket
-// b = [d <= 32, d <= 64, d <= 128, d > 128].  Phase-B items carry their
-// extents in bits 8..15 (rows / 32) and 16..23 (columns / 32) of Item::mode.
+// b = [d <= 32, d <= 64, d <= 128, d > 128]; the last tile along a dimension
+// takes the extent tail_ext of what remains.  Items carry their extents in
+// bits 8..15 (rows / 32) and 16..23 (columns / 32) of Item::mode.
 constexpr uint32_t TILES_DEFAULT = 0x80804020u;  // 32, 64, 128, 128
 __host__ __device__ inline int tile_bucket(int d) { return d <= 32 ? 0 : d <= 64 ? 1 : d <= 128 ? 2 : 3; }
 __host__ __device__ inline int tile_ext(uint32_t tab, int d) { return (int)((tab >> (8 * tile_bucket(d))) & 0xffu); }
+// Extent of the last tile along a dimension whose other tiles have extent e
+// (32, 64 or 128): the smallest of 32, 64, 128 that covers the rem <= e
+// remaining rows, so that only the last tile is padded, by less than its size.
+__host__ __device__ inline int tail_ext(int rem, int e) {
+  const int x = rem <= 32 ? 32 : rem <= 64 ? 64 : 128;
+  return x < e ? x : e;
+}
 __host__ __device__ inline bool tiles_valid(uint32_t tab) {
   for (int b = 0; b < 4; ++b) {
     const uint32_t e = (tab >> (8 * b)) & 0xffu;
