@@ -21,7 +21,8 @@
 // Both phases compute tiles C(i, j) = sum over segments of sum_k A(i, k) B(j, k)
 // with every operand k-contiguous (rows of L, R, T, of the identity and of the
 // padded copies of A and A^T).  Tiles are 32, 64 or 128 rows / columns per the
-// tile table of the task list (per sector-size bucket).  Operands stream from
+// tile table of the task list (per sector-size bucket), the last tile along a
+// dimension 32, 64, 96 or 128 to fit what remains.  Operands stream from
 // global memory straight into a 4-stage LDS ring (16-byte direct loads), the
 // MFMA work consuming one stage per barrier.
 #include <algorithm>
@@ -403,16 +404,14 @@ __device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS
   }
 }
 
-// Ring geometry and workgroups per CU of each (precision, phase): FP32 and
-// FP64 phase B 16 KB stages, two workgroups per CU; FP64 phase A 32 KB stages
-// (its swapped-accumulator epilogue needs more than 256 registers per lane),
-// BF16X3 32 KB stages, one workgroup per CU.
-// PF: operand fragments of the next stage are read while the MFMA work of
-// the current one runs (two fragment sets in registers).
+// Ring geometry of each (precision, phase): KS k-halves per stage, WG
+// workgroups per CU, PF register prefetch of the next stage's fragments.
+// FP32 and FP64 use 16 KB stages at two workgroups per CU, BF16X3 32 KB
+// stages at one.
 template <int P, int PH> struct Geo {
-  static constexpr int KS = (P == TNS_F64 && PH == 0) ? 2 : 1;
-  static constexpr int WG = (P == TNS_BF16X3 || (P == TNS_F64 && PH == 0)) ? 1 : 2;
-  static constexpr bool PF = !(P == TNS_F64 && PH == 0);
+  static constexpr int KS = 1;
+  static constexpr int WG = P == TNS_BF16X3 ? 1 : 2;
+  static constexpr bool PF = true;
 };
 
 // Drives the ring over one stream of K steps: issue(stage) fills a stage
@@ -473,17 +472,24 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS> &rg, 
   }
 }
 
-// Runs CALL(TM, TN) for tile extents (32 tm) x (32 tn), tm, tn in {1, 2, 4}.
+// Runs CALL(TM, TN) for tile extents (32 tm) x (32 tn), tm, tn in {1, 2, 3, 4}.
 #define TNS_TILE_SWITCH(tm, tn, CALL)                  \
   switch ((tm) * 8 + (tn)) {                             \
     case 9: CALL(1, 1); break;                           \
     case 10: CALL(1, 2); break;                          \
+    case 11: CALL(1, 3); break;                          \
     case 12: CALL(1, 4); break;                          \
     case 17: CALL(2, 1); break;                          \
     case 18: CALL(2, 2); break;                          \
+    case 19: CALL(2, 3); break;                          \
     case 20: CALL(2, 4); break;                          \
+    case 25: CALL(3, 1); break;                          \
+    case 26: CALL(3, 2); break;                          \
+    case 27: CALL(3, 3); break;                          \
+    case 28: CALL(3, 4); break;                          \
     case 33: CALL(4, 1); break;                          \
     case 34: CALL(4, 2); break;                          \
+    case 35: CALL(4, 3); break;                          \
     default: CALL(4, 4); break;                          \
   }
 
@@ -699,6 +705,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs 
   switch ((it.mode >> 16) & 0xff) {
     case 1: ring_item_a_t<P, KS, 1>(g, rg, it); break;
     case 2: ring_item_a_t<P, KS, 2>(g, rg, it); break;
+    case 3: ring_item_a_t<P, KS, 3>(g, rg, it); break;
     default: ring_item_a_t<P, KS, 4>(g, rg, it); break;
   }
 }

@@ -52,10 +52,10 @@ constexpr uint32_t TILES_DEFAULT = 0x80804020u;  // 32, 64, 128, 128
 __host__ __device__ inline int tile_bucket(int d) { return d <= 32 ? 0 : d <= 64 ? 1 : d <= 128 ? 2 : 3; }
 __host__ __device__ inline int tile_ext(uint32_t tab, int d) { return (int)((tab >> (8 * tile_bucket(d))) & 0xffu); }
 // Extent of the last tile along a dimension whose other tiles have extent e
-// (32, 64 or 128): the smallest of 32, 64, 128 that covers the rem <= e
-// remaining rows, so that only the last tile is padded, by less than its size.
+// (32, 64 or 128): the smallest multiple of 32 that covers the rem <= e
+// remaining rows, so that only the last tile is padded, by less than 32.
 __host__ __device__ inline int tail_ext(int rem, int e) {
-  const int x = rem <= 32 ? 32 : rem <= 64 ? 64 : 128;
+  const int x = (rem + 31) / 32 * 32;
   return x < e ? x : e;
 }
 __host__ __device__ inline bool tiles_valid(uint32_t tab) {
