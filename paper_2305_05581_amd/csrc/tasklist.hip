@@ -266,14 +266,14 @@ __global__ void k_chunks(Plan p, Sched S) {
     for (int i = b; i < b + n; ++i) {
       const int64_t c = mode_cost(p, p.tasks[S.idx[i]], mode);
       if (i > start && cur + c > cap) {
-        if (FILL) { Chunk ch{g, start, i, 0, cur}; S.chunks[cb + nc] = ch; }
+        if (FILL) { Chunk ch{g, start, i, 0, cur, 0, 0}; S.chunks[cb + nc] = ch; }
         ++nc;
         start = i;
         cur = 0;
       }
       cur += c;
     }
-    if (FILL) { Chunk ch{g, start, b + n, 0, cur}; S.chunks[cb + nc] = ch; }
+    if (FILL) { Chunk ch{g, start, b + n, 0, cur, 0, 0}; S.chunks[cb + nc] = ch; }
     ++nc;
   }
   if (!FILL) S.scratch[g] = nc;
@@ -337,19 +337,23 @@ __global__ void k_chunk_xcd(Sched S) {
   if (i >= nch) return;
   const int64_t round = i / S.nq, pos = i % S.nq;
   S.chunks[S.vals_out[i]].xcd = (int32_t)((round & 1) ? S.nq - 1 - pos : pos);
+  S.chunks[S.vals_out[i]].rank = (int32_t)i;
 }
 
-// Item order: by queue, then longest first; padding entries sort last.
+// Item order: by queue, then by chunk in descending chunk cost, the tiles of
+// a chunk adjacent (row-major), so that the workgroups of one XCD that run a
+// chunk's tiles together share its operand panels in L2; padding sorts last.
 __global__ void k_sort_keys(Sched S) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.items_cap) return;
   const int64_t nit = S.chunk_item_base[S.grp_chunk_base[S.ngroups]];
-  constexpr uint64_t CM = (1ull << 56) - 1;
+  constexpr uint64_t LM = (1ull << 28) - 1;
   uint64_t key = ~0ull;
   if (i < nit) {
     const Item it = S.items_unsorted[i];
-    const uint64_t c = (uint64_t)it.cost < CM ? (uint64_t)it.cost : CM;
-    key = ((uint64_t)S.chunks[it.slot].xcd << 56) | (CM - c);
+    const Chunk &ch = S.chunks[it.slot];
+    key = ((uint64_t)ch.xcd << 56) | (((uint64_t)ch.rank & LM) << 28) |
+          ((uint64_t)(i - S.chunk_item_base[it.slot]) & LM);
   }
   S.keys_in[i] = key;
   S.vals_in[i] = (int32_t)i;

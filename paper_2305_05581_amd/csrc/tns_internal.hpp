@@ -67,8 +67,9 @@ __host__ __device__ inline bool tiles_valid(uint32_t tab) {
 }
 
 struct Chunk {
-  int32_t grp, tb, te, xcd;  // xcd: queue the chunk's row panels go to
+  int32_t grp, tb, te, xcd;  // xcd: queue the chunk's tiles go to
   int64_t cost;
+  int32_t rank, pad_;        // position in descending cost order
 };
 
 // A schedule: groups of tasks that share one output matrix, cut into chunks
