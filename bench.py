@@ -364,6 +364,19 @@ def main():
         print(json.dumps({"only": args.only, **res[args.only]}), flush=True)
         return
 
+    # measured MFMA ceilings (per algorithmic flop: BF16x3 issues three BF16 products)
+    mpeak = {}
+    try:
+        from paper_2305_05581_amd.tns import mfma_peak
+        for prec in res:
+            inst = mfma_peak(prec)
+            mpeak[prec] = inst / 3.0 if prec == "bf16x3" else inst
+            res[prec]["pct_measured_peak"] = 100 * res[prec]["tflops"] / mpeak[prec]
+        log("measured MFMA peak (TFLOP/s per algorithmic flop): " +
+            ", ".join("%s %.1f (%.1f%% of it)" % (p, mpeak[p], res[p]["pct_measured_peak"]) for p in mpeak))
+    except Exception as e:  # reported, not fatal
+        mpeak = {"error": str(e)[:200]}
+
     # hipGraph replay of the headline product
     graph = {}
     try:
@@ -448,6 +461,7 @@ def main():
                 "traffic": measured_traffic(args.config, args.prec) if dom == 0 else None,
                 "algorithmic_flops_per_launch": d_fl, "avg_launch_ms": round(d_ms, 3),
                 "both_phases_tflops": round(head["kernel_tflops"], 3),
+                "measured_peak": round(mpeak[args.prec], 1) if args.prec in mpeak else None,
                 "peak_note": ("BF16 dense 2516.6 TFLOP/s / 3 MFMA products per algorithmic flop"
                               if args.prec == "bf16x3" else "dense MFMA peak of the dtype")}
     line = {
@@ -471,6 +485,7 @@ def main():
                    "operator_GB_f64": round(P.op_vals.nbytes / 1e9, 2), "parallelism": "single GPU",
                    "tile_table": "%08x" % H.tiles, "autotuned": bool(args.autotune)},
         "pct_mfma_peak": round(head["pct_peak"], 2),
+        "measured_mfma_peak": {k: round(v, 1) for k, v in mpeak.items() if isinstance(v, float)},
         "precisions": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in res.items()},
         "mixed_vs_f64_speedup": round(res[args.prec]["tflops"] / res["f64"]["tflops"], 3),

@@ -197,8 +197,9 @@ tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n, tns_prec 
  * work decomposition, Alg. 2's batched products; the bucket choice is this
  * library's).  `tiles` packs four bytes: byte b is the tile extent (32, 64 or
  * 128 rows/columns) used along any output dimension d of bucket b =
- * [d <= 32, d <= 64, d <= 128, d > 128].  Default 0x80804020 (32, 64, 128,
- * 128).  tns_set_tiles rebuilds the forward work items on the device and
+ * [d <= 32, d <= 64, d <= 128, d > 128]; the last tile along a dimension
+ * shrinks to the multiple of 32 that covers what remains.  Default
+ * 0x80804020 (32, 64, 128, 128).  tns_set_tiles rebuilds the forward work items on the device and
  * synchronises the stream (no product may be in flight on the task list);
  * workspaces and results do not depend on the table (the sums are taken in
  * the same order).  TNS_ERR_ARG for an invalid table. */
@@ -265,6 +266,18 @@ const char *tns_status_string(tns_status s);
  * that a caller can time each MFMA kernel alone.  Pass nulls to disable.
  * Not thread-safe; the events belong to the caller. */
 void tns_profile_events(hipEvent_t before, hipEvent_t mid, hipEvent_t after);
+
+/* Measurement aid: the device's MFMA throughput measured with the MFMA
+ * instruction each precision's product uses (v_mfma_f64_16x16x4,
+ * v_mfma_f32_16x16x4, v_mfma_f32_16x16x32_bf16), every wave running 8
+ * independent accumulator chains on register operands, 32 waves per CU; best
+ * of 5 timed launches after a warm-up.  *tflops receives instruction flops
+ * per second (BF16X3: BF16 flops, three per algorithmic flop of a product).
+ * ws: device scratch of tns_mfma_peak_workspace_bytes() bytes (0 when the
+ * device cannot be queried).  Synchronous; TNS_ERR_ARG for a bad precision or
+ * iters <= 0. */
+size_t tns_mfma_peak_workspace_bytes(void);
+tns_status tns_mfma_peak(tns_prec prec, int iters, void *ws, size_t ws_bytes, double *tflops, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -96,6 +96,11 @@ def library(path=LIB_PATH):
     if hasattr(L, "tns_profile_events"):
         L.tns_profile_events.restype = None
         L.tns_profile_events.argtypes = [_P, _P, _P]
+    if hasattr(L, "tns_mfma_peak"):
+        L.tns_mfma_peak_workspace_bytes.restype = sz
+        L.tns_mfma_peak_workspace_bytes.argtypes = []
+        L.tns_mfma_peak.restype = ctypes.c_int
+        L.tns_mfma_peak.argtypes = [ctypes.c_int, ctypes.c_int, _P, sz, ctypes.POINTER(ctypes.c_double), _P]
     if hasattr(L, "tns_set_tiles"):
         L.tns_set_tiles.restype = ctypes.c_int
         L.tns_set_tiles.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_uint32, _P]
@@ -473,3 +478,17 @@ class HeffFunction(torch.autograd.Function):
 
 def heff(psi, vals, problem, prec="f64"):
     return HeffFunction.apply(psi, vals, problem, prec)
+
+
+def mfma_peak(prec, iters=20000):
+    """Measured MFMA throughput (TFLOP/s of MFMA instructions) of the current
+    device for the instruction the precision's product uses
+    (``tns_mfma_peak``)."""
+    L = library()
+    n = L.tns_mfma_peak_workspace_bytes()
+    if n == 0:
+        raise TnsError(-5, "tns_mfma_peak_workspace_bytes")
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_double(0.0)
+    _check(L.tns_mfma_peak(prec_id(prec), int(iters), _ptr(ws), n, ctypes.byref(out), _stream()), "tns_mfma_peak")
+    return out.value
