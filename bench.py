@@ -131,6 +131,23 @@ def phase_flops(P, tasks):
     fa = int(np.sum(np.where(idX, 0, 2 * R * K1 * K2)))
     fb = int(np.sum(np.where(idY, 0, 2 * R * K2 * C)))
     return fa, fb
+def backward_flops(P, tasks):
+    """Algorithmic flops of the backward product (d psi and the operator-block
+    gradients of every task): d psi = alpha L^T G R as (L^T G) R, d L = alpha
+    G R psi^T as (G R) psi^T, d R = alpha G^T L psi as (G^T L) psi; an
+    identity side drops its product (and d of an identity is not formed)."""
+    out, inn = tasks["out"], tasks["in"]
+    q = P.dimL[P.psi_sec[out, 0]].astype(np.int64)
+    r = P.dimR[P.psi_sec[out, 3]].astype(np.int64)
+    m = P.dimL[P.psi_sec[inn, 0]].astype(np.int64)
+    n = P.dimR[P.psi_sec[inn, 3]].astype(np.int64)
+    iL, iR = tasks["lblk"] < 0, tasks["rblk"] < 0
+    dpsi = np.where(iL, 0, 2 * m * q * r) + np.where(iR, 0, 2 * m * r * n)
+    dL = np.where(iL, 0, np.where(iR, 2 * q * r * m, 2 * q * r * n + 2 * q * n * m))
+    dR = np.where(iR, 0, np.where(iL, 2 * r * q * n, 2 * r * q * m + 2 * r * m * n))
+    return int(dpsi.sum()), int(dL.sum() + dR.sum())
+
+
 CONFIGS = {
     "d4096": dict(L=54, N=54, twoSz=0, D=4096, mean=64, dmax=512, K=3000, seed=3, gapped=True),
     "d1024": dict(L=30, N=30, twoSz=0, D=1024, mean=32, dmax=256, K=900, seed=2, gapped=False),
@@ -237,14 +254,72 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_grad(args):
+    """Forward and hand-written backward (d psi and every operator-block
+    gradient) of the L=30, D=1024 workload in FP32, checked against the FP64
+    backward.  Prints one JSON line."""
+    import torch
+    from synth import synthetic_problem, gaussian_psi
+    from paper_2305_05581_amd.tns import HeffProblem
+    cfg = CONFIGS["d1024"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P = synthetic_problem(cfg["L"], cfg["N"], cfg["twoSz"], cfg["D"], cfg["mean"], cfg["dmax"], cfg["K"],
+                          seed=5, threads=min(16, os.cpu_count() or 1))
+    H = HeffProblem(P, device=dev)
+    prec = args.only or "f32"
+    psi64 = torch.from_numpy(gaussian_psi(P, 5)).to(dev)
+    x = psi64.float() if prec != "f64" else psi64
+    tasks, _ = H.tasks()
+    fwd = H.total_flops
+    f_dpsi, f_dops = backward_flops(P, tasks)
+    log("grad1024: tasks %d, forward %.1f GFLOP, backward %.1f GFLOP (d psi %.1f, d operators %.1f)"
+        % (H.ntasks, fwd / 1e9, (f_dpsi + f_dops) / 1e9, f_dpsi / 1e9, f_dops / 1e9))
+    G = x  # loss <psi, sigma>: d loss / d sigma = psi
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    t_f = timed(lambda: H.apply(x, prec), args.steps)
+    t_b = timed(lambda: H.backward(x, G, prec), args.steps)
+    gp, go = H.backward(x, G, prec)
+    gp64, go64 = H.backward(psi64, psi64, "f64")
+    rel = lambda a, b: float(torch.linalg.norm(a.double() - b) / torch.linalg.norm(b))
+    e_psi, e_ops = rel(gp, gp64), rel(go, go64)
+    log("forward %.2f ms %.1f TFLOP/s; backward %.2f ms %.1f TFLOP/s; rel err vs FP64: d psi %.1e, d ops %.1e"
+        % (t_f * 1e3, fwd / t_f / 1e12, t_b * 1e3, (f_dpsi + f_dops) / t_b / 1e12, e_psi, e_ops))
+    bflops = f_dpsi + f_dops
+    line = {
+        "metric": "H_eff backward (d psi + d operator blocks) TFLOP/s", "value": round(bflops / t_b / 1e12, 3),
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_b * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "grad1024: L=30 N=30 2Sz=0 D=1024 per block (mean sector 32, max 256), %d terms, "
+                               "seed 5" % P.nTerms, "tasks": H.ntasks, "backward_flops": bflops,
+                   "forward_flops": fwd},
+        "forward": {"ms_per_step": round(t_f * 1e3, 3), "tflops": round(fwd / t_f / 1e12, 3)},
+        "pct_mfma_peak": round(100 * bflops / t_b / 1e12 / PEAK[prec], 2),
+        "rel_err_vs_f64": {"d_psi": e_psi, "d_ops": e_ops},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "f32", "f64"])
-    ap.add_argument("--config", default="d4096", choices=sorted(CONFIGS) + ["batch64"],
-                    help="batch64: many uneven instances, one launch per phase vs one product at a time")
+    ap.add_argument("--config", default="d4096", choices=sorted(CONFIGS) + ["batch64", "grad1024"],
+                    help="batch64: many uneven instances, one launch per phase vs one product at a time; "
+                         "grad1024: forward and backward at L=30, D=1024")
     ap.add_argument("--instances", type=int, default=64, help="batch64: number of instances")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library's tile autotuner (per sector-size bucket) before timing")
@@ -269,6 +344,9 @@ def main():
         sys.exit(2)
     if args.config == "batch64":
         bench_batch(args)
+        return
+    if args.config == "grad1024":
+        bench_grad(args)
         return
 
     import torch

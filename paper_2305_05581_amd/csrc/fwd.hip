@@ -186,7 +186,7 @@ __device__ inline int pop_work(const FwdArgs &g) {
   return -1;
 }
 
-// --- the LDS ring: direct global -> LDS loads, BNS stages ---------------------------
+// --- the LDS ring: direct global -> LDS loads, NS stages ----------------------------
 // A stage holds the 128 x BK tiles of A and of B (BF16X3: high and low
 // halves) as arrays of eight 1 KB chunks; a chunk (16 rows of 64 bytes = 4
 // 16-byte k-vectors) is the target of one global_load_lds_dwordx4 of a wave.
@@ -194,14 +194,13 @@ __device__ inline int pop_work(const FwdArgs &g) {
 // FP32 [A, B] (BK = 16) and FP64 [A, B] (BK = 8), 16 KB per stage, so that
 // two workgroups share a CU.  The k-vectors of row r sit at slots
 // kv ^ ((r >> 1) & 3), so that the 16 rows read by one MFMA operand fetch
-// fall into distinct LDS banks.  Loads run BNS - 1 stages ahead of the MFMA
+// fall into distinct LDS banks.  Loads run NS - 1 stages ahead of the MFMA
 // work; a stage is consumed after a counted vector-memory wait and one
 // barrier (no fence, in-flight stages stay in flight).  Out-of-range rows and
 // whole k-vectors beyond K read the zero region; the library's own operands
 // (T, padded psi, the identity) hold zeros beyond K, so the k-tail of an
 // operator row always meets zeros.
 typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
-constexpr int BNS = 4;
 
 // KS: k-halves per stage of FP32 / FP64 (each half 4 k-vectors of 16 bytes
 // per row, one array of chunks per operand and half); BF16X3 uses KS = 1 and
@@ -216,22 +215,29 @@ template <int P, int KS> struct RingL {
   static constexpr int LOADS = CH / 4;                      // global_load_lds per wave and stage
   static constexpr int BK = P == TNS_BF16X3 ? 32 : KS * 4 * RingP<P>::VEC;
 };
-// The stages are separate LDS arrays and every access names its stage at
-// compile time (the stage loop is unrolled BNS times): the compiler then
-// tells the direct loads into one stage from the operand reads of another
-// and does not drain the ring before each stage's reads.
+// The NS stages (4 or 5) are separate LDS arrays and every access names its
+// stage at compile time (the stage loop is unrolled NS times): the compiler
+// then tells the direct loads into one stage from the operand reads of
+// another and does not drain the ring before each stage's reads.
 template <int P, int KS> struct __attribute__((aligned(16))) Stage {
   uint8_t b[RingL<P, KS>::CH * 1024];
 };
-template <int P, int KS> struct Ring {
-  Stage<P, KS> &s0, &s1, &s2, &s3;
+struct __attribute__((aligned(16))) NoStage {
+  uint8_t b[16];
 };
-template <int J, int P, int KS>
-__device__ inline Stage<P, KS> &stage(Ring<P, KS> &r) {
+template <int P, int KS, int NS> using Stage4 = typename std::conditional<NS == 5, Stage<P, KS>, NoStage>::type;
+template <int P, int KS, int NS> struct Ring {
+  static_assert(NS == 4 || NS == 5, "four or five stages");
+  Stage<P, KS> &s0, &s1, &s2, &s3;
+  Stage4<P, KS, NS> &s4;
+};
+template <int J, int P, int KS, int NS>
+__device__ inline Stage<P, KS> &stage(Ring<P, KS, NS> &r) {
   if constexpr (J == 0) return r.s0;
   else if constexpr (J == 1) return r.s1;
   else if constexpr (J == 2) return r.s2;
-  else return r.s3;
+  else if constexpr (J == 3) return r.s3;
+  else return r.s4;
 }
 __device__ inline int rswz(int rin) { return (rin >> 1) & 3; }
 
@@ -247,21 +253,21 @@ __device__ inline void gl_lds(const void *src, void *dst) {
                                    (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
 }
 
-// Waits until at most two stages of this wave's ring loads are in flight
+// Waits until at most NS - 2 stages of this wave's ring loads are in flight
 // (vector-memory loads complete in order) and, with LGKM, until its LDS reads
 // are complete, then joins the workgroup.  No fence: only the LDS written by
 // this kernel's ring loads is exchanged here.
-template <int P, int KS, bool LGKM>
+template <int P, int KS, int NS, bool LGKM>
 __device__ inline void ring_sync() {
-  constexpr int E = (7 << 4) | ((LGKM ? 0 : 15) << 8), L = RingL<P, KS>::LOADS;  // expcnt: no wait
-  __builtin_amdgcn_s_waitcnt(E | (2 * L & 15) | ((2 * L >> 4) << 14));
+  constexpr int E = (7 << 4) | ((LGKM ? 0 : 15) << 8), N = (NS - 2) * RingL<P, KS>::LOADS;  // expcnt: no wait
+  static_assert(N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(E | (N & 15) | ((N >> 4) << 14));
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
 }
 
 // Waits for every ring load of this wave (before the workgroup exits).
 __device__ inline void ring_drain() { __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8)); }
-static_assert(BNS == 4, "ring_sync and ring_run assume four stages");
 
 // Source of one 16-row chunk of the A operand: rows p + i * ld, i < vrows
 // (BF16X3: low halves `lo` elements further).
@@ -411,42 +417,48 @@ __device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS
 template <int P, int PH> struct Geo {
   static constexpr int KS = 1;
   static constexpr int WG = P == TNS_BF16X3 ? 1 : 2;
+  static constexpr int NS = 4;
   static constexpr bool PF = true;
 };
 
 // Drives the ring over one stream of K steps: issue(stage) fills a stage
 // with the next step and advances the load cursor, returning false (after
-// filling the stage with zeros) once the stream is exhausted; compute(stage)
-// consumes one step.  Loads run BNS - 1 steps ahead; step s uses stage
-// s mod BNS, written BNS - 1 steps earlier.  Every step issues a stage and
+// filling the stage with zeros) once the stream is exhausted; compute(frags)
+// consumes one step.  Loads run NS - 1 steps ahead; step s uses stage
+// s mod NS, written NS - 1 steps earlier.  Every step issues a stage and
 // only the computation is conditional: with the direct loads on every path
 // of a loop without early exits, the compiler keeps track of which stage
 // each operand read depends on.
 //
-// PF (prefetch): the fragments of stage s + 1 are read into registers during
-// step s, while the MFMA work of stage s (read one step earlier) runs; the
-// slot of stage s is then free at step s and receives stage s + BNS.  Each
-// step waits for this wave's outstanding LDS reads before the barrier, so no
-// slot is overwritten while a read of it is in flight.
-template <int P, int KS, bool PF, class FR, class Issue, class Compute>
-__device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS> &rg, Issue &&issue, Compute &&compute) {
+// PF (prefetch, four stages): the fragments of stage s + 1 are read into
+// registers during step s, while the MFMA work of stage s (read one step
+// earlier) runs; the slot of stage s is then free at step s and receives
+// stage s + 4.  Each step waits for this wave's outstanding LDS reads before
+// the barrier, so no slot is overwritten while a read of it is in flight.
+template <int... J, class F>
+__device__ __attribute__((always_inline)) inline void static_for(std::integer_sequence<int, J...>, F &&f) {
+  (f(std::integral_constant<int, J>{}), ...);
+}
+
+template <int P, int KS, int NS, bool PF, class FR, class Issue, class Compute>
+__device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &rg, Issue &&issue,
+                                                               Compute &&compute) {
   int issued = 0;
-  issued += issue(rg.s0);
-  issued += issue(rg.s1);
-  issued += issue(rg.s2);
+  static_for(std::make_integer_sequence<int, NS - 1>{}, [&](auto J) { issued += issue(stage<J>(rg)); });
   if constexpr (PF) {
+    static_assert(NS == 4, "prefetch alternates two fragment sets over four stages");
     FR f0, f1;
-    ring_sync<P, KS, false>();
+    ring_sync<P, KS, NS, false>();
     issued += issue(rg.s3);
     ring_read(rg.s0, f0);
     auto step = [&](auto J, int s, FR &cur, FR &nxt) {
       constexpr int j = decltype(J)::value;
-      ring_sync<P, KS, true>();
+      ring_sync<P, KS, NS, true>();
       issued += issue(stage<j>(rg));
-      if (s + 1 < issued) ring_read(stage<(j + 1) % BNS>(rg), nxt);
+      if (s + 1 < issued) ring_read(stage<(j + 1) % NS>(rg), nxt);
       if (s < issued) compute(cur);
     };
-    for (int s = 0; s < issued; s += BNS) {
+    for (int s = 0; s < issued; s += NS) {
       step(std::integral_constant<int, 0>{}, s, f0, f1);
       step(std::integral_constant<int, 1>{}, s + 1, f1, f0);
       step(std::integral_constant<int, 2>{}, s + 2, f0, f1);
@@ -454,20 +466,16 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS> &rg, 
     }
   } else {
     FR f;
-    auto step = [&](auto J, int s) {
-      constexpr int j = decltype(J)::value;
-      ring_sync<P, KS, false>();
-      issued += issue(stage<(j + BNS - 1) % BNS>(rg));
-      if (s < issued) {
-        ring_read(stage<j>(rg), f);
-        compute(f);
-      }
-    };
-    for (int s = 0; s < issued; s += BNS) {
-      step(std::integral_constant<int, 0>{}, s);
-      step(std::integral_constant<int, 1>{}, s + 1);
-      step(std::integral_constant<int, 2>{}, s + 2);
-      step(std::integral_constant<int, 3>{}, s + 3);
+    for (int s = 0; s < issued; s += NS) {
+      static_for(std::make_integer_sequence<int, NS>{}, [&](auto J) {
+        constexpr int j = decltype(J)::value;
+        ring_sync<P, KS, NS, false>();
+        issued += issue(stage<(j + NS - 1) % NS>(rg));
+        if (s + j < issued) {
+          ring_read(stage<j>(rg), f);
+          compute(f);
+        }
+      });
     }
   }
 }
@@ -495,7 +503,8 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS> &rg, 
 
 // --- phase B: one item (output tile, chunk of tasks) ------------------------------------
 template <int P, int KS, int TM, int TN>
-__device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it, int mode) {
+__device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
+                                                                    const Item &it, int mode) {
   typedef typename FP<P>::A4 A4;
   constexpr int BK = RingL<P, KS>::BK;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -516,7 +525,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   };
   load_seg();
   typedef Frags<P, KS, TM, TN> FR;
-  ring_run<P, KS, Geo<P, 1>::PF, FR>(
+  ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR>(
       rg,
       [&](Stage<P, KS> &st) {
         const bool live = !ldone;
@@ -549,7 +558,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
 }
 
 template <int P, int KS>
-__device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
+__device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
+                                                                  int wk) {
   const Item it = load_item(g.items + wk);
   const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
 #define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode)
@@ -649,7 +659,8 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
 }
 
 template <int P, int KS, int TN>
-__device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS> &rg, const Item &it) {
+__device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
+                                                                    const Item &it) {
   typedef typename FP<P>::A4 A4;
   typedef typename FP<P>::E E;
   constexpr int BK = RingL<P, KS>::BK;
@@ -667,7 +678,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
   const int blim = min(B.rows, it.c0 + 32 * TN);
   const int ch_end = it.p0 + it.np;
   const int64_t tbase = cld(&g.a_tb[G]) - cld(&g.a_gch[G]) * PCH * ldT;
-  // load cursor: (tile's first chunk, k); compute cursor BNS - 1 steps behind
+  // load cursor: (tile's first chunk, k); compute cursor NS - 1 steps behind
   int lch = it.p0, lk0 = 0, cch = it.p0, ck0 = 0;
   bool ldone = false;
   CSrc as[2];
@@ -678,7 +689,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
   typedef Frags<P, KS, 4, TN> FR;
-  ring_run<P, KS, Geo<P, 0>::PF, FR>(
+  ring_run<P, KS, Geo<P, 0>::NS, Geo<P, 0>::PF, FR>(
       rg,
       [&](Stage<P, KS> &st) {
         const bool live = !ldone;
@@ -700,7 +711,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
 }
 
 template <int P, int KS>
-__device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs &g, Ring<P, KS> &rg, int wk) {
+__device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
+                                                                  int wk) {
   const Item it = load_item(g.a_items + wk);
   switch ((it.mode >> 16) & 0xff) {
     case 1: ring_item_a_t<P, KS, 1>(g, rg, it); break;
@@ -737,20 +749,23 @@ __global__ void k_chunk_recs(FwdArgs g) {
 
 template <int P, int PH>
 __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
-  constexpr int KS = Geo<P, PH>::KS;
+  constexpr int KS = Geo<P, PH>::KS, NS = Geo<P, PH>::NS;
   __shared__ Stage<P, KS> st0, st1, st2, st3;
-  Ring<P, KS> rg{st0, st1, st2, st3};
-  __shared__ int s_work;
+  __shared__ Stage4<P, KS, NS> st4;
+  Ring<P, KS, NS> rg{st0, st1, st2, st3, st4};
+  int *s_work = reinterpret_cast<int *>(st0.b);  // the ring is idle between items
   for (;;) {
-    if (threadIdx.x == 0) s_work = pop_work<PH>(g);
+    ring_drain();  // the previous item's trailing (zero) loads have landed
+    __syncthreads();
+    if (threadIdx.x == 0) *s_work = pop_work<PH>(g);
     __syncthreads();
     // uniform: the item's metadata then comes through scalar loads, which
     // leave the vector-memory count (ring loads in flight) alone
-    const int wk = __builtin_amdgcn_readfirstlane(s_work);
+    const int wk = __builtin_amdgcn_readfirstlane(*s_work);
     __syncthreads();
     if (wk < 0) break;
-    if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
-    else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
+    if (PH == 0) ring_item_a<P, KS>(g, rg, wk);
+    else ring_item_b<P, KS>(g, rg, wk);
   }
   ring_drain();
 }
@@ -893,19 +908,22 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
 
 template <int P, int PH>
 __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b) {
-  constexpr int KS = Geo<P, PH>::KS;
+  constexpr int KS = Geo<P, PH>::KS, NS = Geo<P, PH>::NS;
   __shared__ Stage<P, KS> st0, st1, st2, st3;
-  Ring<P, KS> rg{st0, st1, st2, st3};
-  __shared__ int s_w[2];
+  __shared__ Stage4<P, KS, NS> st4;
+  Ring<P, KS, NS> rg{st0, st1, st2, st3, st4};
+  int *s_w = reinterpret_cast<int *>(st0.b);  // the ring is idle between items
   for (;;) {
+    ring_drain();  // the previous item's trailing (zero) loads have landed
+    __syncthreads();
     if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
     __syncthreads();
     const int inst = __builtin_amdgcn_readfirstlane(s_w[0]), wk = __builtin_amdgcn_readfirstlane(s_w[1]);
     __syncthreads();
     if (inst < 0) break;
     const FwdArgs g = load_words(&b.tab[inst].g);
-    if (PH == 0) ring_item_a<P, Geo<P, PH>::KS>(g, rg, wk);
-    else ring_item_b<P, Geo<P, PH>::KS>(g, rg, wk);
+    if (PH == 0) ring_item_a<P, KS>(g, rg, wk);
+    else ring_item_b<P, KS>(g, rg, wk);
   }
   ring_drain();
 }
