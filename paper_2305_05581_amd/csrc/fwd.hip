@@ -269,66 +269,54 @@ __device__ inline void ring_sync() {
 // Waits for every ring load of this wave (before the workgroup exits).
 __device__ inline void ring_drain() { __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8)); }
 
-// Source of one 16-row chunk of the A operand: rows p + i * ld, i < vrows
-// (BF16X3: low halves `lo` elements further).
-struct CSrc {
-  const void *p;
-  int64_t lo;
-  int32_t ld, vrows;
+// Per-lane sources of the four 16-row chunks a wave loads into every stage:
+// q = 0, 1 the A chunks w and w + 4, q = 2, 3 the B chunks w and w + 4 of the
+// 8 in each array.  ptr[q] is the byte address of the lane's row at k = 0
+// (BF16X3: high half; the low half lies lo[q] bytes further), klim[q] the
+// row's K, 0 for a row outside its operand (whose loads then read zeros).
+// Set when a segment or tile starts, so that issuing a stage is branch-free.
+struct LoadSet {
+  const char *ptr[4];
+  int64_t lo[4];
+  int32_t klim[4];
 };
 
-// The two A chunks a wave loads (chunks w and w + 4 of the 8) from rows
-// [r0, rlim) of M.
+// Rows [r0, r0 + 128) of M into slots q0, q0 + 1 (rows beyond rlim read zeros).
 template <int P>
-__device__ __attribute__((always_inline)) inline void mat_srcs(const Mat &M, int r0, int rlim, CSrc (&as)[2]) {
+__device__ __attribute__((always_inline)) inline void ls_mat(LoadSet &ls, int q0, const Mat &M, int r0, int rlim,
+                                                             int K) {
   typedef typename FP<P>::E E;
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, rin = (threadIdx.x & 63) >> 2;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int r = r0 + 16 * (w + 4 * u);
-    as[u].p = reinterpret_cast<const E *>(M.p) + (int64_t)r * M.ld;
-    as[u].lo = M.lo;
-    as[u].ld = M.ld;
-    as[u].vrows = min(16, rlim - r);
+  for (int v = 0; v < 2; ++v) {
+    const int row = r0 + 16 * (w + 4 * v) + rin;
+    ls.ptr[q0 + v] = reinterpret_cast<const char *>(reinterpret_cast<const E *>(M.p) + (int64_t)row * M.ld);
+    ls.lo[q0 + v] = M.lo * (int64_t)sizeof(E);
+    ls.klim[q0 + v] = row < rlim ? K : 0;
   }
 }
 
-// Stage `buf` <- the A chunks of `as` and rows [c0, blim) of B (rows of the
-// 128-row window beyond blim read zeros), k in [k0, k0 + BK).
+// Stage <- one K step (k in [k0, k0 + BK)) of the chunks of ls; with live
+// false every load reads the zero region.  Branch-free.
 template <int P, int KS>
-__device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &st, const CSrc (&as)[2], const Mat &B, int c0, int blim, int k0,
-                                  int K, const void *zero) {
+__device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &st, const LoadSet &ls, int k0,
+                                                                 bool live, const void *zero) {
   typedef typename FP<P>::E E;
+  static_assert(KS == 1, "one k-range per stage");
   constexpr int VEC = RingP<P>::VEC, L = RingL<P, KS>::LOADS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rin = lane >> 2;
-  const int kl = VEC * ((lane & 3) ^ rswz(rin));
-  const E *z = reinterpret_cast<const E *>(zero);
+  const int k = k0 + VEC * ((lane & 3) ^ rswz(rin));
+  const char *z = reinterpret_cast<const char *>(zero);
 #pragma unroll
   for (int u = 0; u < L; ++u) {
     const int c = w + 4 * u;  // chunk of the stage; array h = c / 8 = u / 2
     const int h = u / 2;
-    bool isB, lo;
-    int k = k0 + kl;
-    if (P == TNS_BF16X3) {
-      isB = h >= 2;
-      lo = h & 1;
-    } else {
-      isB = h >= KS;
-      lo = false;
-      k += (h - KS * (int)isB) * 4 * VEC;  // k-half
-    }
-    const E *src;
-    bool in;
-    if (!isB) {  // chunk c - 8 h = w + 4 (u & 1) of A
-      const CSrc &S = as[u & 1];
-      in = k < K && rin < S.vrows;
-      src = reinterpret_cast<const E *>(S.p) + (lo ? S.lo : 0) + (int64_t)rin * S.ld + k;
-    } else {
-      const int row = c0 + 16 * (c - 8 * h) + rin;
-      in = k < K && row < blim;
-      src = reinterpret_cast<const E *>(B.p) + (lo ? B.lo : 0) + (int64_t)row * B.ld + k;
-    }
+    const bool isB = P == TNS_BF16X3 ? h >= 2 : h >= 1;
+    const bool lo = P == TNS_BF16X3 && (h & 1);
+    const int q = (isB ? 2 : 0) + (u & 1);
+    const bool in = live && k < ls.klim[q];
+    const char *src = ls.ptr[q] + (lo ? ls.lo[q] : 0) + (int64_t)k * (int64_t)sizeof(E);
     gl_lds(in ? src : z, &st.b[c * 1024]);
   }
 }
@@ -421,14 +409,16 @@ template <int P, int PH> struct Geo {
   static constexpr bool PF = true;
 };
 
-// Drives the ring over one stream of K steps: issue(stage) fills a stage
-// with the next step and advances the load cursor, returning false (after
-// filling the stage with zeros) once the stream is exhausted; compute(frags)
-// consumes one step.  Loads run NS - 1 steps ahead; step s uses stage
+// Drives the ring over one stream of K steps.  dma(stage) fills a stage
+// with the load cursor's K step (zeros once the stream is exhausted) and
+// adv() moves the cursor on, returning 1 for a real step and 0 past the end;
+// mma(frags) is the MFMA work of one step and post() runs after each real
+// step (tile completion).  Loads run NS - 1 steps ahead; step s uses stage
 // s mod NS, written NS - 1 steps earlier.  Every step issues a stage and
-// only the computation is conditional: with the direct loads on every path
-// of a loop without early exits, the compiler keeps track of which stage
-// each operand read depends on.
+// runs its MFMA work (past the end on zeros): the loads, the operand reads
+// and the MFMA work of a step form one branch-free block that the compiler
+// can interleave, and with the direct loads on every path of a loop without
+// early exits the compiler keeps track of which stage each read depends on.
 //
 // PF (prefetch, four stages): the fragments of stage s + 1 are read into
 // registers during step s, while the MFMA work of stage s (read one step
@@ -440,23 +430,29 @@ __device__ __attribute__((always_inline)) inline void static_for(std::integer_se
   (f(std::integral_constant<int, J>{}), ...);
 }
 
-template <int P, int KS, int NS, bool PF, class FR, class Issue, class Compute>
-__device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &rg, Issue &&issue,
-                                                               Compute &&compute) {
+template <int P, int KS, int NS, bool PF, class FR, class Dma, class Adv, class Mma, class Post>
+__device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &rg, Dma &&dma, Adv &&adv, Mma &&mma,
+                                                               Post &&post) {
   int issued = 0;
-  static_for(std::make_integer_sequence<int, NS - 1>{}, [&](auto J) { issued += issue(stage<J>(rg)); });
+  static_for(std::make_integer_sequence<int, NS - 1>{}, [&](auto J) {
+    dma(stage<J>(rg));
+    issued += adv();
+  });
   if constexpr (PF) {
     static_assert(NS == 4, "prefetch alternates two fragment sets over four stages");
     FR f0, f1;
     ring_sync<P, KS, NS, false>();
-    issued += issue(rg.s3);
+    dma(rg.s3);
+    issued += adv();
     ring_read(rg.s0, f0);
     auto step = [&](auto J, int s, FR &cur, FR &nxt) {
       constexpr int j = decltype(J)::value;
       ring_sync<P, KS, NS, true>();
-      issued += issue(stage<j>(rg));
-      if (s + 1 < issued) ring_read(stage<(j + 1) % NS>(rg), nxt);
-      if (s < issued) compute(cur);
+      dma(stage<j>(rg));
+      ring_read(stage<(j + 1) % NS>(rg), nxt);
+      mma(cur);
+      issued += adv();
+      if (s < issued) post();
     };
     for (int s = 0; s < issued; s += NS) {
       step(std::integral_constant<int, 0>{}, s, f0, f1);
@@ -470,11 +466,11 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &
       static_for(std::make_integer_sequence<int, NS>{}, [&](auto J) {
         constexpr int j = decltype(J)::value;
         ring_sync<P, KS, NS, false>();
-        issued += issue(stage<(j + NS - 1) % NS>(rg));
-        if (s + j < issued) {
-          ring_read(stage<j>(rg), f);
-          compute(f);
-        }
+        dma(stage<(j + NS - 1) % NS>(rg));
+        ring_read(stage<j>(rg), f);
+        mma(f);
+        issued += adv();
+        if (s + j < issued) post();
       });
     }
   }
@@ -514,31 +510,29 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  int ls = it.tb, lj = 0, lK, blim;
+  int seg = it.tb, lj = 0, lK;
   bool ldone = false;  // every segment has lK >= 1
-  Mat LA, LB;
-  CSrc as[2];
+  LoadSet LS;
   auto load_seg = [&]() {
-    seg_ops<P, 1>(g, cld(&g.idx[ls]), LA, LB, lK, nullptr);
-    mat_srcs<P>(LA, it.p0, min(LA.rows, it.p0 + 32 * TM), as);
-    blim = min(LB.rows, it.c0 + 32 * TN);
+    Mat LA, LB;
+    seg_ops<P, 1>(g, cld(&g.idx[seg]), LA, LB, lK, nullptr);
+    ls_mat<P>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
+    ls_mat<P>(LS, 2, LB, it.c0, min(LB.rows, it.c0 + 32 * TN), lK);
   };
   load_seg();
   typedef Frags<P, KS, TM, TN> FR;
   ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR>(
-      rg,
-      [&](Stage<P, KS> &st) {
-        const bool live = !ldone;
-        ring_issue<P, KS>(st, as, LB, it.c0, blim, lj * BK, live ? lK : 0, g.zero);
-        if (!live) return false;
+      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS>(st, LS, lj * BK, !ldone, g.zero); },
+      [&]() -> int {
+        if (ldone) return 0;
         if (++lj * BK >= lK) {
           lj = 0;
-          if (++ls < it.te) load_seg();
+          if (++seg < it.te) load_seg();
           else ldone = true;
         }
-        return true;
+        return 1;
       },
-      [&](const FR &f) { ring_mma<P, KS, TM, TN, false>(f, acc); });
+      [&](const FR &f) { ring_mma<P, KS, TM, TN, false>(f, acc); }, [] {});
   const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
   auto slot = gptr(reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]));
 #pragma unroll
@@ -573,32 +567,37 @@ __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs 
 // right operand (the padded psi sector), and the ring keeps loading across
 // tile boundaries.
 
-// Sources of the two A chunks of this wave in the tile starting at chunk ch
-// (chunks at or beyond ch_end are empty).
+// Sources of the two A chunks of this wave (slots 0, 1) in the tile
+// starting at chunk ch, inner dimension K (chunks at or beyond ch_end read
+// zeros).
 template <int P>
-__device__ __attribute__((always_inline)) inline void chunk_srcs(const FwdArgs &g, int ch, int ch_end, CSrc (&as)[2]) {
+__device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g, LoadSet &ls, int ch, int ch_end,
+                                                                int K) {
   typedef typename FP<P>::E E;
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, rin = (threadIdx.x & 63) >> 2;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int c = __builtin_amdgcn_readfirstlane(ch + w + 4 * u);  // uniform: scalar loads
-    as[u].p = g.zero;
-    as[u].lo = 0;
-    as[u].ld = 0;
-    as[u].vrows = 0;
+    ls.ptr[u] = reinterpret_cast<const char *>(g.zero);
+    ls.lo[u] = 0;
+    ls.klim[u] = 0;
     if (c < ch_end) {
       const ChunkRec *r = g.recs + c;
       const int64_t off = cld(&r->off);
-      as[u].vrows = cld(&r->vrows);
+      const int vr = cld(&r->vrows);
+      const E *p;
+      int ld;
       if (off >= 0) {
-        as[u].p = reinterpret_cast<const E *>(g.ops) + off;
-        as[u].lo = g.ops_lo;
-        as[u].ld = cld(&r->ld);
+        p = reinterpret_cast<const E *>(g.ops) + off;
+        ld = cld(&r->ld);
+        ls.lo[u] = g.ops_lo * (int64_t)sizeof(E);
       } else {  // identity side: rows of the identity matrix
-        as[u].p = reinterpret_cast<const E *>(g.ident) + (-1 - off) * g.ident_ld;
-        as[u].lo = g.ident_lo;
-        as[u].ld = g.ident_ld;
+        p = reinterpret_cast<const E *>(g.ident) + (-1 - off) * g.ident_ld;
+        ld = g.ident_ld;
+        ls.lo[u] = g.ident_lo * (int64_t)sizeof(E);
       }
+      ls.ptr[u] = reinterpret_cast<const char *>(p + (int64_t)rin * ld);
+      ls.klim[u] = rin < vr ? K : 0;
     }
   }
 }
@@ -675,14 +674,14 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
     B.p = reinterpret_cast<const E *>(g.pp) + cld(&g.pp_off[sec]);
     B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m;
   }
-  const int blim = min(B.rows, it.c0 + 32 * TN);
   const int ch_end = it.p0 + it.np;
   const int64_t tbase = cld(&g.a_tb[G]) - cld(&g.a_gch[G]) * PCH * ldT;
   // load cursor: (tile's first chunk, k); compute cursor NS - 1 steps behind
   int lch = it.p0, lk0 = 0, cch = it.p0, ck0 = 0;
   bool ldone = false;
-  CSrc as[2];
-  chunk_srcs<P>(g, lch, ch_end, as);
+  LoadSet LS;
+  ls_chunks<P>(g, LS, lch, ch_end, K);
+  ls_mat<P>(LS, 2, B, it.c0, min(B.rows, it.c0 + 32 * TN), K);
   A4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -690,19 +689,17 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
   typedef Frags<P, KS, 4, TN> FR;
   ring_run<P, KS, Geo<P, 0>::NS, Geo<P, 0>::PF, FR>(
-      rg,
-      [&](Stage<P, KS> &st) {
-        const bool live = !ldone;
-        ring_issue<P, KS>(st, as, B, it.c0, blim, lk0, live ? K : 0, g.zero);
-        if (!live) return false;
-        if ((lk0 += BK) < K) return true;
+      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS>(st, LS, lk0, !ldone, g.zero); },
+      [&]() -> int {
+        if (ldone) return 0;
+        if ((lk0 += BK) < K) return 1;
         lk0 = 0;
-        if ((lch += PTILE_CH) < ch_end) chunk_srcs<P>(g, lch, ch_end, as);
+        if ((lch += PTILE_CH) < ch_end) ls_chunks<P>(g, LS, lch, ch_end, K);
         else ldone = true;
-        return true;
+        return 1;
       },
-      [&](const FR &f) {
-        ring_mma<P, KS, 4, TN, true>(f, acc);
+      [&](const FR &f) { ring_mma<P, KS, 4, TN, true>(f, acc); },
+      [&]() {
         if ((ck0 += BK) < K) return;
         ck0 = 0;
         ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, ldT);
