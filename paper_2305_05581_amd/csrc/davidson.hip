@@ -33,23 +33,47 @@ static inline unsigned nbk(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 // alpha * L_ii * R_jj at element (i, j); one workgroup per sector, tasks in
 // table order.
 // ---------------------------------------------------------------------------
-__global__ void k_diag(Plan p, const double *__restrict__ ops, double *__restrict__ d) {
+// The sector's diagonal tasks are staged in LDS in batches (table order kept).
+constexpr int DIAG_BATCH = 256;
+__global__ __launch_bounds__(256) void k_diag(Plan p, const double *__restrict__ ops, double *__restrict__ d) {
+  __shared__ double s_alpha[DIAG_BATCH];
+  __shared__ int64_t s_loff[DIAG_BATCH], s_roff[DIAG_BATCH];
+  __shared__ int s_lld[DIAG_BATCH], s_rld[DIAG_BATCH];
+  __shared__ int s_n;
   const int s = blockIdx.x;
   const int iL = p.psi_sec[4 * s], iR = p.psi_sec[4 * s + 3];
   const int m = p.dimL[iL], n = p.dimR[iR];
   const int64_t base = p.psi_off[s];
   const int t0 = p.out_ptr[s], t1 = p.out_ptr[s + 1];
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
-    double acc = 0.0;
-    for (int t = t0; t < t1; ++t) {
-      const tns_task tk = p.tasks[t];
-      if (tk.in != s) continue;
-      const double li = tk.lblk >= 0 ? ops[p.blk_off[tk.lblk] + (int64_t)i * p.blk_ld[tk.lblk] + i] : 1.0;
-      const double rj = tk.rblk >= 0 ? ops[p.blk_off[tk.rblk] + (int64_t)j * p.blk_ld[tk.rblk] + j] : 1.0;
-      acc += tk.alpha * li * rj;
+  for (int e = threadIdx.x; e < m * n; e += blockDim.x) d[base + e] = 0.0;
+  for (int tb = t0; tb < t1; tb += DIAG_BATCH) {
+    __syncthreads();
+    if (threadIdx.x == 0) {  // compact this batch's diagonal tasks, in table order
+      int c = 0;
+      for (int t = tb; t < min(t1, tb + DIAG_BATCH); ++t) {
+        const tns_task tk = p.tasks[t];
+        if (tk.in != s) continue;
+        s_alpha[c] = tk.alpha;
+        s_loff[c] = tk.lblk >= 0 ? p.blk_off[tk.lblk] : -1;
+        s_lld[c] = tk.lblk >= 0 ? p.blk_ld[tk.lblk] : 0;
+        s_roff[c] = tk.rblk >= 0 ? p.blk_off[tk.rblk] : -1;
+        s_rld[c] = tk.rblk >= 0 ? p.blk_ld[tk.rblk] : 0;
+        ++c;
+      }
+      s_n = c;
     }
-    d[base + e] = acc;
+    __syncthreads();
+    const int nb = s_n;
+    for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      double acc = d[base + e];
+      for (int c = 0; c < nb; ++c) {
+        const double li = s_loff[c] >= 0 ? ops[s_loff[c] + (int64_t)i * s_lld[c] + i] : 1.0;
+        const double rj = s_roff[c] >= 0 ? ops[s_roff[c] + (int64_t)j * s_rld[c] + j] : 1.0;
+        acc += s_alpha[c] * li * rj;
+      }
+      d[base + e] = acc;
+    }
   }
 }
 
@@ -85,12 +109,22 @@ __global__ __launch_bounds__(DOT_THREADS) void k_multidot(const double *__restri
   }
 }
 
-__global__ void k_reduce_parts(const double *__restrict__ part, int nblocks, int k, double *__restrict__ out) {
-  const int i = threadIdx.x;
+// out[i] = sum over blocks of part[b][i]: one workgroup per i, each thread a
+// strided partial sum, then a fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_parts(const double *__restrict__ part, int nblocks, int k,
+                                                      double *__restrict__ out) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
   if (i >= k) return;
   double v = 0.0;
-  for (int b = 0; b < nblocks; ++b) v += part[(int64_t)b * DV_MAXSUB + i];
-  out[i] = v;
+  for (int b = threadIdx.x; b < nblocks; b += 256) v += part[(int64_t)b * DV_MAXSUB + i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
 }
 
 // x = beta x + sum_i y[i] V_i
@@ -337,7 +371,7 @@ static void multidot(const double *V, int64_t ldv, int k, const double *t, int64
   for (int k0 = 0; k0 < k; k0 += DOT_ROWS)
     hipLaunchKernelGGL(k_multidot, dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, st, V, ldv, k0, std::min(DOT_ROWS, k - k0),
                        t, N, d.part);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(DV_MAXSUB), 0, st, d.part, DOT_BLOCKS, k, out);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(std::max(k, 1)), dim3(256), 0, st, d.part, DOT_BLOCKS, k, out);
 }
 
 // dst = H src in precision prec (src, dst FP64)
