@@ -94,6 +94,7 @@ struct FwdArgs {
   const int64_t *a_qbase, *a_tb, *a_gch, *a_ch;
   const int32_t *a_idx;
   const ChunkRec *recs;  // chunk sources, written before phase A
+  const SegRec *segb;    // phase-B segments, in the order of idx
 };
 
 // --- per-precision tile parameters ---------------------------------------------
@@ -116,57 +117,6 @@ template <> struct FP<TNS_BF16X3> {
   typedef u16x8 V;
   typedef f4 A4;
 };
-
-// --- segment operands -------------------------------------------------------------
-// Operator block `blk` of an output with `rows` rows; blk < 0 is the identity,
-// read from the identity matrix in the workspace like any other operand.
-template <int P>
-__device__ inline Mat op_mat(const FwdArgs &g, int blk, int rows) {
-  typedef typename FP<P>::E E;
-  Mat m;
-  m.rows = rows;
-  if (blk < 0) {
-    m.p = g.ident; m.lo = g.ident_lo; m.ld = g.ident_ld;
-  } else {
-    m.p = reinterpret_cast<const E *>(g.ops) + cld(&g.blk_off[blk]);
-    m.lo = g.ops_lo;
-    m.ld = cld(&g.blk_ld[blk]);
-  }
-  return m;
-}
-
-// Operands (A, B) and inner dimension K of task t in phase PH.
-template <int P, int PH>
-__device__ inline void seg_ops(const FwdArgs &g, int t, Mat &A, Mat &B, int &K, double *alpha) {
-  typedef typename FP<P>::E E;
-  t = __builtin_amdgcn_readfirstlane(t);  // uniform: scalar loads of the task record
-  const tns_task *tp = g.tasks + t;
-  const int out = cld(&tp->out), in = cld(&tp->in), order = cld(&tp->order);
-  const int lblk = cld(&tp->lblk), rblk = cld(&tp->rblk);
-  const int *so = g.psi_sec + 4 * out, *si = g.psi_sec + 4 * in;
-  const int q = cld(&g.dimL[cld(&so[0])]), r = cld(&g.dimR[cld(&so[3])]);
-  const int m = cld(&g.dimL[cld(&si[0])]), n = cld(&g.dimR[cld(&si[3])]);
-  if (alpha) *alpha = cld(&tp->alpha);
-  if (PH == 0) {
-    if (order == 0) {  // T = L A: B(j, k) = A(k, j) = A^T(j, k)
-      K = m;
-      A = op_mat<P>(g, lblk, q);
-      B.p = reinterpret_cast<const E *>(g.pt) + cld(&g.pt_off[in]);
-      B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n;
-    } else {           // T = R A^T: B(j, k) = A(j, k)
-      K = n;
-      A = op_mat<P>(g, rblk, r);
-      B.p = reinterpret_cast<const E *>(g.pp) + cld(&g.pp_off[in]);
-      B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m;
-    }
-  } else {
-    const int k2 = order == 0 ? n : m;
-    K = k2;
-    A.p = reinterpret_cast<const E *>(g.T) + cld(&g.t_off[t]);
-    A.lo = g.T_lo; A.ld = ld8(k2); A.rows = order == 0 ? q : r;
-    B = order == 0 ? op_mat<P>(g, rblk, r) : op_mat<P>(g, lblk, q);
-  }
-}
 
 // --- work queues --------------------------------------------------------------------
 // Phase A: panel items, phase B: the schedule's items; queue q of a phase is
@@ -513,13 +463,33 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   int seg = it.tb, lj = 0, lK;
   bool ldone = false;  // every segment has lK >= 1
   LoadSet LS;
-  auto load_seg = [&]() {
+  // segment records through scalar loads; the next one is fetched while the
+  // current segment streams
+  auto fetch = [&](int pos, SegRec &r) {
+    const SegRec *q = g.segb + pos;
+    r.a_off = cld(&q->a_off); r.b_off = cld(&q->b_off);
+    r.K = cld(&q->K); r.arows = cld(&q->arows); r.brows = cld(&q->brows); r.bld = cld(&q->bld);
+  };
+  SegRec cur, nxt;
+  fetch(seg, cur);
+  if (seg + 1 < it.te) fetch(seg + 1, nxt);
+  auto load_seg = [&](const SegRec &r) {
+    typedef typename FP<P>::E E;
     Mat LA, LB;
-    seg_ops<P, 1>(g, cld(&g.idx[seg]), LA, LB, lK, nullptr);
+    lK = r.K;
+    LA.p = reinterpret_cast<const E *>(g.T) + r.a_off;
+    LA.lo = g.T_lo; LA.ld = ld8(r.K); LA.rows = r.arows;
+    if (r.b_off >= 0) {
+      LB.p = reinterpret_cast<const E *>(g.ops) + r.b_off;
+      LB.lo = g.ops_lo; LB.ld = r.bld;
+    } else {  // identity operator block
+      LB.p = g.ident; LB.lo = g.ident_lo; LB.ld = g.ident_ld;
+    }
+    LB.rows = r.brows;
     ls_mat<P>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
     ls_mat<P>(LS, 2, LB, it.c0, min(LB.rows, it.c0 + 32 * TN), lK);
   };
-  load_seg();
+  load_seg(cur);
   typedef Frags<P, KS, TM, TN> FR;
   ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR>(
       rg, [&](Stage<P, KS> &st) { ring_issue<P, KS>(st, LS, lj * BK, !ldone, g.zero); },
@@ -527,8 +497,12 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
         if (ldone) return 0;
         if (++lj * BK >= lK) {
           lj = 0;
-          if (++seg < it.te) load_seg();
-          else ldone = true;
+          if (++seg < it.te) {
+            load_seg(nxt);
+            if (seg + 1 < it.te) fetch(seg + 1, nxt);
+          } else {
+            ldone = true;
+          }
         }
         return 1;
       },
@@ -1050,6 +1024,7 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   g.a_items = p.pa.items; g.a_qbase = p.pa.qbase; g.a_tb = p.pa.tb; g.a_gch = p.pa.gch;
   g.a_ch = p.pa.ch; g.a_idx = p.pa.idx;
   g.recs = reinterpret_cast<const ChunkRec *>(recs);
+  g.segb = p.segb;
   return g;
 }
 

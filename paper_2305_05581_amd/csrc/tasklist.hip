@@ -447,6 +447,27 @@ __global__ void k_pan_toff(Plan p, int64_t n) {
   p.t_off[A.idx[i]] = A.tb[G] + (A.ch[i] - A.gch[G]) * PCH * ld8(N);
 }
 
+// Phase-B segment records, one per position of the forward schedule's task
+// list: T_k (class 0: output rows q, K = n; class 1: rows r, K = m) and the
+// second operator block (class 0: R_k, r rows; class 1: L_k, q rows).
+__global__ void k_segb(Plan p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = p.fwd.idx[i];
+  const tns_task k = p.tasks[t];
+  const int *so = p.psi_sec + 4 * k.out, *si = p.psi_sec + 4 * k.in;
+  const int q = p.dimL[so[0]], r = p.dimR[so[3]], m = p.dimL[si[0]], nn = p.dimR[si[3]];
+  SegRec s;
+  s.a_off = p.t_off[t];
+  s.K = k.order == 0 ? nn : m;
+  s.arows = k.order == 0 ? q : r;
+  s.brows = k.order == 0 ? r : q;
+  const int blk = k.order == 0 ? k.rblk : k.lblk;
+  s.b_off = blk >= 0 ? p.blk_off[blk] : -1;
+  s.bld = blk >= 0 ? p.blk_ld[blk] : 0;
+  p.segb[i] = s;
+}
+
 // Panel cost order (descending) and work queue: boustrophedon over the ranks.
 __global__ void k_pan_rank_keys(Plan p) {
   const int64_t G = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -821,6 +842,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.scan_tmp = cv.take<int64_t>(P->nS + 1);
   p.scalars = cv.take<int64_t>(8);
   p.t_off = cv.take<int64_t>(ntcap + 1);
+  p.segb = cv.take<SegRec>(ntcap);
   p.pp_off = cv.take<int64_t>(P->nS + 1);
   p.pt_off = cv.take<int64_t>(P->nS + 1);
   // forward schedule: 2 groups per sector, output tiles GM x GN
@@ -1039,6 +1061,8 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   // phase-A panels and the offsets of the forward intermediates
   s = build_panels(p, st);
   if (s != TNS_OK) return s;
+  if (p.ntasks > 0) hipLaunchKernelGGL(k_segb, dim3(nblk(p.ntasks, B)), dim3(B), 0, st, p, p.ntasks);
+  TNS_HIP(hipGetLastError());
 
   // backward grouping: stable sort of (key, task) entries by key
   const int64_t nent = 3 * p.ntasks;

@@ -141,6 +141,17 @@ struct Panels {
   int64_t *scalars;    // [8]
 };
 
+// One segment of a phase-B work item (a task of its chunk), in the order of
+// the forward schedule's task list: the intermediate T_k (element offset,
+// rows, inner dimension K = its columns, leading dimension ld8(K)) and the
+// operator block Y_k (element offset, or -1 for the identity; rows; leading
+// dimension).  Precision-independent; one scalar load per segment switch.
+struct SegRec {
+  int64_t a_off, b_off;
+  int32_t K, arows, brows, bld;
+};
+static_assert(sizeof(SegRec) == 32, "SegRec layout");
+
 // Host-side record of everything the compute calls need; lives in
 // tns_tasklist::opaque, all pointers are device pointers into the build
 // workspace.
@@ -169,6 +180,7 @@ struct Plan {
   // leading dimension K2 rounded up to 8, stacked per phase-A panel) and the
   // padded copies of psi
   int64_t *t_off;        // [ntcap] element offset of T_k
+  SegRec *segb;          // [ntcap] phase-B segments in the order of fwd.idx
   int64_t t_elems;
   int64_t *pp_off, *pt_off;  // [nS + 1] sector offsets: m x ld8(n) and n x ld8(m)
   int64_t pp_elems, pt_elems;
