@@ -172,11 +172,6 @@ tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, const void *op_
                           const void *psi, void *sigma, double beta, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
-/* Backward of tns_apply_heff for a loss with G = d loss / d sigma:
- * grad_psi   = sum_tasks alpha L^T G_out R            (psi layout; nullable)
- * grad_ops   = sum_tasks alpha G_out R A^T into L,    (operator-value layout,
- *              alpha G_out^T L A into R                 padding untouched; nullable)
- * Both outputs are overwritten (not accumulated).  FP32 and FP64 only. */
 /* Batched form of tns_apply_heff (level 3, Eq. (2), for many independent
  * problems): sigma_i := beta * sigma_i + H_eff,i psi_i for i < n, with one
  * persistent launch per GEMM phase for all instances together (work of the
@@ -219,6 +214,18 @@ tns_status tns_autotune_tiles_batch(tns_tasklist *const *tls, int n, tns_prec pr
                                     const void *const *op_vals, const void *const *psi, void *const *sigma,
                                     void *ws, size_t ws_bytes, uint32_t *tiles_out, hipStream_t stream);
 
+/* Backward of tns_apply_heff (the adjoint of each task's product L A R^T of
+ * Eq. (2); the paper itself only applies H_eff) for a loss with
+ * G = d loss / d sigma:
+ * grad_psi   = sum_tasks alpha L^T G_out R            (psi layout; nullable)
+ * grad_ops   = sum_tasks alpha G_out R A^T into L,    (operator-value layout,
+ *              alpha G_out^T L A into R                 padding untouched; nullable)
+ * A = psi_in, L and R the task's blocks (identity sides contribute no
+ * operator gradient).  Both outputs are overwritten (not accumulated); sums
+ * run in a fixed order, so results are bitwise reproducible.  FP32 and FP64
+ * only (TNS_ERR_ARG for TNS_BF16X3); TNS_ERR_WORKSPACE when ws_bytes is below
+ * tns_backward_workspace_bytes.  psi, grad_sigma, grad_psi: device, psi_dim
+ * elements of the precision's type; op_vals as for tns_apply_heff. */
 size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
 tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
                                    const void *psi, const void *grad_sigma, void *grad_psi,

@@ -165,7 +165,7 @@ template <int P, int KS> struct RingL {
   static constexpr int LOADS = CH / 4;                      // global_load_lds per wave and stage
   static constexpr int BK = P == TNS_BF16X3 ? 32 : KS * 4 * RingP<P>::VEC;
 };
-// The NS stages (4 or 5) are separate LDS arrays and every access names its
+// The NS stages (2 to 5) are separate LDS arrays and every access names its
 // stage at compile time (the stage loop is unrolled NS times): the compiler
 // then tells the direct loads into one stage from the operand reads of
 // another and does not drain the ring before each stage's reads.
@@ -175,14 +175,19 @@ template <int P, int KS> struct __attribute__((aligned(16))) Stage {
 struct __attribute__((aligned(16))) NoStage {
   uint8_t b[16];
 };
-template <int P, int KS, int NS> using Stage4 = typename std::conditional<NS == 5, Stage<P, KS>, NoStage>::type;
+// Stage J of a ring of NS stages (a 16-byte placeholder when J >= NS).
+template <int P, int KS, int NS, int J>
+using StageJ = typename std::conditional<(J < NS), Stage<P, KS>, NoStage>::type;
 template <int P, int KS, int NS> struct Ring {
-  static_assert(NS == 4 || NS == 5, "four or five stages");
-  Stage<P, KS> &s0, &s1, &s2, &s3;
-  Stage4<P, KS, NS> &s4;
+  static_assert(NS >= 2 && NS <= 5, "two to five stages");
+  Stage<P, KS> &s0, &s1;
+  StageJ<P, KS, NS, 2> &s2;
+  StageJ<P, KS, NS, 3> &s3;
+  StageJ<P, KS, NS, 4> &s4;
 };
 template <int J, int P, int KS, int NS>
 __device__ inline Stage<P, KS> &stage(Ring<P, KS, NS> &r) {
+  static_assert(J < NS, "stage of the ring");
   if constexpr (J == 0) return r.s0;
   else if constexpr (J == 1) return r.s1;
   else if constexpr (J == 2) return r.s2;
@@ -210,7 +215,7 @@ __device__ inline void gl_lds(const void *src, void *dst) {
 template <int P, int KS, int NS, bool LGKM>
 __device__ inline void ring_sync() {
   constexpr int E = (7 << 4) | ((LGKM ? 0 : 15) << 8), N = (NS - 2) * RingL<P, KS>::LOADS;  // expcnt: no wait
-  static_assert(N < 64, "vmcnt range");
+  static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt(E | (N & 15) | ((N >> 4) << 14));
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
@@ -721,8 +726,10 @@ __global__ void k_chunk_recs(FwdArgs g) {
 template <int P, int PH>
 __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
   constexpr int KS = Geo<P, PH>::KS, NS = Geo<P, PH>::NS;
-  __shared__ Stage<P, KS> st0, st1, st2, st3;
-  __shared__ Stage4<P, KS, NS> st4;
+  __shared__ Stage<P, KS> st0, st1;
+  __shared__ StageJ<P, KS, NS, 2> st2;
+  __shared__ StageJ<P, KS, NS, 3> st3;
+  __shared__ StageJ<P, KS, NS, 4> st4;
   Ring<P, KS, NS> rg{st0, st1, st2, st3, st4};
   int *s_work = reinterpret_cast<int *>(st0.b);  // the ring is idle between items
   for (;;) {
@@ -880,8 +887,10 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
 template <int P, int PH>
 __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b) {
   constexpr int KS = Geo<P, PH>::KS, NS = Geo<P, PH>::NS;
-  __shared__ Stage<P, KS> st0, st1, st2, st3;
-  __shared__ Stage4<P, KS, NS> st4;
+  __shared__ Stage<P, KS> st0, st1;
+  __shared__ StageJ<P, KS, NS, 2> st2;
+  __shared__ StageJ<P, KS, NS, 3> st3;
+  __shared__ StageJ<P, KS, NS, 4> st4;
   Ring<P, KS, NS> rg{st0, st1, st2, st3, st4};
   int *s_w = reinterpret_cast<int *>(st0.b);  // the ring is idle between items
   for (;;) {
