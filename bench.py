@@ -133,7 +133,9 @@ def phase_flops(P, tasks):
     return fa, fb
 def backward_flops(P, tasks):
     """Algorithmic flops of the backward product (d psi and the operator-block
-    gradients of every task): d psi = alpha L^T G R as (L^T G) R, d L = alpha
+    gradients of every task): d psi = alpha L^T G R in the cheaper order of
+    the transposed task, which costs what the task itself costs (the two
+    orders of L A R^T and of L^T G R are the same pair of costs); d L = alpha
     G R psi^T as (G R) psi^T, d R = alpha G^T L psi as (G^T L) psi; an
     identity side drops its product (and d of an identity is not formed)."""
     out, inn = tasks["out"], tasks["in"]
@@ -142,7 +144,7 @@ def backward_flops(P, tasks):
     m = P.dimL[P.psi_sec[inn, 0]].astype(np.int64)
     n = P.dimR[P.psi_sec[inn, 3]].astype(np.int64)
     iL, iR = tasks["lblk"] < 0, tasks["rblk"] < 0
-    dpsi = np.where(iL, 0, 2 * m * q * r) + np.where(iR, 0, 2 * m * r * n)
+    dpsi = tasks["cost"]
     dL = np.where(iL, 0, np.where(iR, 2 * q * r * m, 2 * q * r * n + 2 * q * n * m))
     dR = np.where(iR, 0, np.where(iL, 2 * r * q * n, 2 * r * q * m + 2 * r * m * n))
     return int(dpsi.sum()), int(dL.sum() + dR.sum())
@@ -289,12 +291,16 @@ def bench_grad(args):
 
     t_f = timed(lambda: H.apply(x, prec), args.steps)
     t_b = timed(lambda: H.backward(x, G, prec), args.steps)
+    t_bpsi = timed(lambda: H.backward(x, G, prec, want_ops=False), args.steps)
+    t_bops = timed(lambda: H.backward(x, G, prec, want_psi=False), args.steps)
     gp, go = H.backward(x, G, prec)
     gp64, go64 = H.backward(psi64, psi64, "f64")
     rel = lambda a, b: float(torch.linalg.norm(a.double() - b) / torch.linalg.norm(b))
     e_psi, e_ops = rel(gp, gp64), rel(go, go64)
     log("forward %.2f ms %.1f TFLOP/s; backward %.2f ms %.1f TFLOP/s; rel err vs FP64: d psi %.1e, d ops %.1e"
         % (t_f * 1e3, fwd / t_f / 1e12, t_b * 1e3, (f_dpsi + f_dops) / t_b / 1e12, e_psi, e_ops))
+    log("one output at a time: d psi %.2f ms %.1f TFLOP/s; operator gradients %.2f ms %.1f TFLOP/s"
+        % (t_bpsi * 1e3, f_dpsi / t_bpsi / 1e12, t_bops * 1e3, f_dops / t_bops / 1e12))
     bflops = f_dpsi + f_dops
     line = {
         "metric": "H_eff backward (d psi + d operator blocks) TFLOP/s", "value": round(bflops / t_b / 1e12, 3),
@@ -305,6 +311,8 @@ def bench_grad(args):
                                "seed 5" % P.nTerms, "tasks": H.ntasks, "backward_flops": bflops,
                    "forward_flops": fwd},
         "forward": {"ms_per_step": round(t_f * 1e3, 3), "tflops": round(fwd / t_f / 1e12, 3)},
+        "d_psi_only": {"ms_per_step": round(t_bpsi * 1e3, 3), "tflops": round(f_dpsi / t_bpsi / 1e12, 3)},
+        "d_ops_only": {"ms_per_step": round(t_bops * 1e3, 3), "tflops": round(f_dops / t_bops / 1e12, 3)},
         "pct_mfma_peak": round(100 * bflops / t_b / 1e12 / PEAK[prec], 2),
         "rel_err_vs_f64": {"d_psi": e_psi, "d_ops": e_ops},
     }

@@ -146,7 +146,10 @@ size_t tns_tasklist_workspace_bytes(const tns_problem *prob);
  * pair that yields a contribution, sorts them by output sector (term order
  * inside a sector), and builds the work schedules of the persistent kernels
  * (output row panels x task chunks, longest first) for the forward product
- * and for its backward.  Synchronises the stream twice to read counts.
+ * and for its backward, including the adjoint task list (every task with its
+ * sectors swapped and its blocks transposed, sorted by the new output sector)
+ * that the backward's d psi runs as a forward product.  Synchronises the
+ * stream four times to read counts.
  * `ws` must stay untouched while `out` is in use. */
 tns_status tns_build_tasklist(const tns_problem *prob, void *ws, size_t ws_bytes,
                               tns_tasklist *out, hipStream_t stream);
@@ -194,7 +197,8 @@ tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n, tns_prec 
  * 128 rows/columns) used along any output dimension d of bucket b =
  * [d <= 32, d <= 64, d <= 128, d > 128]; the last tile along a dimension
  * shrinks to the multiple of 32 that covers what remains.  Default
- * 0x80804020 (32, 64, 128, 128).  tns_set_tiles rebuilds the forward work items on the device and
+ * 0x80804020 (32, 64, 128, 128).  tns_set_tiles rebuilds the forward work items on the device (the
+ * backward's adjoint product keeps the default table) and
  * synchronises the stream (no product may be in flight on the task list);
  * workspaces and results do not depend on the table (the sums are taken in
  * the same order).  TNS_ERR_ARG for an invalid table. */
@@ -221,7 +225,10 @@ tns_status tns_autotune_tiles_batch(tns_tasklist *const *tls, int n, tns_prec pr
  * grad_ops   = sum_tasks alpha G_out R A^T into L,    (operator-value layout,
  *              alpha G_out^T L A into R                 padding untouched; nullable)
  * A = psi_in, L and R the task's blocks (identity sides contribute no
- * operator gradient).  Both outputs are overwritten (not accumulated); sums
+ * operator gradient).  grad_psi is the forward product (two grouped GEMM
+ * phases) of the adjoint task list on a copy of the blocks, transposed into
+ * the workspace on every call; the operator gradients run in a fused
+ * persistent kernel.  Both outputs are overwritten (not accumulated); sums
  * run in a fixed order, so results are bitwise reproducible.  FP32 and FP64
  * only (TNS_ERR_ARG for TNS_BF16X3); TNS_ERR_WORKSPACE when ws_bytes is below
  * tns_backward_workspace_bytes.  psi, grad_sigma, grad_psi: device, psi_dim

@@ -4,18 +4,21 @@
 // conversions and the C entry points of the product.  The forward product
 // itself lives in fwd.hip.
 //
-// The backward runs one persistent fused kernel.  Work item = (output
-// matrix, row panel of TQ rows, chunk of tasks); for every task of its chunk
-// the item computes a chained product on chip:
+// d psi = sum alpha L^T G R is the forward product of the adjoint task list
+// (fwd.hip's two grouped GEMM phases) on a transposed copy of the operator
+// blocks.  The operator-block gradients run in one persistent fused kernel.
+// Work item = (operator block, row panel of TQ rows, chunk of the tasks that
+// use the block); for every task of its chunk the item computes a chained
+// product on chip:
 //
 //   stage 1   V = X[p0:p0+TQ, :] * M[:, c0:c0+KC]      (K = K1, MFMA)
 //   stage 2   acc += alpha V * Y[:, c0:c0+KC]^T          (K = KC, MFMA)
 //
 // over column chunks c0 of M (the Mode list in tns_internal.hpp gives X, M, Y
-// of d psi = L^T G R, d L = G R A^T and d R = G^T L A).  The intermediate V
-// stays in LDS and the sum over the task chunk in the MFMA accumulators;
-// each item writes its panel into its own partial slot and an epilogue adds
-// the slots of every output in a fixed order.
+// of d L = G R A^T and d R = G^T L A).  The intermediate V stays in LDS and
+// the sum over the task chunk in the MFMA accumulators; each item writes its
+// panel into its own partial slot and an epilogue adds the slots of every
+// block in a fixed order.
 #include <algorithm>
 
 #include "kern.hpp"
@@ -122,28 +125,20 @@ __device__ inline TaskOps task_ops(const ApplyArgs &a, const tns_task &t, int mo
   R.off = R.ident ? 0 : a.blk_off[t.rblk]; R.si = R.ident ? 0 : a.blk_ld[t.rblk];
   A.rows = m; A.cols = n; A.off = a.psi_off[t.in]; A.si = n; A.sk = 1; A.ident = 0; A.src = 1;
   G.rows = q; G.cols = r; G.off = a.psi_off[t.out]; G.si = r; G.sk = 1; G.ident = 0; G.src = 2;
-  switch (mode) {
-    case M_FWD0: o.X = L; o.M = A; o.Y = R; o.K1 = m; o.K2 = n; break;
-    case M_FWD1: o.X = R; o.M = transposed(A); o.Y = L; o.K1 = n; o.K2 = m; break;
-    case M_DPSI: o.X = transposed(L); o.M = G; o.Y = transposed(R); o.K1 = q; o.K2 = r; break;
-    case M_DL: o.X = G; o.M = R; o.Y = A; o.K1 = r; o.K2 = n; break;
-    default: o.X = transposed(G); o.M = L; o.Y = transposed(A); o.K1 = q; o.K2 = m; break;
+  if (mode == M_DL) {
+    o.X = G; o.M = R; o.Y = A; o.K1 = r; o.K2 = n;
+  } else {  // M_DR
+    o.X = transposed(G); o.M = L; o.Y = transposed(A); o.K1 = q; o.K2 = m;
   }
   o.alpha = t.alpha;
   return o;
 }
 
-// Rows (panel dimension) and columns of the output matrix of an item.
+// Rows (panel dimension) and columns of the output matrix of an item: the
+// operator block whose gradient it computes.
 __device__ inline void out_dims(const ApplyArgs &a, const Item &it, int *rows, int *cols) {
-  if (it.mode <= M_DPSI) {
-    const int jL = a.psi_sec[4 * it.out], jR = a.psi_sec[4 * it.out + 3];
-    const int q = a.dimL[jL], r = a.dimR[jR];
-    *rows = it.mode == M_FWD1 ? r : q;
-    *cols = it.mode == M_FWD1 ? q : r;
-  } else {
-    *rows = a.blk_rows[it.out];
-    *cols = a.blk_cols[it.out];
-  }
+  *rows = a.blk_rows[it.out];
+  *cols = a.blk_cols[it.out];
 }
 
 // ---------------------------------------------------------------------------
@@ -437,9 +432,7 @@ __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
               const int row = rt * 16 + mrow(acc[rt][u], lg, v);
               const int col = ct0 + jt * 16 + l16;
               if (row < it.np && col < Ctot) {
-                const int64_t idx = it.mode == M_FWD1 ? ((int64_t)col * Rtot + p0 + row)
-                                                      : ((int64_t)(p0 + row) * Ctot + col);
-                slot[idx] = acc[rt][u][v];
+                slot[(int64_t)(p0 + row) * Ctot + col] = acc[rt][u][v];
               }
             }
           }
@@ -584,26 +577,84 @@ tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void 
   return fwd_apply(p, prec, ops, psi, sigma, beta, ws, ws_bytes, st, timed ? ev : nullptr);
 }
 
+// Operator values transposed block by block: block b (rows x cols, leading
+// dimension bld[b], at boff[b]) becomes a cols x ld8(rows) row-major matrix at
+// toff[b], its padding columns zero.  32 x 32 tiles through LDS, so that
+// both the reads and the writes are row-contiguous.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose_blocks(const T *__restrict__ src, const int64_t *__restrict__ boff,
+                                                          const int32_t *__restrict__ bld,
+                                                          const int32_t *__restrict__ rows,
+                                                          const int32_t *__restrict__ cols,
+                                                          const int64_t *__restrict__ toff, T *__restrict__ dst,
+                                                          int nblk) {
+  __shared__ T tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int R = rows[b], C = cols[b], ld = bld[b], tl = ld8(R);
+    const T *s = src + boff[b];
+    T *d = dst + toff[b];
+    for (int r0 = 0; r0 < tl; r0 += 32)
+      for (int c0 = 0; c0 < C; c0 += 32) {
+        for (int i = ty; i < 32; i += 8) {
+          const int r = r0 + i, c = c0 + tx;
+          tile[i][tx] = (r < R && c < C) ? s[(int64_t)r * ld + c] : T(0);
+        }
+        __syncthreads();
+        for (int i = ty; i < 32; i += 8) {
+          const int c = c0 + i, r = r0 + tx;
+          if (c < C && r < tl) d[(int64_t)c * tl + r] = tile[tx][i];
+        }
+        __syncthreads();
+      }
+  }
+}
+
+// Backward workspace: [k_apply: queue counter | partial slots of the
+// operator-gradient schedule] [transposed operator values] [workspace of the
+// adjoint forward product].
+static size_t bwd_transposed_at(const Plan &p, tns_prec prec) { return apply_ws(p.bwd, p.psi_dim, prec); }
+static size_t bwd_fwd_at(const Plan &p, tns_prec prec) {
+  return bwd_transposed_at(p, prec) +
+         align_up((size_t)std::max<int64_t>(p.adj.n_vals, 1) * elem_bytes(prec), 256);
+}
+static size_t bwd_workspace(const Plan &p, tns_prec prec) {
+  return bwd_fwd_at(p, prec) + fwd_workspace(adjoint_plan(p), prec);
+}
+
+// d psi = sum alpha L^T G R is the forward product of the adjoint task list on
+// the transposed blocks (two grouped GEMM phases); the operator gradients
+// run in the fused kernel k_apply.
 template <int P>
 static tns_status backward_impl(const Plan &p, const void *ops, const void *psi, const void *G, void *gpsi,
                                 void *gops, void *ws, hipStream_t st) {
   typedef typename Prec<P>::acc T;
   const Sched &S = p.bwd;
   char *w = reinterpret_cast<char *>(ws);
-  int32_t *queue = reinterpret_cast<int32_t *>(w);
-  T *part = reinterpret_cast<T *>(w + 256);
-  ApplyArgs a = make_args(p, S, ops, psi, G, part, queue);
-  a.mode_mask = (gpsi ? (1 << M_DPSI) : 0) | (gops ? ((1 << M_DL) | (1 << M_DR)) : 0);
-  hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(32), 0, st, queue);
-  if (S.nitems > 0) hipLaunchKernelGGL(k_apply<P>, dim3(grid_for(k_apply<P>, p.n_cu)), dim3(NWG), 0, st, a);
-  if (gpsi)
-    hipLaunchKernelGGL(k_epilogue_psi<T>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 1,
-                       S.grp_chunk_base, S.slot_off, (const T *)part, (T *)gpsi, p.psi_dim, 0);
   if (gops) {
+    int32_t *queue = reinterpret_cast<int32_t *>(w);
+    T *part = reinterpret_cast<T *>(w + 256);
+    ApplyArgs a = make_args(p, S, ops, psi, G, part, queue);
+    a.mode_mask = (1 << M_DL) | (1 << M_DR);
+    hipLaunchKernelGGL(k_reset_head, dim3(1), dim3(32), 0, st, queue);
+    if (S.nitems > 0) hipLaunchKernelGGL(k_apply<P>, dim3(grid_for(k_apply<P>, p.n_cu)), dim3(NWG), 0, st, a);
     hipLaunchKernelGGL(k_zero<T>, dim3(nb(p.n_vals, 256)), dim3(256), 0, st, (T *)gops, p.n_vals);
     if (p.nBlk > 0)
       hipLaunchKernelGGL(k_epilogue_blk<T>, dim3(p.nBlk), dim3(256), 0, st, p.nS, S.grp_chunk_base, S.slot_off,
                          p.blk_off, p.blk_rows, p.blk_cols, p.blk_ld, (const T *)part, (T *)gops);
+    TNS_HIP(hipGetLastError());
+  }
+  if (gpsi) {
+    const tns_prec prec = (tns_prec)P;
+    const Plan q = adjoint_plan(p);
+    T *opsT = reinterpret_cast<T *>(w + bwd_transposed_at(p, prec));
+    if (p.nBlk > 0)
+      hipLaunchKernelGGL(k_transpose_blocks<T>, dim3(std::min(p.nBlk, 1 << 16)), dim3(256), 0, st,
+                         (const T *)ops, p.blk_off, p.blk_ld, p.blk_rows, p.blk_cols, q.blk_off, opsT, p.nBlk);
+    TNS_HIP(hipGetLastError());
+    char *wf = w + bwd_fwd_at(p, prec);
+    const tns_status s = fwd_apply(q, prec, opsT, G, gpsi, 0.0, wf, fwd_workspace(q, prec), st, nullptr);
+    if (s != TNS_OK) return s;
   }
   return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
 }
@@ -649,8 +700,7 @@ extern "C" void tns_profile_events(hipEvent_t before, hipEvent_t mid, hipEvent_t
 
 extern "C" size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec) {
   if (!tl || (prec != TNS_F64 && prec != TNS_F32)) return 0;
-  const Plan &p = plan_of(tl);
-  return apply_ws(p.bwd, p.psi_dim, prec);
+  return bwd_workspace(plan_of(tl), prec);
 }
 
 extern "C" tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
@@ -659,7 +709,7 @@ extern "C" tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec p
   if (!tl || !op_vals || !psi || !grad_sigma || !ws) return TNS_ERR_ARG;
   if (prec != TNS_F64 && prec != TNS_F32) return TNS_ERR_ARG;
   const Plan &p = plan_of(tl);
-  if (ws_bytes < apply_ws(p.bwd, p.psi_dim, prec)) return TNS_ERR_WORKSPACE;
+  if (ws_bytes < bwd_workspace(p, prec)) return TNS_ERR_WORKSPACE;
   if (!grad_psi && !grad_ops) return TNS_OK;
   if (prec == TNS_F64) return backward_impl<TNS_F64>(p, op_vals, psi, grad_sigma, grad_psi, grad_ops, ws, st);
   return backward_impl<TNS_F32>(p, op_vals, psi, grad_sigma, grad_psi, grad_ops, ws, st);

@@ -201,9 +201,9 @@ __device__ inline int64_t mode_cost(const Plan &p, const tns_task &t, int mode) 
   if (mode <= M_FWD1) return t.cost;
   const int64_t q = p.dimL[p.psi_sec[4 * t.out]], r = p.dimR[p.psi_sec[4 * t.out + 3]];
   const int64_t m = p.dimL[p.psi_sec[4 * t.in]], n = p.dimR[p.psi_sec[4 * t.in + 3]];
-  if (mode == M_DPSI) return 2 * m * q * r + 2 * m * r * n;
   if (mode == M_DL) return 2 * q * r * n + 2 * q * n * m;
-  return 2 * r * q * m + 2 * r * m * n;
+  if (mode == M_DR) return 2 * r * q * m + 2 * r * m * n;
+  return 0;  // d psi groups carry no tasks
 }
 
 // Summed cost per group (one wave per group) and the schedule total.
@@ -619,6 +619,9 @@ __global__ void k_bwd_groups(Plan p, Sched S) {
   S.grp_begin[g] = (int32_t)S.grp_chunk_base[g];  // scan of counts (reused buffer)
   S.grp_n[g] = (int32_t)(S.grp_chunk_base[g + 1] - S.grp_chunk_base[g]);
   if (g < p.nS) {
+    // the tasks of input sector g: the adjoint task list's CSR; d psi runs as
+    // the forward product of that list, so the group gets no work here
+    S.grp_n[g] = 0;
     S.grp_rows[g] = p.dimL[p.psi_sec[4 * g]];
     S.grp_cols[g] = p.dimR[p.psi_sec[4 * g + 3]];
     S.grp_out[g] = g;
@@ -630,6 +633,36 @@ __global__ void k_bwd_groups(Plan p, Sched S) {
     S.grp_out[g] = b;
     S.grp_mode[g] = p.op_side[p.blk_op[b]] ? M_DR : M_DL;
   }
+}
+
+// Adjoint task j: the task at position j of the backward grouping (sorted by
+// input sector, forward order inside a sector) with its sectors swapped.
+// The evaluation order is chosen for the swapped shapes by the rule of the
+// forward list (order 1 only if strictly cheaper); identity sides keep their
+// cost (their sectors have equal dimensions).
+__global__ void k_adj_tasks(Plan p, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const tns_task f = p.tasks[p.bwd.idx[j]];
+  tns_task t = f;
+  t.out = f.in;
+  t.in = f.out;
+  const int64_t q = p.dimL[p.psi_sec[4 * t.out]], r = p.dimR[p.psi_sec[4 * t.out + 3]];
+  const int64_t m = p.dimL[p.psi_sec[4 * t.in]], nn = p.dimR[p.psi_sec[4 * t.in + 3]];
+  t.order = 0;
+  if (t.lblk >= 0 && t.rblk >= 0) {
+    const int64_t c0 = 2 * q * nn * (m + r), c1 = 2 * m * r * (nn + q);
+    t.order = c1 < c0 ? 1 : 0;
+    t.cost = c1 < c0 ? c1 : c0;
+  }
+  p.adj.tasks[j] = t;
+}
+
+// CSR of the adjoint list: the backward grouping's begin of input sector s.
+__global__ void k_adj_ptr(Plan p, int64_t ntasks) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > p.nS) return;
+  p.adj.out_ptr[s] = s < p.nS ? p.bwd.grp_begin[s] : (int32_t)ntasks;
 }
 
 __global__ void k_copy_i32(const int32_t *a, int32_t *b, int64_t n) {
@@ -858,6 +891,19 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
   layout_sched(cv, p.bwd, bgroups, bent, bchunks, maxdim, TQ, 0, 0u, n_xcd, false);
   layout_panels(cv, p.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
+  // adjoint task list (d psi of the backward) and its forward schedule
+  Adjoint &J = p.adj;
+  J.tasks = cv.take<tns_task>(ntcap);
+  J.out_ptr = cv.take<int32_t>(P->nS + 1);
+  J.scalars = cv.take<int64_t>(8);
+  J.blk_off = cv.take<int64_t>(nb);
+  J.blk_ld = cv.take<int32_t>(nb);
+  J.t_off = cv.take<int64_t>(ntcap + 1);
+  J.segb = cv.take<SegRec>(ntcap);
+  J.n_vals = 0;
+  for (int b = 0; b < P->nBlk; ++b) J.n_vals += (int64_t)P->blk_cols[b] * ld8(P->blk_rows[b]);
+  layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, maxdim, GM, GN, TILES_DEFAULT, n_xcd, true);
+  layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
   if (pl) *pl = p;
   return cv.off + 256;
 }
@@ -974,6 +1020,69 @@ static void read_sched(Sched &S, const int64_t *h) {
   S.nchunks = h[1];
   S.nitems = h[2];
   S.partial_elems = h[3];
+}
+
+Plan adjoint_plan(const Plan &p) {
+  const Adjoint &J = p.adj;
+  Plan q = p;
+  q.tasks = J.tasks;
+  q.out_ptr = J.out_ptr;
+  q.scalars = J.scalars;
+  q.blk_off = J.blk_off;
+  q.blk_ld = J.blk_ld;
+  q.blk_rows = p.blk_cols;
+  q.blk_cols = p.blk_rows;
+  q.blk_in = p.blk_out;
+  q.blk_out = p.blk_in;
+  q.t_off = J.t_off;
+  q.segb = J.segb;
+  q.n_vals = J.n_vals;
+  q.t_elems = J.t_elems;
+  q.fwd = J.fwd;
+  q.pa = J.pa;
+  q.tiles = J.fwd.tiles;
+  return q;
+}
+
+// The adjoint task list and its forward schedule (after the backward grouping,
+// whose order by input sector it takes).  boff / bld: the transposed block
+// table (host memory that stays valid until the stream has synchronised).
+static tns_status build_adjoint(Plan &p, const int64_t *boff, const int32_t *bld, hipStream_t st) {
+  const int B = 256;
+  Adjoint &J = p.adj;
+  TNS_HIP(up(J.blk_off, boff, p.nBlk, st));
+  TNS_HIP(up(J.blk_ld, bld, p.nBlk, st));
+  if (p.ntasks > 0) hipLaunchKernelGGL(k_adj_tasks, dim3(nblk(p.ntasks, B)), dim3(B), 0, st, p, p.ntasks);
+  hipLaunchKernelGGL(k_adj_ptr, dim3(nblk(p.nS + 1, B)), dim3(B), 0, st, p, p.ntasks);
+  TNS_HIP(hipGetLastError());
+  Plan q = adjoint_plan(p);
+  if (p.nS > 0)
+    hipLaunchKernelGGL(k_fwd_groups, dim3(nblk(p.nS, 4)), dim3(256), 0, st, q, q.fwd);
+  TNS_HIP(hipGetLastError());
+  tns_status s = finish_sched(q, q.fwd, st);
+  if (s != TNS_OK) return s;
+  int64_t h[8];
+  TNS_HIP(hipMemcpyAsync(h, q.fwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipStreamSynchronize(st));
+  read_sched(q.fwd, h);
+  if (q.fwd.nchunks > q.fwd.chunks_cap || q.fwd.nitems > q.fwd.items_cap) return TNS_ERR_WORKSPACE;
+  s = build_panels(q, st);
+  if (s != TNS_OK) return s;
+  if (q.ntasks > 0) hipLaunchKernelGGL(k_segb, dim3(nblk(q.ntasks, B)), dim3(B), 0, st, q, q.ntasks);
+  TNS_HIP(hipGetLastError());
+  int64_t ext[3];
+  TNS_HIP(hipMemcpyAsync(ext, q.pa.tb + q.pa.ngroups, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 1, q.pa.ch + q.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 2, q.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipStreamSynchronize(st));
+  q.pa.t_elems = ext[0];
+  q.pa.nchunks = ext[1];
+  q.pa.nitems = ext[2];
+  if (q.pa.nitems > q.pa.items_cap) return TNS_ERR_WORKSPACE;
+  J.fwd = q.fwd;
+  J.pa = q.pa;
+  J.t_elems = ext[0];
+  return TNS_OK;
 }
 
 }  // namespace tns
@@ -1097,6 +1206,17 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   p.pa.nitems = ext[4];
   if (p.bwd.nchunks > p.bwd.chunks_cap || p.bwd.nitems > p.bwd.items_cap) return TNS_ERR_WORKSPACE;
   if (p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
+
+  // adjoint task list and schedule (d psi of the backward)
+  std::vector<int64_t> toff(std::max(1, P->nBlk));
+  std::vector<int32_t> tld(std::max(1, P->nBlk));
+  for (int64_t b = 0, o = 0; b < P->nBlk; ++b) {
+    tld[b] = ld8(P->blk_rows[b]);
+    toff[b] = o;
+    o += (int64_t)P->blk_cols[b] * tld[b];
+  }
+  s = build_adjoint(p, toff.data(), tld.data(), st);
+  if (s != TNS_OK) return s;
 
   memset(out, 0, sizeof(*out));
   out->ntasks = p.ntasks;

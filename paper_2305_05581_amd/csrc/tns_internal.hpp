@@ -19,15 +19,19 @@ constexpr int ITEMS_PER_CU = 8;
 // workgroups are dispatched to the dies round-robin.
 constexpr int NQ_MAX = 8;
 
-// Evaluation modes of the fused chained product
+// Evaluation modes of a task's chained product
 //   out(i, j) += alpha * sum_c (sum_k X(i, k) M(k, c)) Y(j, c)
 // (q, m: output / input left dims; r, n: output / input right dims; A = psi
 // input sector, G = grad of sigma output sector):
 //   0  (L A) R^T        X = L,   M = A,   Y = R      out = sigma rows   (q x r)
 //   1  L (A R^T)        X = R,   M = A^T, Y = L      out = sigma^T rows (r x q)
-//   2  d psi = L^T G R  X = L^T, M = G,   Y = R^T    out = (m x n)
+//   2  d psi = L^T G R  (labels the backward's per-sector groups, which stay
+//                        empty: d psi runs as the forward product of the
+//                        adjoint task list)
 //   3  d L = G R A^T    X = G,   M = R,   Y = A      out = (q x m)
 //   4  d R = G^T L A    X = G^T, M = L,   Y = A^T    out = (r x n)
+// Modes 0 and 1 are the two classes of the forward's GEMM phases; modes 3
+// and 4 run in the backward's fused kernel.
 enum Mode { M_FWD0 = 0, M_FWD1 = 1, M_DPSI = 2, M_DL = 3, M_DR = 4 };
 
 // One work item of a persistent kernel: the tile rows [p0, p0+np) x columns
@@ -152,6 +156,27 @@ struct SegRec {
 };
 static_assert(sizeof(SegRec) == 32, "SegRec layout");
 
+// The adjoint task list and its forward schedule.  Each task of the forward
+// list, transposed (output and input sectors swapped, L and R read as L^T and
+// R^T, the same alpha, the evaluation order chosen again for the swapped
+// shapes), sorted by its new output sector; the backward evaluates
+// d psi = sum alpha L^T G R as the forward product of this list.  Blocks are
+// read from a transposed copy of the operator values: block b as a
+// cols x ld8(rows) row-major matrix at blk_off[b].
+struct Adjoint {
+  tns_task *tasks;    // [ntcap]
+  int32_t *out_ptr;   // [nS + 1] CSR over the new output sectors
+  int64_t *scalars;   // [8]
+  int64_t *blk_off;   // [nBlk] element offset of transposed block b
+  int32_t *blk_ld;    // [nBlk] ld8(rows of block b)
+  int64_t *t_off;     // [ntcap + 1] offsets of the intermediates T_k
+  SegRec *segb;       // [ntcap] phase-B segment records
+  int64_t n_vals;     // elements of the transposed operator copy
+  int64_t t_elems;
+  Sched fwd;
+  Panels pa;
+};
+
 // Host-side record of everything the compute calls need; lives in
 // tns_tasklist::opaque, all pointers are device pointers into the build
 // workspace.
@@ -190,6 +215,7 @@ struct Plan {
   size_t bsort_tmp_bytes;
   Sched fwd, bwd;
   Panels pa;
+  Adjoint adj;
 };
 static_assert(sizeof(Plan) <= sizeof(((tns_tasklist *)0)->opaque), "Plan too large");
 
@@ -257,6 +283,10 @@ __host__ __device__ inline void mono_shift(int m, int *dN, int *d2Sz) {
   *dN = du + dd;
   *d2Sz = du - dd;
 }
+
+// Plan of the adjoint product (the tables of p with the adjoint task list,
+// block table and schedules of p.adj in place of the forward ones).
+Plan adjoint_plan(const Plan &p);
 
 // Launch helpers implemented in tasklist.hip / apply.hip / fwd.hip
 tns_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t st);
