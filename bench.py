@@ -31,8 +31,10 @@ PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0}  # TFLOP/s per algori
 PREC_ID = {"f64": 0, "f32": 1, "bf16x3": 2}
 # the two MFMA kernels of a product: phase A (T_k = alpha X_k M_k), phase B (sum_k T_k Y_k^T)
 KERNEL = {p: ("k_fwd<%d, 0>" % i, "k_fwd<%d, 1>" % i) for p, i in PREC_ID.items()}
+# sources that decide the forward kernels' memory traffic: the kernels and the
+# schedule that orders their work items
 KERNEL_SOURCES = ["paper_2305_05581_amd/csrc/fwd.hip", "paper_2305_05581_amd/csrc/kern.hpp",
-                  "paper_2305_05581_amd/csrc/tns_internal.hpp"]
+                  "paper_2305_05581_amd/csrc/tns_internal.hpp", "paper_2305_05581_amd/csrc/tasklist.hip"]
 TRAFFIC_FILE = os.path.join("profiles", "traffic.json")
 
 
