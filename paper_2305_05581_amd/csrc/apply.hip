@@ -28,7 +28,7 @@ namespace tns {
 
 constexpr int KK = 32;    // K1 step of stage 1
 constexpr int KC = 32;    // column chunk of M (K of stage 2)
-constexpr int CMAX = 512; // output columns held in accumulators per pass
+constexpr int CMAX = 256; // output columns held in accumulators per pass
 constexpr int YG = 128;   // columns of Y staged in LDS at a time
 constexpr int NWG = 256;  // threads per workgroup (4 waves)
 
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
   constexpr int NU = CMAX / 64;
   constexpr int NX = TQ * KK_ / NWG;
   constexpr int TM = KK_ / 4, TY = KS_ / 4;  // MFMA k-steps per stage-1 step / stage-2 slice
-  static_assert(TQ == 32 && KC_ == 64, "stage 1 maps V column tile w to wave w");
+  static_assert(TQ % 16 == 0 && TQ <= 128 && KC_ == 64, "stage 1 maps V column tile w to wave w");
   __shared__ T xs[TQ * SX];
   __shared__ T vs[TQ * SV];
   __shared__ int s_item;

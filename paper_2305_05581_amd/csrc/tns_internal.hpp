@@ -8,9 +8,10 @@
 
 namespace tns {
 
-// Row-panel height of one work item; every item owns TQ rows (or fewer) of
-// an output sector and all of its columns.
-constexpr int TQ = 32;
+// Row-panel height of one work item of the backward's fused kernel: every
+// item owns TQ rows (or fewer) of an operator block's gradient and all of its
+// columns.
+constexpr int TQ = 64;
 // Work items per compute unit the schedule aims at (load balance of the
 // longest-first queue).
 constexpr int ITEMS_PER_CU = 8;
