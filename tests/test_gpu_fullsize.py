@@ -56,3 +56,52 @@ def test_cfg3_sampled_parity():
         err = np.sqrt(num / den)
         say("  %s sampled rel err %.3e" % (prec, err))
         assert err <= tol
+
+
+def _block_view(P, vals, b):
+    o, r, c, ld = int(P.blk_off[b]), int(P.blk_rows[b]), int(P.blk_cols[b]), int(P.blk_ld[b])
+    return vals[o:o + r * ld].reshape(r, ld)[:, :c]
+
+
+@pytest.mark.timeout(600)
+def test_grad1024_sampled_backward():
+    """Backward at the size of bench.py's grad1024 (L=30, D=1024, 900 terms,
+    seed 5) in FP64 and FP32: d psi of sampled input sectors (the oracle runs
+    every task with that input sector) and the gradients of sampled operator
+    blocks (every task that uses the block)."""
+    from paper_2305_05581_amd.tns import HeffProblem
+    from oracle import grad as ograd
+    import bench
+    cfg = bench.CONFIGS["d1024"]
+    say("generating the D=1024 instance")
+    P = synthetic_problem(cfg["L"], cfg["N"], cfg["twoSz"], cfg["D"], cfg["mean"], cfg["dmax"], cfg["K"],
+                          seed=5, threads=min(16, os.cpu_count() or 1))
+    H = HeffProblem(P)
+    tasks, _ = H.tasks()
+    say("tasks", H.ntasks)
+    rng = np.random.default_rng(7)
+    cost_in = np.bincount(tasks["in"], weights=tasks["cost"].astype(np.float64), minlength=P.nS)
+    pick_s = {int(np.argmax(cost_in))} | set(int(s) for s in rng.choice(np.nonzero(cost_in > 0)[0], 3, replace=False))
+    pick_b = set()
+    for side in ("lblk", "rblk"):
+        used = tasks[side][tasks[side] >= 0]
+        counts = np.bincount(used)
+        pick_b |= {int(np.argmax(counts))} | set(int(b) for b in rng.choice(np.unique(used), 2, replace=False))
+    sel = np.isin(tasks["in"], list(pick_s)) | np.isin(tasks["lblk"], list(pick_b)) | np.isin(tasks["rblk"], list(pick_b))
+    sub = [tuple(t) for t in tasks[sel].tolist()]
+    say("sampled sectors", sorted(pick_s), "blocks", sorted(pick_b), "oracle tasks", len(sub))
+    psi, G = gaussian_psi(P, 5), gaussian_psi(P, 6)
+    ref_dpsi, ref_dvals, _ = ograd.backward(P, psi, G, sub)
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        x, g = to_dev(psi, dt), to_dev(G, dt)
+        gp, go = H.backward(x, g, prec)
+        gp, go = gp.double().cpu().numpy(), go.double().cpu().numpy()
+        a = np.concatenate([gp[P.psi_off[s]:P.psi_off[s + 1]] for s in sorted(pick_s)])
+        b = np.concatenate([ref_dpsi[P.psi_off[s]:P.psi_off[s + 1]] for s in sorted(pick_s)])
+        e1 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        a = np.concatenate([_block_view(P, go, k).reshape(-1) for k in sorted(pick_b)])
+        b = np.concatenate([_block_view(P, ref_dvals, k).reshape(-1) for k in sorted(pick_b)])
+        e2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        say("  %s sampled rel err d psi %.3e, d blocks %.3e" % (prec, e1, e2))
+        assert e1 <= tol and e2 <= tol
