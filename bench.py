@@ -349,7 +349,7 @@ def main():
         ingest_counters(args)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU's share only: this build runs on a single GPU "
+        print("bench.py measures one GPU's share only: the library runs the product on a single GPU "
               "(no collectives or sharding); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.config == "batch64":
