@@ -84,9 +84,9 @@ typedef struct {
   int32_t target_N, target_2Sz;
   int64_t n_vals;            /* length (elements) of the operator value array       */
   const int32_t *qL;         /* [nL][2] (N, 2Sz)                                     */
-  const int32_t *dimL;       /* [nL]                                                 */
+  const int32_t *dimL;       /* [nL] 1..32768                                         */
   const int32_t *qR;         /* [nR][2]                                              */
-  const int32_t *dimR;       /* [nR]                                                 */
+  const int32_t *dimR;       /* [nR] 1..32768                                         */
   const int32_t *psi_sec;    /* [nS][4] (iL, sa, sb, iR), ascending (iL, sa, sb)     */
   const int64_t *psi_off;    /* [nS+1]                                               */
   const int32_t *op_side;    /* [nOps] 0 = left block, 1 = right block               */
@@ -223,7 +223,8 @@ tns_status tns_autotune_tiles_batch(tns_tasklist *const *tls, int n, tns_prec pr
  * G = d loss / d sigma:
  * grad_psi   = sum_tasks alpha L^T G_out R            (psi layout; nullable)
  * grad_ops   = sum_tasks alpha G_out R A^T into L,    (operator-value layout,
- *              alpha G_out^T L A into R                 padding untouched; nullable)
+ *              alpha G_out^T L A into R                 padding, gaps and blocks no
+ *                                                       task uses are zero; nullable)
  * A = psi_in, L and R the task's blocks (identity sides contribute no
  * operator gradient).  grad_psi is the forward product (two grouped GEMM
  * phases) of the adjoint task list on a copy of the blocks, transposed into

@@ -477,11 +477,13 @@ __global__ void k_epilogue_blk(int nS, const int64_t *__restrict__ grp_chunk_bas
   const int64_t c0 = grp_chunk_base[nS + b], c1 = grp_chunk_base[nS + b + 1];
   if (c0 == c1) return;  // unused block: stays zero
   const int rows = blk_rows[b], cols = blk_cols[b], ld = blk_ld[b];
-  const int64_t n = (int64_t)rows * cols;
-  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+  const int n = rows * cols;  // a block holds fewer than 2^31 elements
+  T *o = out + blk_off[b];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
     double acc = 0.0;
     for (int64_t c = c0; c < c1; ++c) acc += (double)part[slot_off[c] + e];
-    out[blk_off[b] + (e / cols) * ld + (e % cols)] = (T)acc;
+    const int r = e / cols;
+    o[(int64_t)r * ld + (e - r * cols)] = (T)acc;
   }
 }
 
@@ -580,7 +582,8 @@ tns_status apply_impl(const Plan &p, tns_prec prec, const void *ops, const void 
 // Operator values transposed block by block: block b (rows x cols, leading
 // dimension bld[b], at boff[b]) becomes a cols x ld8(rows) row-major matrix at
 // toff[b], its padding columns zero.  32 x 32 tiles through LDS, so that
-// both the reads and the writes are row-contiguous.
+// both the reads and the writes are row-contiguous; the gridDim.y workgroups
+// of a block take every gridDim.y-th row of tiles.
 template <class T>
 __global__ __launch_bounds__(256) void k_transpose_blocks(const T *__restrict__ src, const int64_t *__restrict__ boff,
                                                           const int32_t *__restrict__ bld,
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(256) void k_transpose_blocks(const T *__restrict__ 
     const int R = rows[b], C = cols[b], ld = bld[b], tl = ld8(R);
     const T *s = src + boff[b];
     T *d = dst + toff[b];
-    for (int r0 = 0; r0 < tl; r0 += 32)
+    for (int r0 = 32 * blockIdx.y; r0 < tl; r0 += 32 * gridDim.y)
       for (int c0 = 0; c0 < C; c0 += 32) {
         for (int i = ty; i < 32; i += 8) {
           const int r = r0 + i, c = c0 + tx;
@@ -649,7 +652,7 @@ static tns_status backward_impl(const Plan &p, const void *ops, const void *psi,
     const Plan q = adjoint_plan(p);
     T *opsT = reinterpret_cast<T *>(w + bwd_transposed_at(p, prec));
     if (p.nBlk > 0)
-      hipLaunchKernelGGL(k_transpose_blocks<T>, dim3(std::min(p.nBlk, 1 << 16)), dim3(256), 0, st,
+      hipLaunchKernelGGL(k_transpose_blocks<T>, dim3(std::min(p.nBlk, 1 << 16), 8), dim3(256), 0, st,
                          (const T *)ops, p.blk_off, p.blk_ld, p.blk_rows, p.blk_cols, q.blk_off, opsT, p.nBlk);
     TNS_HIP(hipGetLastError());
     char *wf = w + bwd_fwd_at(p, prec);

@@ -696,8 +696,16 @@ static tns_status validate(const tns_problem *P, int32_t *nmax_out, int32_t *max
   if (P->nTerms > 0 && (!P->term_L || !P->term_ma || !P->term_mb || !P->term_R || !P->term_coef))
     return TNS_ERR_ARG;
   int32_t maxdim = 1;
-  for (int i = 0; i < P->nL; ++i) { if (P->dimL[i] <= 0) return TNS_ERR_SHAPE; maxdim = std::max(maxdim, P->dimL[i]); }
-  for (int i = 0; i < P->nR; ++i) { if (P->dimR[i] <= 0) return TNS_ERR_SHAPE; maxdim = std::max(maxdim, P->dimR[i]); }
+  // sector dimensions 1..MAX_DIM: every block and sector matrix then holds
+  // fewer than 2^31 elements (32-bit element indices inside one matrix)
+  for (int i = 0; i < P->nL; ++i) {
+    if (P->dimL[i] <= 0 || P->dimL[i] > MAX_DIM) return TNS_ERR_SHAPE;
+    maxdim = std::max(maxdim, P->dimL[i]);
+  }
+  for (int i = 0; i < P->nR; ++i) {
+    if (P->dimR[i] <= 0 || P->dimR[i] > MAX_DIM) return TNS_ERR_SHAPE;
+    maxdim = std::max(maxdim, P->dimR[i]);
+  }
   for (int i = 1; i < P->nL; ++i)
     if (P->qL[2 * i] < P->qL[2 * i - 2] || (P->qL[2 * i] == P->qL[2 * i - 2] && P->qL[2 * i + 1] <= P->qL[2 * i - 1]))
       return TNS_ERR_QN;

@@ -12,6 +12,8 @@ namespace tns {
 // item owns TQ rows (or fewer) of an operator block's gradient and all of its
 // columns.
 constexpr int TQ = 64;
+// Largest sector dimension the library accepts (tns.h).
+constexpr int MAX_DIM = 32768;
 // Work items per compute unit the schedule aims at (load balance of the
 // longest-first queue).
 constexpr int ITEMS_PER_CU = 8;

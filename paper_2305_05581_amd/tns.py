@@ -150,16 +150,40 @@ def prec_id(prec):
     return _PREC_OF[prec] if isinstance(prec, str) else int(prec)
 
 
+_TABLES = (("qL", np.int32), ("dimL", np.int32), ("qR", np.int32), ("dimR", np.int32),
+           ("psi_sec", np.int32), ("psi_off", np.int64), ("op_side", np.int32), ("op_dN", np.int32),
+           ("op_d2Sz", np.int32), ("blk_op", np.int32), ("blk_in", np.int32), ("blk_out", np.int32),
+           ("blk_rows", np.int32), ("blk_cols", np.int32), ("blk_ld", np.int32), ("blk_off", np.int64),
+           ("term_L", np.int32), ("term_ma", np.int32), ("term_mb", np.int32), ("term_R", np.int32),
+           ("term_coef", np.float64))
+
+
+def problem_struct(P, n_vals=None):
+    """``(tns_problem, host arrays)`` of a problem; the arrays back the
+    struct's pointers and must outlive its use."""
+    host = {}
+    cp = TnsProblem()
+    cp.nL, cp.nR, cp.nS = P.nL, P.nR, P.nS
+    cp.nOps, cp.nBlk, cp.nTerms = P.nOps, P.nBlk, P.nTerms
+    cp.target_N, cp.target_2Sz = int(P.target[0]), int(P.target[1])
+    cp.n_vals = len(P.op_vals) if n_vals is None else int(n_vals)
+    for name, dt in _TABLES:
+        a = np.ascontiguousarray(getattr(P, name), dtype=dt)
+        host[name] = a
+        setattr(cp, name, a.ctypes.data_as(ctypes.c_void_p) if a.size else None)
+    return cp, host
+
+
+def tasklist_workspace_bytes(P):
+    """Build-workspace bytes of a problem, 0 when it fails the library's host
+    validation (no device call beyond a query of the device's unit counts)."""
+    cp, host = problem_struct(P)
+    return int(library().tns_tasklist_workspace_bytes(ctypes.byref(cp)))
+
+
 class HeffProblem:
     """A two-site problem resident on the GPU: task table and schedule built by
     the library, FP64 operator values in HBM, operand copies per precision."""
-
-    _TABLES = (("qL", np.int32), ("dimL", np.int32), ("qR", np.int32), ("dimR", np.int32),
-               ("psi_sec", np.int32), ("psi_off", np.int64), ("op_side", np.int32), ("op_dN", np.int32),
-               ("op_d2Sz", np.int32), ("blk_op", np.int32), ("blk_in", np.int32), ("blk_out", np.int32),
-               ("blk_rows", np.int32), ("blk_cols", np.int32), ("blk_ld", np.int32), ("blk_off", np.int64),
-               ("term_L", np.int32), ("term_ma", np.int32), ("term_mb", np.int32), ("term_R", np.int32),
-               ("term_coef", np.float64))
 
     def __init__(self, P, device="cuda", vals64=None):
         self.P = P
@@ -168,17 +192,7 @@ class HeffProblem:
             dev = torch.device(dev.type, torch.cuda.current_device())
         self.device = dev
         L = library()
-        self._host = {}
-        cp = TnsProblem()
-        cp.nL, cp.nR, cp.nS = P.nL, P.nR, P.nS
-        cp.nOps, cp.nBlk, cp.nTerms = P.nOps, P.nBlk, P.nTerms
-        cp.target_N, cp.target_2Sz = int(P.target[0]), int(P.target[1])
-        n_vals = int(vals64.numel()) if vals64 is not None else len(P.op_vals)
-        cp.n_vals = n_vals
-        for name, dt in self._TABLES:
-            a = np.ascontiguousarray(getattr(P, name), dtype=dt)
-            self._host[name] = a
-            setattr(cp, name, a.ctypes.data_as(ctypes.c_void_p) if a.size else None)
+        cp, self._host = problem_struct(P, int(vals64.numel()) if vals64 is not None else None)
         self.cprob = cp
         nbytes = L.tns_tasklist_workspace_bytes(ctypes.byref(cp))
         if nbytes == 0:
