@@ -448,6 +448,7 @@ def main():
         for prec in ("f32", "bf16x3"):
             if prec in outs:
                 res[prec]["sigma_rel_err_vs_f64"] = float(torch.linalg.norm(outs[prec] - ref) / torch.linalg.norm(ref))
+                log("%s sigma relative error against the FP64 product: %.3e" % (prec, res[prec]["sigma_rel_err_vs_f64"]))
     if args.only:
         print(json.dumps({"only": args.only, **res[args.only]}), flush=True)
         return
@@ -574,7 +575,7 @@ def main():
                    "tile_table": "%08x" % H.tiles, "autotuned": bool(args.autotune)},
         "pct_mfma_peak": round(head["pct_peak"], 2),
         "measured_mfma_peak": {k: round(v, 1) for k, v in mpeak.items() if isinstance(v, float)},
-        "precisions": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+        "precisions": {k: {kk: (float("%.4g" % vv) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                        for k, v in res.items()},
         "mixed_vs_f64_speedup": round(res[args.prec]["tflops"] / res["f64"]["tflops"], 3),
         "roofline": roofline,

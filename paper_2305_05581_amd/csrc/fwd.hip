@@ -367,8 +367,9 @@ template <int P, int PH> struct Geo {
 // Drives the ring over one stream of K steps.  dma(stage) fills a stage
 // with the load cursor's K step (zeros once the stream is exhausted) and
 // adv() moves the cursor on, returning 1 for a real step and 0 past the end;
-// mma(frags) is the MFMA work of one step and post() runs after each real
-// step (tile completion).  Loads run NS - 1 steps ahead; step s uses stage
+// mma(frags, J) is the MFMA work of one step, J (a compile-time constant) the
+// step's position in the unrolled group of NS steps, and post() runs after
+// each real step (tile completion).  Loads run NS - 1 steps ahead; step s uses stage
 // s mod NS, written NS - 1 steps earlier.  Every step issues a stage and
 // runs its MFMA work (past the end on zeros): the loads, the operand reads
 // and the MFMA work of a step form one branch-free block that the compiler
@@ -405,7 +406,7 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &
       ring_sync<P, KS, NS, true>();
       dma(stage<j>(rg));
       ring_read(stage<(j + 1) % NS>(rg), nxt);
-      mma(cur);
+      mma(cur, J);
       issued += adv();
       if (s < issued) post();
     };
@@ -423,7 +424,7 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &
         ring_sync<P, KS, NS, false>();
         dma(stage<(j + NS - 1) % NS>(rg));
         ring_read(stage<j>(rg), f);
-        mma(f);
+        mma(f, J);
         issued += adv();
         if (s + j < issued) post();
       });
@@ -460,11 +461,16 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   constexpr int BK = RingL<P, KS>::BK;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
-  A4 acc[4][4];
+  // FP32: the MFMA accumulators take NS steps at a time and are then added
+  // into a second set (two-level summation), so that the rounding error over
+  // a long inner dimension grows with the square roots of the steps per fold
+  // and of the number of folds rather than with that of the whole dimension.
+  constexpr bool TWO = P == TNS_F32;
+  A4 acc[4][4], acc2[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc2[i][j] = vzero<A4>();
   int seg = it.tb, lj = 0, lK;
   bool ldone = false;  // every segment has lK >= 1
   LoadSet LS;
@@ -511,7 +517,19 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
         }
         return 1;
       },
-      [&](const FR &f) { ring_mma<P, KS, TM, TN, false>(f, acc); }, [] {});
+      [&](const FR &f, auto J) {
+        ring_mma<P, KS, TM, TN, false>(f, acc);
+        if constexpr (TWO && decltype(J)::value == Geo<P, 1>::NS - 1) {
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              acc2[i][j] += acc[i][j];
+              acc[i][j] = vzero<A4>();
+            }
+        }
+      },
+      [] {});
   const int R = cld(&g.grp_rows[it.grp]), C = cld(&g.grp_cols[it.grp]);
   auto slot = gptr(reinterpret_cast<typename FP<P>::Acc *>(g.partial) + cld(&g.slot_off[it.slot]));
 #pragma unroll
@@ -524,7 +542,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
         const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
         if (row < R && col < C) {
           const int64_t o = mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
-          slot[o] = acc[i][j][v];
+          slot[o] = TWO ? acc2[i][j][v] + acc[i][j][v] : acc[i][j][v];
         }
       }
     }
@@ -677,7 +695,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
         else ldone = true;
         return 1;
       },
-      [&](const FR &f) { ring_mma<P, KS, 4, TN, true>(f, acc); },
+      [&](const FR &f, auto) { ring_mma<P, KS, 4, TN, true>(f, acc); },
       [&]() {
         if ((ck0 += BK) < K) return;
         ck0 = 0;

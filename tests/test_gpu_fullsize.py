@@ -44,9 +44,17 @@ def test_cfg3_sampled_parity():
     assert want.tobytes() == got.tobytes()
     psi = gaussian_psi(P, 3)
     ref = oheff.sigma_sectors(P, psi, pick, tasks=ref_tasks)
+    full64 = None
     for prec, tol in (("f64", 1e-12), ("f32", 1e-6), ("bf16x3", 2e-4)):
         dt = torch.float64 if prec == "f64" else torch.float32
-        out = H.apply(to_dev(psi, dt), prec).double().cpu().numpy()
+        y = H.apply(to_dev(psi, dt), prec).double()
+        if full64 is None:
+            full64 = y
+        else:  # all of sigma against the FP64 product (pinned on the sample)
+            whole = float(torch.linalg.norm(y - full64) / torch.linalg.norm(full64))
+            say("  %s whole-sigma rel err against FP64 %.3e" % (prec, whole))
+            assert whole <= tol
+        out = y.cpu().numpy()
         num = den = 0.0
         for s in pick:
             a = out[P.psi_off[s]:P.psi_off[s + 1]]
@@ -105,3 +113,46 @@ def test_grad1024_sampled_backward():
         e2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
         say("  %s sampled rel err d psi %.3e, d blocks %.3e" % (prec, e1, e2))
         assert e1 <= tol and e2 <= tol
+
+
+@pytest.mark.timeout(600)
+def test_batch64_generator_sampled_parity():
+    """The batched product (one launch per phase for all instances) on the
+    first 12 instances of bench.py's batch64 generator (L 20..40, D 256..2048
+    log-uniform, K = L^2): FP64 on two output sectors per instance (its
+    largest and a seeded random one) against the oracle, FP32 and BF16x3 over
+    all of sigma against that FP64 product."""
+    from paper_2305_05581_amd.tns import HeffProblem, HeffBatch
+    import bench
+    rng = np.random.default_rng(11)
+    Ps, Hs, picks = [], [], []
+    for i, c in enumerate(bench.batch_specs(64)[:12]):
+        P = synthetic_problem(c["L"], c["N"], c["twoSz"], c["D"], c["mean"], c["dmax"], c["K"], seed=c["seed"],
+                              threads=min(16, os.cpu_count() or 1))
+        H = HeffProblem(P)
+        tasks, ptr = H.tasks()
+        cost = np.array([tasks["cost"][ptr[s]:ptr[s + 1]].sum() for s in range(P.nS)])
+        pick = sorted({int(np.argmax(cost)), int(rng.choice(np.nonzero(cost > 0)[0]))})
+        say("instance %d: L=%d D=%d tasks %d, sectors %s" % (i, c["L"], c["D"], H.ntasks, pick))
+        Ps.append(P)
+        Hs.append(H)
+        picks.append(pick)
+    B = HeffBatch(Hs)
+    xs = [gaussian_psi(P, 60 + i) for i, P in enumerate(Ps)]
+    ref64 = B.apply([to_dev(x) for x in xs], "f64")
+    for i, (P, x, y, pick) in enumerate(zip(Ps, xs, ref64, picks)):
+        ref = oheff.sigma_sectors(P, x, pick)
+        got = y.cpu().numpy()
+        a = np.concatenate([got[P.psi_off[s]:P.psi_off[s + 1]] for s in pick])
+        b = np.concatenate([ref[s].reshape(-1) for s in pick])
+        err = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        say("  f64 instance %d sampled rel err %.2e" % (i, err))
+        assert err <= 1e-12
+    # the FP64 product is pinned to the oracle above; the reduced precisions
+    # are held to their bars over the whole of sigma against it
+    for prec, tol in (("f32", 1e-6), ("bf16x3", 2e-4)):
+        outs = B.apply([to_dev(x, torch.float32) for x in xs], prec)
+        for i, (y, r) in enumerate(zip(outs, ref64)):
+            err = float(torch.linalg.norm(y.double() - r) / torch.linalg.norm(r))
+            say("  %s instance %d whole-sigma rel err against FP64 %.2e" % (prec, i, err))
+            assert err <= tol, (prec, i, err)
