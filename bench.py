@@ -133,6 +133,8 @@ def phase_flops(P, tasks):
     fa = int(np.sum(np.where(idX, 0, 2 * R * K1 * K2)))
     fb = int(np.sum(np.where(idY, 0, 2 * R * K2 * C)))
     return fa, fb
+
+
 def backward_flops(P, tasks):
     """Algorithmic flops of the backward product (d psi and the operator-block
     gradients of every task): d psi = alpha L^T G R in the cheaper order of
