@@ -518,7 +518,7 @@ __global__ void k_pan_total(Plan p) {
 
 __global__ void k_pan_target(Plan p) {
   if (threadIdx.x == 0 && blockIdx.x == 0)
-    p.pa.scalars[1] = p.pa.scalars[0] / ((int64_t)ITEMS_PER_CU * p.n_cu) + 1;
+    p.pa.scalars[1] = p.pa.scalars[0] / ((int64_t)PANEL_ITEMS_PER_CU * p.n_cu) + 1;
 }
 
 __global__ void k_pan_count(Plan p) {
@@ -553,7 +553,9 @@ __global__ void k_pan_items(Plan p) {
       it.nc = min(tc, N - c * tc);
       it.mode = (tail_ext(it.nc, tc) / 32) << 16;
       it.cost = 2 * (r1 - r0) * PCH * (int64_t)it.nc * K;
-      const int64_t j = ib + (int64_t)c * pieces + k;
+      // the column tiles of a row piece are neighbours in the queue, so that
+      // they run at the same time and share the piece's operator rows in L2
+      const int64_t j = ib + (int64_t)k * ncol + c;
       A.items_unsorted[j] = it;
       A.ikeys_in[j] = ((uint64_t)A.xcd[G] << 56) | ((uint64_t)A.rank[G] << 28) | ((uint64_t)(j - ib) & LM);
       A.ivals_in[j] = (int32_t)j;
@@ -836,8 +838,8 @@ static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int m
   A.ntcap = ntcap;
   A.tiles = TILES_DEFAULT;
   // items: a panel's column tiles (smallest extent 32) plus one extra row
-  // piece per ITEMS_PER_CU share of the work
-  A.items_cap = std::max<int64_t>(2 * (int64_t)ITEMS_PER_CU * n_cu + (int64_t)ng * ((maxdim + 31) / 32) + 16, ng);
+  // piece per PANEL_ITEMS_PER_CU share of the work
+  A.items_cap = std::max<int64_t>(2 * (int64_t)PANEL_ITEMS_PER_CU * n_cu + (int64_t)ng * ((maxdim + 31) / 32) + 16, ng);
   const size_t g1 = (size_t)ng + 1;
   A.keys_in = cv.take<int32_t>(ntcap); A.keys_out = cv.take<int32_t>(ntcap);
   A.vals_in = cv.take<int32_t>(ntcap); A.idx = cv.take<int32_t>(ntcap);

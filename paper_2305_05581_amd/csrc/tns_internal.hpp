@@ -17,6 +17,9 @@ constexpr int MAX_DIM = 32768;
 // Work items per compute unit the schedule aims at (load balance of the
 // longest-first queue).
 constexpr int ITEMS_PER_CU = 8;
+// Phase-A work items per compute unit: short row pieces whose column tiles
+// run side by side on one XCD, so that they share the operator rows in L2.
+constexpr int PANEL_ITEMS_PER_CU = 64;
 // Most work queues of a schedule: one per XCD (accelerator complex die, each
 // with its own L2).  Workgroup b of a launch runs on XCD b mod n_xcd, since
 // workgroups are dispatched to the dies round-robin.
