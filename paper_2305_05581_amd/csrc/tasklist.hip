@@ -516,9 +516,18 @@ __global__ void k_pan_total(Plan p) {
   atomicAdd((unsigned long long *)&A.scalars[0], (unsigned long long)(2 * nrt * GM * (int64_t)tc * K * ncol));
 }
 
+// Target cost of a phase-A work item: PANEL_ITEMS_PER_CU items per CU on
+// large products, but never below PANEL_ITEM_MIN_FLOP unless the product has
+// fewer than ITEMS_PER_CU items of that size per CU (small products keep
+// ITEMS_PER_CU items per CU, whose per-item overhead would otherwise dominate).
 __global__ void k_pan_target(Plan p) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    p.pa.scalars[1] = p.pa.scalars[0] / ((int64_t)PANEL_ITEMS_PER_CU * p.n_cu) + 1;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int64_t total = p.pa.scalars[0];
+    const int64_t fine = total / ((int64_t)PANEL_ITEMS_PER_CU * p.n_cu);
+    const int64_t coarse = total / ((int64_t)ITEMS_PER_CU * p.n_cu);
+    const int64_t floor_ = coarse < PANEL_ITEM_MIN_FLOP ? coarse : PANEL_ITEM_MIN_FLOP;
+    p.pa.scalars[1] = (fine > floor_ ? fine : floor_) + 1;
+  }
 }
 
 __global__ void k_pan_count(Plan p) {

@@ -20,6 +20,7 @@ constexpr int ITEMS_PER_CU = 8;
 // Phase-A work items per compute unit: short row pieces whose column tiles
 // run side by side on one XCD, so that they share the operator rows in L2.
 constexpr int PANEL_ITEMS_PER_CU = 64;
+constexpr int64_t PANEL_ITEM_MIN_FLOP = 100000000;
 // Most work queues of a schedule: one per XCD (accelerator complex die, each
 // with its own L2).  Workgroup b of a launch runs on XCD b mod n_xcd, since
 // workgroups are dispatched to the dies round-robin.
