@@ -256,8 +256,13 @@ __global__ void k_chunks(Plan p, Sched S) {
   const int n = S.grp_n[g];
   int nc = 0;
   if (n > 0) {
+    // ITEMS_PER_CU items per CU on large schedules, but chunks no smaller
+    // than ITEM_MIN_FLOP unless that leaves fewer than ITEMS_MIN_PER_CU per CU
     const int64_t total = S.scalars[0];
-    const int64_t target = total / ((int64_t)ITEMS_PER_CU * p.n_cu) + 1;
+    const int64_t fine = total / ((int64_t)ITEMS_PER_CU * p.n_cu);
+    const int64_t coarse = total / ((int64_t)ITEMS_MIN_PER_CU * p.n_cu);
+    const int64_t floor_ = coarse < ITEM_MIN_FLOP ? coarse : ITEM_MIN_FLOP;
+    const int64_t target = (fine > floor_ ? fine : floor_) + 1;
     const int64_t cap = target * cap_tiles(S, S.grp_rows[g], S.grp_cols[g]);
     const int b = S.grp_begin[g], mode = S.grp_mode[g];
     int64_t cur = 0;
@@ -518,13 +523,14 @@ __global__ void k_pan_total(Plan p) {
 
 // Target cost of a phase-A work item: PANEL_ITEMS_PER_CU items per CU on
 // large products, but never below PANEL_ITEM_MIN_FLOP unless the product has
-// fewer than ITEMS_PER_CU items of that size per CU (small products keep
-// ITEMS_PER_CU items per CU, whose per-item overhead would otherwise dominate).
+// fewer than PANEL_ITEMS_MIN_PER_CU items of that size per CU (small products
+// keep that many items per CU, whose per-item overhead would otherwise
+// dominate).
 __global__ void k_pan_target(Plan p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int64_t total = p.pa.scalars[0];
     const int64_t fine = total / ((int64_t)PANEL_ITEMS_PER_CU * p.n_cu);
-    const int64_t coarse = total / ((int64_t)ITEMS_PER_CU * p.n_cu);
+    const int64_t coarse = total / ((int64_t)PANEL_ITEMS_MIN_PER_CU * p.n_cu);
     const int64_t floor_ = coarse < PANEL_ITEM_MIN_FLOP ? coarse : PANEL_ITEM_MIN_FLOP;
     p.pa.scalars[1] = (fine > floor_ ? fine : floor_) + 1;
   }
