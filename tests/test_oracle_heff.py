@@ -188,3 +188,44 @@ def test_order_flag_does_not_change_sigma():
     tasks = heff.enumerate_tasks(P)
     flipped = [t[:5] + (1 - t[5],) + t[6:] if (t[3] >= 0 and t[4] >= 0) else t for t in tasks]
     assert rel(heff.sigma(P, x, tasks), heff.sigma(P, x, flipped)) < 1e-13
+
+
+def _sectors_instances(cfg1):
+    h, eri = molecular_integrals(6, 13)
+    return [("exact cfg1", cfg1["P"]),
+            ("exact odd 2Sz", Construction(h, eri, 5, 1, l=2).problem()),
+            ("ragged synthetic", synthetic_problem(14, 14, 0, 70, 6, 23, 40, seed=17)),
+            ("gapped synthetic", synthetic_problem(12, 12, 0, 40, 5, 12, 30, seed=5, gapped=True))]
+
+
+def test_sigma_sectors_equals_sigma(cfg1):
+    """Eq. (2) restricted to a subset of output sectors: ``sigma_sectors``
+    (the reference of the sampled and whole-product checks) returns exactly
+    the corresponding slices of the pinned ``sigma`` on every sector, through
+    both of its routes (its own filtered enumeration, and a caller's task
+    list that holds other sectors too).  The instances cover identity-side
+    and both-identity terms (cfg1), an odd 2Sz target, ragged sector sizes
+    and the gapped diagonal terms."""
+    for name, P in _sectors_instances(cfg1):
+        psi = gaussian_psi(P, 9)
+        full = heff.sigma(P, psi)
+        every = heff.sigma_sectors(P, psi, range(P.nS))
+        assert sorted(every) == list(range(P.nS)), name
+        for s in range(P.nS):
+            got = every[s].reshape(-1)
+            want = full[P.psi_off[s]:P.psi_off[s + 1]]
+            assert got.shape == want.shape and np.array_equal(got, want), (name, s)
+        rng = np.random.default_rng(3)
+        pick = sorted(int(s) for s in rng.choice(P.nS, min(5, P.nS), replace=False))
+        all_tasks = heff.enumerate_tasks(P)
+        for sub in (heff.sigma_sectors(P, psi, pick), heff.sigma_sectors(P, psi, pick, tasks=all_tasks)):
+            assert sorted(sub) == pick, name
+            for s in pick:
+                assert np.array_equal(sub[s].reshape(-1), full[P.psi_off[s]:P.psi_off[s + 1]]), (name, s)
+        # the filtered enumeration holds exactly the tasks of the picked sectors
+        filt = heff.enumerate_tasks(P, out_filter=set(pick))
+        assert filt == [t for t in all_tasks if t[0] in set(pick)], name
+        # identity-side and both-identity tasks are present where the instance has them
+        if name == "exact cfg1":
+            assert any(t[3] < 0 <= t[4] for t in all_tasks) and any(t[4] < 0 <= t[3] for t in all_tasks)
+            assert any(t[3] < 0 and t[4] < 0 for t in all_tasks)
