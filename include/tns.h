@@ -175,6 +175,23 @@ tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, const void *op_
                           const void *psi, void *sigma, double beta, void *ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* tns_apply_heff for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product, bitwise identical to tns_apply_heff, with the workspace
+ * taken from a fixed device array that the library holds on every device it
+ * runs on (TNS_NOALLOC_SCRATCH_BYTES = 64 MiB each, kept until the process
+ * ends) instead of a caller buffer.  The call allocates nothing and enqueues
+ * the same kernels on `stream` (asynchronous); the first call on a device
+ * looks the array's address up once.  TNS_ERR_WORKSPACE when the product
+ * needs more than the array (tns_apply_workspace_bytes(tl, prec) >
+ * TNS_NOALLOC_SCRATCH_BYTES); other errors as tns_apply_heff.  Every call on
+ * one device shares that device's array: calls whose executions overlap on
+ * one device (several streams, several host threads) race and give wrong
+ * results; serialise them. */
+#define TNS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tns_status tns_apply_heff_noalloc(const tns_tasklist *tl, tns_prec prec, const void *op_vals, const void *psi,
+                                  void *sigma, double beta, hipStream_t stream);
+
 /* Batched form of tns_apply_heff (level 3, Eq. (2), for many independent
  * problems): sigma_i := beta * sigma_i + H_eff,i psi_i for i < n, with one
  * persistent launch per GEMM phase for all instances together (work of the

@@ -20,6 +20,7 @@
 // panel into its own partial slot and an epilogue adds the slots of every
 // block in a fixed order.
 #include <algorithm>
+#include <mutex>
 
 #include "kern.hpp"
 #include "tns_internal.hpp"
@@ -693,6 +694,53 @@ extern "C" tns_status tns_apply_heff(const tns_tasklist *tl, tns_prec prec, cons
   if (prec != TNS_F64 && prec != TNS_F32 && prec != TNS_BF16X3) return TNS_ERR_ARG;
   if (beta != 0.0 && beta != 1.0) return TNS_ERR_ARG;
   return apply_impl(plan_of(tl), prec, op_vals, psi, sigma, beta, ws, ws_bytes, st);
+}
+
+// --- the allocation-free product ----------------------------------------------
+// Device array that stands in for the caller's workspace in
+// tns_apply_heff_noalloc.  Each device holds its own copy, at its own address,
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name is a stand-in, not a device address): it
+// passes the address hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) uint8_t scratch[TNS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the stream's device, looked up once per
+// device with that device current.
+static tns_status scratch_for(hipStream_t st, void **out) {
+  int dev = -1, cur = -1;
+  TNS_HIP(hipGetDevice(&cur));
+  TNS_HIP(hipStreamGetDevice(st, &dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return TNS_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    if (dev != cur) TNS_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) TNS_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || !p) return TNS_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TNS_OK;
+}
+
+extern "C" tns_status tns_apply_heff_noalloc(const tns_tasklist *tl, tns_prec prec, const void *op_vals,
+                                             const void *psi, void *sigma, double beta, hipStream_t st) {
+  if (!tl || !op_vals || !psi || !sigma) return TNS_ERR_ARG;
+  if (prec != TNS_F64 && prec != TNS_F32 && prec != TNS_BF16X3) return TNS_ERR_ARG;
+  if (beta != 0.0 && beta != 1.0) return TNS_ERR_ARG;
+  const Plan &p = plan_of(tl);
+  if (fwd_workspace(p, prec) > TNS_NOALLOC_SCRATCH_BYTES) return TNS_ERR_WORKSPACE;
+  void *ws = nullptr;
+  const tns_status s = scratch_for(st, &ws);
+  if (s != TNS_OK) return s;
+  // the product clears what must start at zero (queue counters, the zero
+  // region) with a kernel and writes every other byte it reads
+  return apply_impl(p, prec, op_vals, psi, sigma, beta, ws, TNS_NOALLOC_SCRATCH_BYTES, st);
 }
 
 extern "C" void tns_profile_events(hipEvent_t before, hipEvent_t mid, hipEvent_t after) {

@@ -81,6 +81,10 @@ def library(path=LIB_PATH):
     L.tns_prepare_operands.argtypes = [ctypes.c_int, _P, _i64, _P, _P]
     L.tns_apply_heff.restype = ctypes.c_int
     L.tns_apply_heff.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int, _P, _P, _P, ctypes.c_double, _P, sz, _P]
+    if hasattr(L, "tns_apply_heff_noalloc"):
+        L.tns_apply_heff_noalloc.restype = ctypes.c_int
+        L.tns_apply_heff_noalloc.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int, _P, _P, _P, ctypes.c_double,
+                                             _P]
     if hasattr(L, "tns_apply_heff_backward"):
         L.tns_backward_workspace_bytes.restype = sz
         L.tns_backward_workspace_bytes.argtypes = [ctypes.POINTER(TnsTasklist), ctypes.c_int]
@@ -266,6 +270,18 @@ class HeffProblem:
         ws = self.workspace("apply", p)
         _check(library().tns_apply_heff(ctypes.byref(self.tl), p, _ptr(self._ops_arg(p, ops)), _ptr(psi), _ptr(out),
                                         float(beta), _ptr(ws), ws.numel(), _stream()), "tns_apply_heff")
+        return out
+
+    def apply_noalloc(self, psi, out, prec="f64", beta=0.0):
+        """``apply`` through ``tns_apply_heff_noalloc``: the library's fixed
+        device scratch instead of a workspace tensor (``out`` given by the
+        caller; nothing is allocated)."""
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        self._vec(psi, dt, "psi")
+        self._vec(out, dt, "out")
+        _check(library().tns_apply_heff_noalloc(ctypes.byref(self.tl), p, _ptr(self.operands(p)), _ptr(psi),
+                                                _ptr(out), float(beta), _stream()), "tns_apply_heff_noalloc")
         return out
 
     # -- tile table (per sector-size bucket) ----------------------------------
