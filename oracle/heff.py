@@ -180,6 +180,57 @@ def sigma_sectors(P, psi, sectors, tasks=None):
     return res
 
 
+def sigma_threaded(P, psi, tasks=None, threads=None, sectors=None):
+    """:func:`sigma` (Eq. (2)) with the output sectors shared out over a pool
+    of ``threads`` Python threads (default: the cores this process may run
+    on), BLAS at one thread per call.  Each output sector is summed by one
+    thread in task-table order, as :func:`sigma` sums it; the two differ
+    only by the rounding inside the BLAS calls.  ``sectors``: only these output
+    sectors (the rest of the result stays zero).  Returns ``(sigma, threads)``."""
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+    from threadpoolctl import threadpool_limits
+    if tasks is None:
+        tasks = enumerate_tasks(P)
+    by_out = {}
+    for t in tasks:
+        by_out.setdefault(int(t[0]), []).append(t)
+    outs = sorted(by_out) if sectors is None else sorted(set(int(x) for x in sectors) & set(by_out))
+    # largest sectors first so that the pool ends evenly
+    outs.sort(key=lambda s2: -sum(int(t[7]) for t in by_out[s2]))
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
+    out = np.zeros(P.psi_dim)
+
+    def one(s2):
+        acc = None
+        for t in by_out[s2]:
+            y = task_product(P, psi, t)
+            acc = y if acc is None else acc + y
+        out[P.psi_off[s2]:P.psi_off[s2 + 1]] += acc.reshape(-1)
+
+    with threadpool_limits(limits=1, user_api="blas"):
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(one, outs))
+    return out, threads
+
+
+def diagonal(P, tasks):
+    """diag(H_eff) from the definition of Eq. (2): only tasks whose output
+    sector is their input sector reach the diagonal, each adding
+    ``alpha * diag(L) (x) diag(R)`` (a ones vector for an identity side)."""
+    d = np.zeros(P.psi_dim)
+    for (s2, s, k, lb, rb, order, alpha, _) in tasks:
+        if s2 != s:
+            continue
+        m = int(P.dimL[P.psi_sec[s][0]])
+        n = int(P.dimR[P.psi_sec[s][3]])
+        dl = np.diag(P.block(lb)) if lb >= 0 else np.ones(m)
+        dr = np.diag(P.block(rb)) if rb >= 0 else np.ones(n)
+        d[P.psi_off[s]:P.psi_off[s + 1]] += alpha * np.outer(dl, dr).reshape(-1)
+    return d
+
+
 def total_flops(tasks):
     return int(sum(int(t[7]) for t in tasks))
 

@@ -11,18 +11,7 @@ from oracle.davidson import davidson
 
 
 def diag_of(P, tasks):
-    """diag(H_eff) read off a dense assembly is avoided: take it from the
-    tasks whose output is their input, as the definition gives it."""
-    d = np.zeros(P.psi_dim)
-    for (s2, s, k, lb, rb, order, alpha, _) in tasks:
-        if s2 != s:
-            continue
-        m = int(P.dimL[P.psi_sec[s][0]])
-        n = int(P.dimR[P.psi_sec[s][3]])
-        dl = np.diag(P.block(lb)) if lb >= 0 else np.ones(m)
-        dr = np.diag(P.block(rb)) if rb >= 0 else np.ones(n)
-        d[P.psi_off[s]:P.psi_off[s + 1]] += alpha * np.outer(dl, dr).reshape(-1)
-    return d
+    return heff.diagonal(P, tasks)
 
 
 def test_cfg1_davidson_equals_fci(cfg1):

@@ -229,3 +229,27 @@ def test_sigma_sectors_equals_sigma(cfg1):
         if name == "exact cfg1":
             assert any(t[3] < 0 <= t[4] for t in all_tasks) and any(t[4] < 0 <= t[3] for t in all_tasks)
             assert any(t[3] < 0 and t[4] < 0 for t in all_tasks)
+
+
+def test_sigma_threaded_equals_sigma():
+    """The thread-pool driver of the oracle's sigma (output sectors over
+    threads, BLAS at one thread) against the pinned sequential sum of Eq. (2),
+    on a ragged synthetic instance, an exact-block instance and a subset of
+    output sectors."""
+    from synth import molecular_integrals
+    from oracle.blocks import Construction
+    for P in (synthetic_problem(22, 22, 0, 700, 23, 187, 120, seed=12),
+              Construction(*molecular_integrals(8, 1), 8, 0).problem()):
+        psi = gaussian_psi(P, 4)
+        t = heff.enumerate_tasks(P)
+        ref = heff.sigma(P, psi, t)
+        got, n = heff.sigma_threaded(P, psi, t, threads=3)
+        assert n == 3
+        assert np.linalg.norm(got - ref) <= 1e-14 * np.linalg.norm(ref)
+        part, _ = heff.sigma_threaded(P, psi, t, threads=2, sectors=[0, P.nS - 1])
+        for s in range(P.nS):
+            a, b = P.psi_off[s], P.psi_off[s + 1]
+            if s in (0, P.nS - 1):
+                assert np.allclose(part[a:b], ref[a:b], rtol=0, atol=1e-14 * max(1.0, np.abs(ref).max()))
+            else:
+                assert not part[a:b].any()
