@@ -262,8 +262,10 @@ tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec prec, const 
  * device; the matrix-vector products run in `inner` precision.  With
  * refine != 0 and inner != TNS_F64, each inner convergence is followed by an
  * FP64 product w = H x, theta = <x, w>, r = w - theta x, and the inner
- * iteration restarts from (x, w) until |r| <= tol_res.  The reported energy
- * is the FP64 Rayleigh quotient. */
+ * iteration restarts from (x, w) (iterative refinement: each restarted inner
+ * iteration aims at a twentieth of the last FP64 residual) until the FP64
+ * residual |r| <= tol_res; acceptance never rests on the inner-precision
+ * residual.  The reported energy is the FP64 Rayleigh quotient. */
 typedef struct {
   int32_t max_sub;     /* subspace size before restart (<= 64)   */
   int32_t keep;        /* Ritz vectors kept at restart           */

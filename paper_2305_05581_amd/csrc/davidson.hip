@@ -293,12 +293,16 @@ __global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ S, in
   if (tid < k) ev[tid] = A[order[tid]][order[tid]];
 }
 
-// S[i][kk] = S[kk][i] = (<V_i, W_kk> + <W_i, V_kk>) / 2 for i <= kk
+// S[i][kk] = S[kk][i] = (<V_i, W_kk> + <W_i, V_kk>) / 2 for i <= kk.  With
+// exact0, W_0 = H V_0 holds an FP64 product while the later columns of W come
+// from the inner precision: the coupling of V_0 is then taken from the exact
+// side alone, <W_0, V_kk> (after an FP64 correction it is about the residual
+// size, below the inner precision's rounding of <V_0, W_kk>).
 __global__ void k_fill_S(double *__restrict__ S, const double *__restrict__ vw, const double *__restrict__ wv,
-                         int kk) {
+                         int kk, int exact0) {
   const int i = threadIdx.x;
   if (i > kk) return;
-  const double v = 0.5 * (vw[i] + wv[i]);
+  const double v = (exact0 && i == 0) ? wv[0] : 0.5 * (vw[i] + wv[i]);
   S[i * DV_MAXSUB + kk] = v;
   S[kk * DV_MAXSUB + i] = v;
 }
@@ -422,6 +426,9 @@ extern "C" tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_op
   int k = 1;
   double theta_prev = NAN, best_res = INFINITY;
   int stall = 0, rounds = 0;
+  bool rounds_done = false;  // an FP64 correction has run
+  bool w0_exact = false;     // W_0 is the FP64 product of V_0 (refinement restart)
+  double r64_prev = INFINITY;
   bool accepted = false;
   // residual floor of the inner products (relative rounding of one product)
   const double eps_inner = o->inner == TNS_F32 ? 1e-6 : (o->inner == TNS_BF16X3 ? 3e-5 : 0.0);
@@ -433,7 +440,8 @@ extern "C" tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_op
     // new row / column of S
     multidot(d.V, N, k, d.W + (int64_t)(k - 1) * N, N, d, d.c, st);
     multidot(d.W, N, k, d.V + (int64_t)(k - 1) * N, N, d, d.c + DV_MAXSUB, st);
-    hipLaunchKernelGGL(k_fill_S, dim3(1), dim3(DV_MAXSUB), 0, st, d.S, d.c, d.c + DV_MAXSUB, k - 1);
+    hipLaunchKernelGGL(k_fill_S, dim3(1), dim3(DV_MAXSUB), 0, st, d.S, d.c, d.c + DV_MAXSUB, k - 1,
+                       (int)w0_exact);
     hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, st, d.S, k, d.ev, d.Y);
     hipLaunchKernelGGL(k_col, dim3(1), dim3(DV_MAXSUB), 0, st, d.Y, k, 0, d.y);
     hipLaunchKernelGGL(k_combine, dim3(g), dim3(256), 0, st, d.V, N, k, d.y, d.x, N, 0);
@@ -453,16 +461,21 @@ extern "C" tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_op
     TNS_HIP(hipMemcpyAsync(h + 3, d.ev, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     TNS_HIP(hipStreamSynchronize(st));
     const double theta = h[3], res = std::sqrt(std::max(h[1], 0.0)), tn = std::sqrt(std::max(h[2], 0.0));
-    const double gap = k > 1 ? h[4] - h[3] : INFINITY;
     inf.iters += 1;
     inf.e_lo = theta;
     if (!std::isfinite(theta) || !std::isfinite(res)) { result = TNS_ERR_NUMERIC; break; }
     if (res < 0.9 * best_res) { best_res = res; stall = 0; } else { ++stall; }
     const double floor_res = eps_inner * std::max(1.0, std::fabs(theta));
     const bool dtheta_ok = std::isfinite(theta_prev) && std::fabs(theta - theta_prev) <= o->tol_e;
-    // inner convergence: tolerance (or the precision floor) reached, or a
-    // stall of the residual close to the floor, or breakdown of the correction
-    const bool conv_inner = (res <= std::max(o->tol_res, floor_res) && dtheta_ok) ||
+    // inner convergence: the target residual reached, or a stall of the
+    // residual close to the precision floor, or breakdown of the correction.
+    // The first round aims at tol_res (or the inner rounding floor).  After an
+    // FP64 correction the inner iteration restarts from (x, H64 x): its
+    // residual is then exact up to the inner rounding of the correction alone,
+    // so it aims at a fraction of the last FP64 residual (iterative refinement).
+    const double target = rounds_done ? std::max(0.5 * o->tol_res, 0.05 * r64_prev)
+                                      : std::max(o->tol_res, floor_res);
+    const bool conv_inner = (res <= target && dtheta_ok) ||
                             (mixed && stall >= 4 && res <= 100.0 * floor_res) ||
                             tn < 1e-10 * std::max(1.0, res);
     theta_prev = theta;
@@ -486,7 +499,13 @@ extern "C" tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_op
       TNS_HIP(hipMemcpyAsync(h, d.sc + 6, sizeof(double), hipMemcpyDeviceToHost, st));
       TNS_HIP(hipStreamSynchronize(st));
       const double r64 = std::sqrt(std::max(h[0], 0.0));
-      const bool ok = r64 <= o->tol_res || (std::isfinite(gap) && gap > 0 && r64 * r64 / gap <= o->tol_e);
+      // Accept on the FP64 residual alone.  An energy bound r64^2 / gap would
+      // need a lower bound of the gap lambda2 - lambda1; the Ritz values of
+      // the (restarted, low-precision) subspace only bound lambda2 from above,
+      // so the gap cannot be bounded safely from them.
+      const bool ok = r64 <= o->tol_res;
+      rounds_done = true;
+      r64_prev = r64;
       if (ok) accepted = true;
       if (ok || rounds >= o->refine || budget <= 1) break;
       ++rounds;
@@ -494,6 +513,7 @@ extern "C" tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_op
       hipLaunchKernelGGL(k_scale_by_rnorm, dim3(g), dim3(256), 0, st, d.x, d.V, d.sc + 4, N);
       hipLaunchKernelGGL(k_scale_by_rnorm, dim3(g), dim3(256), 0, st, d.w, d.W, d.sc + 4, N);
       hipLaunchKernelGGL(k_reset_S, dim3(1), dim3(256), 0, st, d.S, d.ev, 0);
+      w0_exact = true;
       k = 1;
       best_res = INFINITY;
       stall = 0;
@@ -516,6 +536,7 @@ extern "C" tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_op
       for (int j = 0; j < o->keep; ++j)
         hipLaunchKernelGGL(k_copy, dim3(g), dim3(256), 0, st, d.T + (int64_t)j * N, d.W + (int64_t)j * N, N);
       hipLaunchKernelGGL(k_reset_S, dim3(1), dim3(256), 0, st, d.S, d.ev, o->keep);
+      w0_exact = false;  // the kept columns mix inner-precision products
       k = o->keep;
       // t is orthogonal to the old span, which contains the new one
     }

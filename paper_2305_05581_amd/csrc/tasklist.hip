@@ -320,7 +320,8 @@ __global__ void k_items(Sched S) {
     it.slot = (int32_t)c;
     it.out = S.grp_out[ch.grp];
     it.cost = ch.cost * ((int64_t)it.np * it.nc) / ((int64_t)rows * cols);
-    S.items_unsorted[ib + k] = it;
+    // the host compares the item total with items_cap after the build
+    if (ib + k < S.items_cap) S.items_unsorted[ib + k] = it;
   }
 }
 
@@ -813,18 +814,25 @@ static size_t radix_tmp_i32(int64_t n) {
 }
 
 // Carves one schedule's arrays; `idx` may be supplied by the caller.
-static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, int64_t chunks_cap, int maxdim,
-                         int tile_r, int tile_c, uint32_t tiles, int nq, bool own_idx) {
+// tile_sum: the number of output tiles of all groups at the smallest tile
+// extent (32 x 32 with a tile table, tile_r rows without).  Work items are
+// bounded without knowing the tasks: k_chunks closes a chunk before the task
+// that would take it over cap = target x (tiles of the group at the largest
+// extent), so any two consecutive chunks of a group cost more than cap, a
+// group of cost c has at most 1 + 2c / cap chunks, and with target above
+// total / (ITEMS_PER_CU n_cu) all groups together have at most
+// tile_sum + 2 x 16 x ITEMS_PER_CU n_cu items (16 smallest tiles per
+// largest one; factor 1 without a tile table).
+static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, int64_t chunks_cap, int64_t tile_sum,
+                         int n_cu, int tile_r, int tile_c, uint32_t tiles, int nq, bool own_idx) {
   S.ngroups = ngroups;
   S.ntcap = ntcap;
   S.chunks_cap = chunks_cap;
   S.tile_r = tile_r;
   S.tile_c = tile_c;
   S.tiles = tiles;
-  // items: up to the smallest tiles of the table (32 x 32) per chunk
-  const int er = tiles ? 32 : tile_r, ec = tiles ? 32 : tile_c;
-  const int64_t tmax = (int64_t)((maxdim + er - 1) / er) * (ec > 0 ? (maxdim + ec - 1) / ec : 1);
-  S.items_cap = chunks_cap * tmax;
+  const int64_t per_big = tiles ? (int64_t)(GM / 32) * (GN / 32) : 1;
+  S.items_cap = std::max<int64_t>(chunks_cap, tile_sum + 2 * per_big * ITEMS_PER_CU * (int64_t)n_cu + 16);
   S.nq = nq;
   if (own_idx) S.idx = cv.take<int32_t>(ntcap);
   const size_t ng = std::max(1, ngroups);
@@ -903,9 +911,13 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.segb = cv.take<SegRec>(ntcap);
   p.pp_off = cv.take<int64_t>(P->nS + 1);
   p.pt_off = cv.take<int64_t>(P->nS + 1);
-  // forward schedule: 2 groups per sector, output tiles GM x GN
+  // forward schedule: 2 groups per sector (sigma and sigma^T of its
+  // output), output tiles GM x GN at most, 32 x 32 at least
   const int64_t fchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 4 * (int64_t)P->nS + 16;
-  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, maxdim, GM, GN, TILES_DEFAULT, n_xcd, true);
+  int64_t ftiles = 0;
+  for (int s = 0; s < P->nS; ++s)
+    ftiles += 2 * (int64_t)((P->dimL[P->psi_sec[4 * s]] + 31) / 32) * ((P->dimR[P->psi_sec[4 * s + 3]] + 31) / 32);
+  layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
   // backward schedule: one group per sector (d psi) and one per block (d L / d R)
   const int64_t bent = 3 * ntcap;
   p.bkeys_in = cv.take<int32_t>(bent); p.bkeys_out = cv.take<int32_t>(bent); p.bvals_in = cv.take<int32_t>(bent);
@@ -914,7 +926,9 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.bsort_tmp = cv.take<char>(p.bsort_tmp_bytes + 256);
   const int32_t bgroups = P->nS + P->nBlk;
   const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
-  layout_sched(cv, p.bwd, bgroups, bent, bchunks, maxdim, TQ, 0, 0u, n_xcd, false);
+  int64_t btiles = 0;  // row panels of the operator-block groups (the sector groups stay empty)
+  for (int b = 0; b < P->nBlk; ++b) btiles += (P->blk_rows[b] + TQ - 1) / TQ;
+  layout_sched(cv, p.bwd, bgroups, bent, bchunks, btiles, n_cu, TQ, 0, 0u, n_xcd, false);
   layout_panels(cv, p.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
   // adjoint task list (d psi of the backward) and its forward schedule
   Adjoint &J = p.adj;
@@ -927,8 +941,13 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   J.segb = cv.take<SegRec>(ntcap);
   J.n_vals = 0;
   for (int b = 0; b < P->nBlk; ++b) J.n_vals += (int64_t)P->blk_cols[b] * ld8(P->blk_rows[b]);
-  layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, maxdim, GM, GN, TILES_DEFAULT, n_xcd, true);
+  layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
   layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
+  // counts that the sorts and item indices hold in 32 bits
+  const int64_t caps[] = {bent, p.fwd.items_cap, p.bwd.items_cap, J.fwd.items_cap, p.pa.items_cap, J.pa.items_cap,
+                          p.fwd.chunks_cap, p.bwd.chunks_cap};
+  for (int64_t c : caps)
+    if (c >= INT32_MAX) return 0;
   if (pl) *pl = p;
   return cv.off + 256;
 }
@@ -1128,6 +1147,7 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   if (s != TNS_OK) return s;
   const int n_cu = device_cu_count(), n_xcd = device_xcd_count();
   const size_t need = layout(P, nmax, maxdim, n_cu, n_xcd, nullptr, nullptr);
+  if (need == 0) return TNS_ERR_SHAPE;  // schedule counts beyond 32-bit indices
   if (ws_bytes < need) return TNS_ERR_WORKSPACE;
   Plan p;
   layout(P, nmax, maxdim, n_cu, n_xcd, (char *)ws, &p);

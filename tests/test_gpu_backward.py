@@ -89,3 +89,40 @@ def test_rdm_from_gpu_block_gradients(cases):
     dh, dv = ograd.integral_gradients(C, P, go.cpu().numpy(), dcoef, h.shape)
     g1, g2 = rdms(v[:, 0], dets, 6)
     assert abs(dh - g1).max() < 1e-10 and abs(dv - 0.5 * g2).max() < 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_integral_gradients_exact10():
+    """Integral gradients at the exact-block L = 10 size (blocks of 4
+    orbitals, 256 states each, psi dimension 63504): the GPU operator-block
+    gradients of E = <x, H x> in FP64 and FP32, contracted with the
+    construction's strings, against the brute-force RDMs of x stored by
+    tests/golden/make_exact10_rdm.py (gamma = dE/dh, Gamma / 2 = dE/d(ij|kl))."""
+    import json
+    import os
+    from paper_2305_05581_amd.tns import HeffProblem
+    with open(os.path.join(os.path.dirname(__file__), "golden", "exact10_rdm.json")) as fh:
+        g = json.load(fh)
+    L = g["L"]
+    h, eri = molecular_integrals(L, g["integral_seed"])
+    say("exact10: building blocks")
+    C = Construction(h, eri, g["N"], g["twoSz"])
+    P = C.problem()
+    assert P.psi_dim == g["psi_dim"]
+    x = gaussian_psi(P, 7)
+    # coefficient gradients only for the terms that keep their weight in the
+    # coefficient (identity on both blocks); every other string is contracted
+    # from the operator-block gradients of the GPU
+    both_id = [t for t in oheff.enumerate_tasks(P) if t[3] < 0 and t[4] < 0]
+    _, _, dcoef = ograd.backward(P, x, x, both_id)
+    H = HeffProblem(P)
+    g1 = np.array(g["gamma"])
+    g2 = np.array(g["Gamma"]).reshape(L, L, L, L)
+    for prec, tol in (("f64", 1e-10), ("f32", 2e-5)):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        _, go = H.backward(to_dev(x, dt), to_dev(x, dt), prec, want_psi=False)
+        dh, dv = ograd.integral_gradients(C, P, go.double().cpu().numpy(), dcoef, h.shape)
+        e1 = float(np.abs(dh - g1).max() / np.abs(g1).max())
+        e2 = float(np.abs(dv - 0.5 * g2).max() / np.abs(0.5 * g2).max())
+        say("  %s dE/dh vs gamma %.2e, dE/d(ij|kl) vs Gamma/2 %.2e (max-norm relative)" % (prec, e1, e2))
+        assert e1 <= tol and e2 <= tol

@@ -57,3 +57,30 @@ def test_davidson_restart_small_subspace():
     b, _, ib = H.davidson(x0, tol_res=1e-8)
     say("restart", a, b, ia, ib)
     assert abs(a - b) < 1e-10
+
+
+def test_small_gap_mixed_acceptance():
+    """Random terms without the gapped diagonal: the mixed-precision
+    iteration accepts on the FP64 residual alone, so whatever the inner
+    precision, a converged result has |r64| <= tol_res, its energy obeys the
+    quadratic residual bound with the true gap, and at tol_res = 1e-6 it lies
+    within 1e-8 of the exact lowest eigenvalue."""
+    from paper_2305_05581_amd.tns import HeffProblem
+    P = synthetic_problem(14, 14, 0, 64, 6, 16, 40, seed=8)
+    tasks = oheff.enumerate_tasks(P)
+    op = sla.LinearOperator((P.psi_dim, P.psi_dim), matvec=lambda v: oheff.sigma(P, v, tasks), dtype=np.float64)
+    e1, e2 = sorted(sla.eigsh(op, k=2, which="SA", tol=1e-13)[0])
+    gap = e2 - e1
+    say("exact lowest pair %.12f %.12f gap %.3e" % (e1, e2, gap))
+    H = HeffProblem(P)
+    x0 = to_dev(gaussian_psi(P, 2))
+    for inner in ("f32", "bf16x3"):
+        for tol_res in (1e-6, 1e-3):
+            e, _, info = H.davidson(x0, inner=inner, tol_res=tol_res, tol_e=1e-10)
+            err = abs(e - e1)
+            say(inner, tol_res, "dE %.2e" % err, info)
+            assert info["converged"]
+            assert info["res_norm"] <= tol_res * 1.0001
+            assert err <= info["res_norm"] ** 2 / gap * 1.01 + 1e-12
+            if tol_res <= 1e-6:
+                assert err <= 1e-8

@@ -13,11 +13,11 @@ from synth.problem import mono_id
 from oracle import grad as ograd
 from oracle import heff as oheff
 
-from gpu_common import say, rel, to_dev
+from gpu_common import say, rel, to_dev, SIGMA_TOL
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 2e-4}
+TOL = SIGMA_TOL
 PRECS = ["f64", "f32", "bf16x3"]
 
 

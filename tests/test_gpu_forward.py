@@ -7,11 +7,11 @@ from synth import synthetic_problem, gaussian_psi, molecular_integrals
 from oracle import heff as oheff
 from oracle.blocks import Construction
 
-from gpu_common import say, rel, to_dev
+from gpu_common import say, rel, to_dev, SIGMA_TOL
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-6, "bf16x3": 2e-4}
+TOL = SIGMA_TOL
 
 
 def _instances():

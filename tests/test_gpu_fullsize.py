@@ -1,8 +1,9 @@
-"""Parity at the benchmark's full size (L=54, D=4096, 3000 terms + gapped
-terms, 36 GB of FP64 operators) in the launch configuration bench.py times:
-the oracle recomputes a sample of output sectors one by one (the largest one
-and seeded random ones) and their task records."""
+"""Parity at full size in the launch configuration bench.py times: the
+benchmark workload (L=54, D=4096, 3000 terms + gapped terms, 36 GB of FP64
+operators) and the L=30, D=1024 workload, whole task tables and whole sigma
+against the oracle; the backward and the batched product at full size."""
 import os
+import time
 
 import numpy as np
 import pytest
@@ -11,13 +12,53 @@ import torch
 from synth import synthetic_problem, gaussian_psi
 from oracle import heff as oheff
 
-from gpu_common import say, to_dev
+from gpu_common import say, to_dev, SIGMA_TOL as TOL
 
 pytestmark = pytest.mark.gpu
 
 
+def _upload(P):
+    vals = torch.empty(len(P.op_vals), dtype=torch.float64, device="cuda")
+    for i in range(0, len(P.op_vals), 1 << 28):
+        vals[i:i + (1 << 28)].copy_(torch.from_numpy(P.op_vals[i:i + (1 << 28)]))
+    return vals
+
+
+def _whole_parity(P, H, psi_seed, bars):
+    """Whole task table byte for byte against the oracle's canonical table,
+    then all of sigma in every precision against the oracle's FP64 sigma
+    (relative Frobenius error over the whole vector and the largest
+    per-sector relative error)."""
+    say("oracle task table")
+    ref_tab, ref_ptr = oheff.task_table(P)
+    tasks, ptr = H.tasks()
+    say("tasks device %d oracle %d" % (len(tasks), len(ref_tab)))
+    assert len(tasks) == len(ref_tab) == H.ntasks
+    assert tasks.tobytes() == ref_tab.tobytes()
+    assert np.array_equal(ptr, ref_ptr)
+    psi = gaussian_psi(P, psi_seed)
+    t = time.time()
+    ref, nthr = oheff.sigma_threaded(P, psi, [tuple(x) for x in ref_tab.tolist()])
+    say("oracle sigma: %.1f s on %d threads" % (time.time() - t, nthr))
+    nref = np.linalg.norm(ref)
+    for prec in ("f64", "f32", "bf16x3"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        out = H.apply(to_dev(psi, dt), prec).double().cpu().numpy()
+        err = float(np.linalg.norm(out - ref) / nref)
+        worst = 0.0
+        for s in range(P.nS):
+            a, b = P.psi_off[s], P.psi_off[s + 1]
+            nb = np.linalg.norm(ref[a:b])
+            if nb > 0:
+                worst = max(worst, float(np.linalg.norm(out[a:b] - ref[a:b]) / nb))
+        say("  %s whole-sigma rel err %.3e, worst sector %.3e" % (prec, err, worst))
+        assert err <= bars[prec], (prec, err)
+
+
 @pytest.mark.timeout(900)
-def test_cfg3_sampled_parity():
+def test_cfg3_whole_parity():
+    """The benchmark workload (L=54, D=4096, 3000 terms + gapped terms, seed
+    3): all 356 k task records and all of sigma against the oracle."""
     from paper_2305_05581_amd.tns import HeffProblem
     import bench
     cfg = bench.CONFIGS["d4096"]
@@ -25,45 +66,25 @@ def test_cfg3_sampled_parity():
     P = synthetic_problem(cfg["L"], cfg["N"], cfg["twoSz"], cfg["D"], cfg["mean"], cfg["dmax"], cfg["K"],
                           seed=cfg["seed"], gapped=cfg["gapped"], threads=min(16, os.cpu_count() or 1))
     say("uploading %.1f GB" % (P.op_vals.nbytes / 1e9))
-    vals = torch.empty(len(P.op_vals), dtype=torch.float64, device="cuda")
-    for i in range(0, len(P.op_vals), 1 << 28):
-        vals[i:i + (1 << 28)].copy_(torch.from_numpy(P.op_vals[i:i + (1 << 28)]))
-    H = HeffProblem(P, vals64=vals)
+    H = HeffProblem(P, vals64=_upload(P))
     say("tasks", H.ntasks, "flops", H.total_flops)
-    tasks, ptr = H.tasks()
-    assert ptr[-1] == H.ntasks == len(tasks)
-    cost = np.array([tasks["cost"][ptr[s]:ptr[s + 1]].sum() for s in range(P.nS)])
-    rng = np.random.default_rng(5)
-    big = int(np.argmax(cost))
-    pick = sorted({big} | set(int(s) for s in rng.choice(np.nonzero(cost > 0)[0], 4, replace=False)))
-    say("sample sectors", pick, "GFLOP", cost[pick].sum() / 1e9)
-    ref_tasks = oheff.enumerate_tasks(P, out_filter=set(pick))
-    # task records of the sampled sectors, bit-exact (oracle list is in (term, input) order)
-    want = np.array(sorted(ref_tasks, key=lambda t: t[0]), dtype=oheff.TASK_DTYPE)
-    got = np.concatenate([tasks[ptr[s]:ptr[s + 1]] for s in pick])
-    assert want.tobytes() == got.tobytes()
-    psi = gaussian_psi(P, 3)
-    ref = oheff.sigma_sectors(P, psi, pick, tasks=ref_tasks)
-    full64 = None
-    for prec, tol in (("f64", 1e-12), ("f32", 1e-6), ("bf16x3", 2e-4)):
-        dt = torch.float64 if prec == "f64" else torch.float32
-        y = H.apply(to_dev(psi, dt), prec).double()
-        if full64 is None:
-            full64 = y
-        else:  # all of sigma against the FP64 product (pinned on the sample)
-            whole = float(torch.linalg.norm(y - full64) / torch.linalg.norm(full64))
-            say("  %s whole-sigma rel err against FP64 %.3e" % (prec, whole))
-            assert whole <= tol
-        out = y.cpu().numpy()
-        num = den = 0.0
-        for s in pick:
-            a = out[P.psi_off[s]:P.psi_off[s + 1]]
-            b = ref[s].reshape(-1)
-            num += float(np.sum((a - b) ** 2))
-            den += float(np.sum(b ** 2))
-        err = np.sqrt(num / den)
-        say("  %s sampled rel err %.3e" % (prec, err))
-        assert err <= tol
+    _whole_parity(P, H, 3, TOL)
+
+
+@pytest.mark.timeout(600)
+def test_cfg2_whole_parity():
+    """Plain FP64 workload at L=30, D=1024 (mean sector 32, max 256), 900
+    random terms, seed 2, no gapped terms: all task records and all of sigma
+    in every precision against the oracle."""
+    from paper_2305_05581_amd.tns import HeffProblem
+    import bench
+    cfg = bench.CONFIGS["d1024"]
+    say("generating the D=1024 instance, seed %d" % cfg["seed"])
+    P = synthetic_problem(cfg["L"], cfg["N"], cfg["twoSz"], cfg["D"], cfg["mean"], cfg["dmax"], cfg["K"],
+                          seed=cfg["seed"], gapped=cfg["gapped"], threads=min(16, os.cpu_count() or 1))
+    H = HeffProblem(P)
+    say("tasks", H.ntasks, "flops", H.total_flops)
+    _whole_parity(P, H, 2, TOL)
 
 
 def _block_view(P, vals, b):
@@ -85,8 +106,10 @@ def test_grad1024_sampled_backward():
     P = synthetic_problem(cfg["L"], cfg["N"], cfg["twoSz"], cfg["D"], cfg["mean"], cfg["dmax"], cfg["K"],
                           seed=5, threads=min(16, os.cpu_count() or 1))
     H = HeffProblem(P)
-    tasks, _ = H.tasks()
+    dev_tab, _ = H.tasks()
+    tasks, _ = oheff.task_table(P)
     say("tasks", H.ntasks)
+    assert dev_tab.tobytes() == tasks.tobytes()  # the oracle's records drive the reference below
     rng = np.random.default_rng(7)
     cost_in = np.bincount(tasks["in"], weights=tasks["cost"].astype(np.float64), minlength=P.nS)
     pick_s = {int(np.argmax(cost_in))} | set(int(s) for s in rng.choice(np.nonzero(cost_in > 0)[0], 3, replace=False))
@@ -150,7 +173,7 @@ def test_batch64_generator_sampled_parity():
         assert err <= 1e-12
     # the FP64 product is pinned to the oracle above; the reduced precisions
     # are held to their bars over the whole of sigma against it
-    for prec, tol in (("f32", 1e-6), ("bf16x3", 2e-4)):
+    for prec, tol in (("f32", TOL["f32"]), ("bf16x3", TOL["bf16x3"])):
         outs = B.apply([to_dev(x, torch.float32) for x in xs], prec)
         for i, (y, r) in enumerate(zip(outs, ref64)):
             err = float(torch.linalg.norm(y.double() - r) / torch.linalg.norm(r))
