@@ -159,10 +159,12 @@ size_t tns_apply_workspace_bytes(const tns_tasklist *tl, tns_prec prec);
 
 /* Convert FP64 operator values (device, n elements) into the operand format of
  * `prec`: TNS_F64 copies, TNS_F32 rounds to float (`out` = float[n]),
- * TNS_BF16X3 writes hi = bf16(x) then lo = bf16(x - hi) (round to nearest
- * even each), `out` = uint16[2 n8] with n8 = n rounded up to a multiple of 8:
- * the n hi values at element 0 and the n lo values at element n8 (both halves
- * start 16-byte aligned). */
+ * TNS_BF16X3 writes hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+ * even each), `out` = uint16[2 n8] with n8 = n rounded up to a multiple of 8,
+ * the halves interleaved in groups of 8 elements: element e's hi at u16
+ * index 2e - (e mod 8) and its lo 8 further (8 hi values, then their 8 lo
+ * values), so that 32 consecutive elements of a row (rows start at multiples
+ * of 8) carry both halves in 128 contiguous bytes. */
 tns_status tns_prepare_operands(tns_prec prec, const double *vals64, int64_t n, void *out,
                                 hipStream_t stream);
 

@@ -499,13 +499,13 @@ __global__ void k_zero(T *p, int64_t n) {
   GRID_STRIDE(i, n) p[i] = T(0);
 }
 
-__global__ void k_split_f64(const double *__restrict__ x, int64_t n, uint16_t *__restrict__ hi,
-                            uint16_t *__restrict__ lo) {
+// BF16X3 operands: hi = bf16(x), lo = bf16(x - hi), interleaved (bfx_hi).
+__global__ void k_split_f64(const double *__restrict__ x, int64_t n, uint16_t *__restrict__ out) {
   GRID_STRIDE(i, n) {
     const float v = (float)x[i];
     const uint16_t h = f32_to_bf16_rne(v);
-    hi[i] = h;
-    lo[i] = f32_to_bf16_rne(v - bf16_to_f32(h));
+    out[bfx_hi(i)] = h;
+    out[bfx_hi(i) + 8] = f32_to_bf16_rne(v - bf16_to_f32(h));
   }
 }
 
@@ -680,8 +680,7 @@ extern "C" tns_status tns_prepare_operands(tns_prec prec, const double *vals64, 
   } else if (prec == TNS_F32) {
     hipLaunchKernelGGL(k_f64_to_f32, dim3(nb(n, 256)), dim3(256), 0, st, vals64, n, (float *)out);
   } else if (prec == TNS_BF16X3) {
-    uint16_t *h = (uint16_t *)out;
-    hipLaunchKernelGGL(k_split_f64, dim3(nb(n, 256)), dim3(256), 0, st, vals64, n, h, h + ((n + 7) & ~int64_t(7)));
+    hipLaunchKernelGGL(k_split_f64, dim3(nb(n, 256)), dim3(256), 0, st, vals64, n, (uint16_t *)out);
   } else {
     return TNS_ERR_ARG;
   }

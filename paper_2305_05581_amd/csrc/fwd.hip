@@ -36,12 +36,11 @@ namespace tns {
 
 constexpr int GTH = 256;  // threads per workgroup: 4 waves in a 2 x 2 grid of wave tiles
 
-// Operand: element (i, k) at p[i * ld + k] for i < rows, k < K of the
-// segment.  BF16X3: p is the high half, the low half lies `lo` elements
-// further.  Identity operators are matrices in memory too.
+// Operand: element (i, k) at index i * ld + k for i < rows, k < K of the
+// segment (BF16X3: of the interleaved halves, see bfx_hi).  Identity
+// operators are matrices in memory too.
 struct Mat {
   const void *p;
-  int64_t lo;
   int32_t ld, rows;
 };
 
@@ -68,13 +67,10 @@ struct FwdArgs {
   const int32_t *psi_sec, *dimL, *dimR;
   const int64_t *blk_off;
   const int32_t *blk_ld;
-  const void *ops;  // F64 / F32 values, or BF16 hi[n] then lo at ld8-aligned offset
-  int64_t ops_lo;   // element offset of the low half (BF16X3)
+  const void *ops;  // F64 / F32 values, or BF16X3 halves interleaved (bfx_hi)
   const void *pp, *pt;  // padded psi (m x ld8(n)) and psi^T (n x ld8(m)) per sector
-  int64_t pp_lo, pt_lo;
   const int64_t *pp_off, *pt_off;
   void *T;  // intermediates
-  int64_t T_lo;
   const int64_t *t_off;
   // phase B schedule
   const Item *items;
@@ -85,8 +81,7 @@ struct FwdArgs {
   int32_t *queue;  // [0, 8): phase A queues, [8, 16): phase B queues
   int32_t nq;
   const void *zero;  // 64 zero bytes
-  const void *ident;  // identity matrix maxdim x ld8(maxdim) (BF16X3: hi; lo `ident_lo` further)
-  int64_t ident_lo;
+  const void *ident;  // identity matrix maxdim x ld8(maxdim)
   int32_t ident_ld;
   uint32_t tiles;     // tile table
   // phase-A panels
@@ -137,14 +132,16 @@ __device__ inline int pop_work(const FwdArgs &g) {
 }
 
 // --- the LDS ring: direct global -> LDS loads, NS stages ----------------------------
-// A stage holds the 128 x BK tiles of A and of B (BF16X3: high and low
-// halves) as arrays of eight 1 KB chunks; a chunk (16 rows of 64 bytes = 4
-// 16-byte k-vectors) is the target of one global_load_lds_dwordx4 of a wave.
-// Arrays: BF16X3 [A hi, A lo, B hi, B lo] (BK = 32, 32 KB per stage);
-// FP32 [A, B] (BK = 16) and FP64 [A, B] (BK = 8), 16 KB per stage, so that
-// two workgroups share a CU.  The k-vectors of row r sit at slots
-// kv ^ ((r >> 1) & 3), so that the 16 rows read by one MFMA operand fetch
-// fall into distinct LDS banks.  Loads run NS - 1 stages ahead of the MFMA
+// A stage holds the 128 x BK tiles of A and of B as 1 KB chunks, each the
+// target of one global_load_lds_dwordx4 of a wave.  FP32 [A, B] (BK = 16) and
+// FP64 [A, B] (BK = 8): arrays of 8 chunks of 16 rows x 64 bytes (4 16-byte
+// k-vectors), 16 KB per stage, so that two workgroups share a CU; the
+// k-vectors of row r sit at slots kv ^ ((r >> 1) & 3).  BF16X3 [A, B]
+// (BK = 32): arrays of 16 chunks of 8 rows x 128 bytes, the interleaved high
+// and low halves of 32 k, so that every row of a stage is one whole 128-byte
+// line in memory; vector v of row r sits at slot v ^ (r & 7); 32 KB per
+// stage, one workgroup per CU.  Either way the 16 rows read by one MFMA
+// operand fetch fall into distinct LDS banks.  Loads run NS - 1 stages ahead of the MFMA
 // work; a stage is consumed after a counted vector-memory wait and one
 // barrier (no fence, in-flight stages stay in flight).  Out-of-range rows and
 // whole k-vectors beyond K read the zero region; the library's own operands
@@ -160,7 +157,7 @@ template <> struct RingP<TNS_BF16X3> { static constexpr int VEC = 8; };
 template <> struct RingP<TNS_F32> { static constexpr int VEC = 4; };
 template <> struct RingP<TNS_F64> { static constexpr int VEC = 2; };
 template <int P, int KS> struct RingL {
-  static constexpr int ARR = P == TNS_BF16X3 ? 4 : 2 * KS;  // arrays of 8 chunks
+  static constexpr int ARR = P == TNS_BF16X3 ? 4 : 2 * KS;  // 8 chunks each (BF16X3: A and B of 16)
   static constexpr int CH = 8 * ARR;                        // chunks per stage
   static constexpr int LOADS = CH / 4;                      // global_load_lds per wave and stage
   static constexpr int BK = P == TNS_BF16X3 ? 32 : KS * 4 * RingP<P>::VEC;
@@ -203,6 +200,16 @@ __device__ inline __attribute__((address_space(1))) T *gptr(T *p) {
   return (__attribute__((address_space(1))) T *)p;
 }
 
+// Address of element e of an operand array: BF16X3 arrays interleave the
+// halves (element e's high half at bfx_hi(e), its low half 8 further), so
+// row starts (e a multiple of 8) map to u16 index 2 e.
+template <int P>
+__device__ inline const void *elem_ptr(const void *base, int64_t e) {
+  typedef typename FP<P>::E E;
+  if constexpr (P == TNS_BF16X3) return reinterpret_cast<const uint16_t *>(base) + 2 * e;
+  else return reinterpret_cast<const E *>(base) + e;
+}
+
 __device__ inline void gl_lds(const void *src, void *dst) {
   __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
                                    (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
@@ -224,62 +231,96 @@ __device__ inline void ring_sync() {
 // Waits for every ring load of this wave (before the workgroup exits).
 __device__ inline void ring_drain() { __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8)); }
 
-// Per-lane sources of the four 16-row chunks a wave loads into every stage:
-// q = 0, 1 the A chunks w and w + 4, q = 2, 3 the B chunks w and w + 4 of the
-// 8 in each array.  ptr[q] is the byte address of the lane's row at k = 0
-// (BF16X3: high half; the low half lies lo[q] bytes further), klim[q] the
-// row's K, 0 for a row outside its operand (whose loads then read zeros).
-// Set when a segment or tile starts, so that issuing a stage is branch-free.
-struct LoadSet {
-  const char *ptr[4];
-  int64_t lo[4];
-  int32_t klim[4];
+// Per-lane sources of the chunks a wave loads into every stage, set when a
+// segment or tile starts so that issuing a stage is branch-free.  ptr[q] is
+// the byte address of the lane's row at k = 0, klim[q] the row's K (0 for a
+// row outside its operand, whose loads then read zeros).
+// FP32 / FP64: a chunk is 16 rows x 64 bytes (4 lanes per row); q = 0, 1 the
+// A chunks w and w + 4, q = 2, 3 the B chunks w and w + 4 of the 8 in each
+// array.
+// BF16X3 (high and low halves interleaved in groups of 8 elements, so 32 k of
+// a row are 128 contiguous bytes): a chunk is 8 rows x 128 bytes (8 lanes per
+// row); wave w loads rows [32 w, 32 w + 32) of each operand, q = u (A) and
+// 4 + u (B) the chunk 4 w + u of the 16 in each array, u < 4.
+template <int P> struct LoadSetT {
+  static constexpr int N = P == TNS_BF16X3 ? 8 : 4;
+  const char *ptr[N];
+  int32_t klim[N];
 };
 
-// Rows [r0, r0 + 128) of M into slots q0, q0 + 1 (rows beyond rlim read zeros).
+// Rows [r0, r0 + 128) of M into the slots of one operand (q0 = 0: A, else B;
+// rows beyond rlim read zeros).
 template <int P>
-__device__ __attribute__((always_inline)) inline void ls_mat(LoadSet &ls, int q0, const Mat &M, int r0, int rlim,
+__device__ __attribute__((always_inline)) inline void ls_mat(LoadSetT<P> &ls, int q0, const Mat &M, int r0, int rlim,
                                                              int K) {
   typedef typename FP<P>::E E;
-  const int w = threadIdx.x >> 6, rin = (threadIdx.x & 63) >> 2;
+  const int w = threadIdx.x >> 6;
+  if constexpr (P == TNS_BF16X3) {
+    const int rin = (threadIdx.x & 63) >> 3, base = q0 ? 4 : 0;
 #pragma unroll
-  for (int v = 0; v < 2; ++v) {
-    const int row = r0 + 16 * (w + 4 * v) + rin;
-    ls.ptr[q0 + v] = reinterpret_cast<const char *>(reinterpret_cast<const E *>(M.p) + (int64_t)row * M.ld);
-    ls.lo[q0 + v] = M.lo * (int64_t)sizeof(E);
-    ls.klim[q0 + v] = row < rlim ? K : 0;
+    for (int u = 0; u < 4; ++u) {
+      const int row = r0 + 32 * w + 8 * u + rin;
+      ls.ptr[base + u] = reinterpret_cast<const char *>(M.p) + 4 * ((int64_t)row * M.ld);
+      ls.klim[base + u] = row < rlim ? K : 0;
+    }
+  } else {
+    const int rin = (threadIdx.x & 63) >> 2, base = q0 ? 2 : 0;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int row = r0 + 16 * (w + 4 * v) + rin;
+      ls.ptr[base + v] = reinterpret_cast<const char *>(reinterpret_cast<const E *>(M.p) + (int64_t)row * M.ld);
+      ls.klim[base + v] = row < rlim ? K : 0;
+    }
   }
 }
 
 // Stage <- one K step (k in [k0, k0 + BK)) of the chunks of ls; with live
 // false every load reads the zero region.  Branch-free.
 template <int P, int KS>
-__device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &st, const LoadSet &ls, int k0,
+__device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &st, const LoadSetT<P> &ls, int k0,
                                                                  bool live, const void *zero) {
   typedef typename FP<P>::E E;
   static_assert(KS == 1, "one k-range per stage");
   constexpr int VEC = RingP<P>::VEC, L = RingL<P, KS>::LOADS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int rin = lane >> 2;
-  const int k = k0 + VEC * ((lane & 3) ^ rswz(rin));
   const char *z = reinterpret_cast<const char *>(zero);
+  if constexpr (P == TNS_BF16X3) {
+    // lane: row rin of the chunk, 16-byte slot lane & 7 holding vector
+    // v = slot ^ rin (v = 2 g + h: k-group g, h = 0 high, 1 low half)
+    const int rin = lane >> 3, v = (lane & 7) ^ rin;
+    const int k = k0 + 8 * (v >> 1);
+    const int64_t boff = 4 * (int64_t)k0 + 16 * v;
 #pragma unroll
-  for (int u = 0; u < L; ++u) {
-    const int c = w + 4 * u;  // chunk of the stage; array h = c / 8 = u / 2
-    const int h = u / 2;
-    const bool isB = P == TNS_BF16X3 ? h >= 2 : h >= 1;
-    const bool lo = P == TNS_BF16X3 && (h & 1);
-    const int q = (isB ? 2 : 0) + (u & 1);
-    const bool in = live && k < ls.klim[q];
-    const char *src = ls.ptr[q] + (lo ? ls.lo[q] : 0) + (int64_t)k * (int64_t)sizeof(E);
-    gl_lds(in ? src : z, &st.b[c * 1024]);
+    for (int u = 0; u < L; ++u) {
+      const int c = (u >> 2) * 16 + 4 * w + (u & 3);  // chunk of the stage (A 0..15, B 16..31)
+      const bool in = live && k < ls.klim[u];
+      gl_lds(in ? ls.ptr[u] + boff : z, &st.b[c * 1024]);
+    }
+  } else {
+    const int rin = lane >> 2;
+    const int k = k0 + VEC * ((lane & 3) ^ rswz(rin));
+#pragma unroll
+    for (int u = 0; u < L; ++u) {
+      const int c = w + 4 * u;  // chunk of the stage; array h = c / 8 = u / 2
+      const int q = (u / 2 >= 1 ? 2 : 0) + (u & 1);
+      const bool in = live && k < ls.klim[q];
+      const char *src = ls.ptr[q] + (int64_t)k * (int64_t)sizeof(E);
+      gl_lds(in ? src : z, &st.b[c * 1024]);
+    }
   }
 }
 
-// Byte offset in a stage of 16-byte k-vector kv of row `row` of array arr.
+// Byte offset in a stage of 16-byte k-vector kv of row `row` of array arr
+// (FP32 / FP64 chunks of 16 rows x 64 bytes).
 __device__ inline int ring_off(int arr, int row, int kv) {
   const int rin = row & 15;
   return (8 * arr + (row >> 4)) * 1024 + (rin * 4 + (kv ^ rswz(rin))) * 16;
+}
+// BF16X3: byte offset of vector v (2 g + h) of row `row` of operand arr
+// (chunks of 8 rows x 128 bytes; row r keeps vector v at slot v ^ (r & 7), so
+// the 16 rows of one MFMA operand fetch spread over the banks).
+__device__ inline int ring_off_bf(int arr, int row, int v) {
+  return (16 * arr + (row >> 3)) * 1024 + (row & 7) * 128 + ((v ^ (row & 7)) << 4);
 }
 
 // MFMA fragment of one 16-row tile for lane (l16, g): the 16-byte k-vector of
@@ -294,8 +335,8 @@ __device__ __attribute__((always_inline)) inline Frag<P, KS> ring_frag(const Sta
   Frag<P, KS> f;
   const uint8_t *base = st.b;
   if constexpr (P == TNS_BF16X3) {
-    f.h = *reinterpret_cast<const u16x8 *>(base + ring_off(2 * isB, row0 + l16, g));
-    f.l = *reinterpret_cast<const u16x8 *>(base + ring_off(2 * isB + 1, row0 + l16, g));
+    f.h = *reinterpret_cast<const u16x8 *>(base + ring_off_bf(isB, row0 + l16, 2 * g));
+    f.l = *reinterpret_cast<const u16x8 *>(base + ring_off_bf(isB, row0 + l16, 2 * g + 1));
   } else {
 #pragma unroll
     for (int kh = 0; kh < KS; ++kh)
@@ -473,7 +514,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     for (int j = 0; j < 4; ++j) acc[i][j] = acc2[i][j] = vzero<A4>();
   int seg = it.tb, lj = 0, lK;
   bool ldone = false;  // every segment has lK >= 1
-  LoadSet LS;
+  LoadSetT<P> LS;
   // segment records through scalar loads; the next one is fetched while the
   // current segment streams
   auto fetch = [&](int pos, SegRec &r) {
@@ -488,13 +529,13 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     typedef typename FP<P>::E E;
     Mat LA, LB;
     lK = r.K;
-    LA.p = reinterpret_cast<const E *>(g.T) + r.a_off;
-    LA.lo = g.T_lo; LA.ld = ld8(r.K); LA.rows = r.arows;
+    LA.p = elem_ptr<P>(g.T, r.a_off);
+    LA.ld = ld8(r.K); LA.rows = r.arows;
     if (r.b_off >= 0) {
-      LB.p = reinterpret_cast<const E *>(g.ops) + r.b_off;
-      LB.lo = g.ops_lo; LB.ld = r.bld;
+      LB.p = elem_ptr<P>(g.ops, r.b_off);
+      LB.ld = r.bld;
     } else {  // identity operator block
-      LB.p = g.ident; LB.lo = g.ident_lo; LB.ld = g.ident_ld;
+      LB.p = g.ident; LB.ld = g.ident_ld;
     }
     LB.rows = r.brows;
     ls_mat<P>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
@@ -564,37 +605,38 @@ __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs 
 // right operand (the padded psi sector), and the ring keeps loading across
 // tile boundaries.
 
-// Sources of the two A chunks of this wave (slots 0, 1) in the tile
-// starting at chunk ch, inner dimension K (chunks at or beyond ch_end read
-// zeros).
+// Sources of this wave's A rows in the tile starting at chunk ch, inner
+// dimension K (chunks at or beyond ch_end read zeros).  FP32 / FP64: the 16
+// rows of chunks ch + w and ch + w + 4 (slots 0, 1); BF16X3: rows [32 w,
+// 32 w + 32) of the tile, i.e. rows u & 1 ? 8..15 : 0..7 of chunk
+// ch + 2 w + (u >> 1) for slot u < 4.
 template <int P>
-__device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g, LoadSet &ls, int ch, int ch_end,
+__device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g, LoadSetT<P> &ls, int ch, int ch_end,
                                                                 int K) {
   typedef typename FP<P>::E E;
-  const int w = threadIdx.x >> 6, rin = (threadIdx.x & 63) >> 2;
+  const int w = threadIdx.x >> 6;
+  constexpr bool BF = P == TNS_BF16X3;
+  constexpr int NU = BF ? 4 : 2;
+  const int rin = BF ? (threadIdx.x & 63) >> 3 : (threadIdx.x & 63) >> 2;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int c = __builtin_amdgcn_readfirstlane(ch + w + 4 * u);  // uniform: scalar loads
+  for (int u = 0; u < NU; ++u) {
+    const int c = __builtin_amdgcn_readfirstlane(BF ? ch + 2 * w + (u >> 1) : ch + w + 4 * u);  // uniform: scalar loads
+    const int row = BF ? 8 * (u & 1) + rin : rin;  // row inside the chunk
     ls.ptr[u] = reinterpret_cast<const char *>(g.zero);
-    ls.lo[u] = 0;
     ls.klim[u] = 0;
     if (c < ch_end) {
       const ChunkRec *r = g.recs + c;
       const int64_t off = cld(&r->off);
       const int vr = cld(&r->vrows);
-      const E *p;
-      int ld;
+      int64_t e;  // element index of the lane's row at k = 0
       if (off >= 0) {
-        p = reinterpret_cast<const E *>(g.ops) + off;
-        ld = cld(&r->ld);
-        ls.lo[u] = g.ops_lo * (int64_t)sizeof(E);
+        e = off + (int64_t)row * cld(&r->ld);
+        ls.ptr[u] = reinterpret_cast<const char *>(elem_ptr<P>(g.ops, e));
       } else {  // identity side: rows of the identity matrix
-        p = reinterpret_cast<const E *>(g.ident) + (-1 - off) * g.ident_ld;
-        ld = g.ident_ld;
-        ls.lo[u] = g.ident_lo * (int64_t)sizeof(E);
+        e = (-1 - off + row) * (int64_t)g.ident_ld;
+        ls.ptr[u] = reinterpret_cast<const char *>(elem_ptr<P>(g.ident, e));
       }
-      ls.ptr[u] = reinterpret_cast<const char *>(p + (int64_t)rin * ld);
-      ls.klim[u] = rin < vr ? K : 0;
+      ls.klim[u] = row < vr ? K : 0;
     }
   }
 }
@@ -640,9 +682,11 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
                 const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
                 const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
                                 (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
-                uint16_t *Th = reinterpret_cast<uint16_t *>(g.T);
-                *gptr(reinterpret_cast<uint64_t *>(Th + o)) = __builtin_bit_cast(uint64_t, h);
-                *gptr(reinterpret_cast<uint64_t *>(Th + g.T_lo + o)) = __builtin_bit_cast(uint64_t, l);
+                // four consecutive elements (o a multiple of 4): 8 bytes of
+                // high halves and, 16 bytes further, 8 bytes of low halves
+                uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + bfx_hi(o);
+                *gptr(reinterpret_cast<uint64_t *>(Th)) = __builtin_bit_cast(uint64_t, h);
+                *gptr(reinterpret_cast<uint64_t *>(Th + 8)) = __builtin_bit_cast(uint64_t, l);
               }
             }
           }
@@ -665,18 +709,18 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
   const int K = cls ? n : m, N = cls ? m : n, ldT = ld8(N);
   Mat B;  // B(j, k) = M(k, j): class 0 A_s^T rows, class 1 A_s rows
   if (cls == 0) {
-    B.p = reinterpret_cast<const E *>(g.pt) + cld(&g.pt_off[sec]);
-    B.lo = g.pt_lo; B.ld = ld8(m); B.rows = n;
+    B.p = elem_ptr<P>(g.pt, cld(&g.pt_off[sec]));
+    B.ld = ld8(m); B.rows = n;
   } else {
-    B.p = reinterpret_cast<const E *>(g.pp) + cld(&g.pp_off[sec]);
-    B.lo = g.pp_lo; B.ld = ld8(n); B.rows = m;
+    B.p = elem_ptr<P>(g.pp, cld(&g.pp_off[sec]));
+    B.ld = ld8(n); B.rows = m;
   }
   const int ch_end = it.p0 + it.np;
   const int64_t tbase = cld(&g.a_tb[G]) - cld(&g.a_gch[G]) * PCH * ldT;
   // load cursor: (tile's first chunk, k); compute cursor NS - 1 steps behind
   int lch = it.p0, lk0 = 0, cch = it.p0, ck0 = 0;
   bool ldone = false;
-  LoadSet LS;
+  LoadSetT<P> LS;
   ls_chunks<P>(g, LS, lch, ch_end, K);
   ls_mat<P>(LS, 2, B, it.c0, min(B.rows, it.c0 + 32 * TN), K);
   A4 acc[4][4];
@@ -766,16 +810,16 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
   ring_drain();
 }
 
-// Identity matrix n x ld (BF16X3: high halves, low halves `lo` further).
+// Identity matrix n x ld (BF16X3: halves interleaved, low halves zero).
 template <int P>
-__global__ void k_ident(void *p, int n, int ld, int64_t lo) {
+__global__ void k_ident(void *p, int n, int ld) {
   typedef typename FP<P>::E E;
   E *q = reinterpret_cast<E *>(p);
   GRID_STRIDE(e, (int64_t)n * ld) {
     const int64_t i = e / ld, j = e % ld;
     if constexpr (P == TNS_BF16X3) {
-      q[e] = i == j ? (uint16_t)0x3f80 : (uint16_t)0;
-      q[lo + e] = 0;
+      q[bfx_hi(e)] = i == j ? (uint16_t)0x3f80 : (uint16_t)0;
+      q[bfx_hi(e) + 8] = 0;
     } else {
       q[e] = i == j ? E(1) : E(0);
     }
@@ -784,16 +828,17 @@ __global__ void k_ident(void *p, int n, int ld, int64_t lo) {
 
 // --- padded copies of psi ----------------------------------------------------------
 // Sector s (m x n) to pp (m x ld8(n)) and, transposed, to pt (n x ld8(m));
-// BF16X3 writes high halves and, `lo` elements further, low halves.
+// BF16X3 writes both halves, interleaved (bfx_hi).
 template <class In, int P>
 __device__ inline void pad_sector(int s, const In *__restrict__ psi, const int64_t *psi_off, const int32_t *psi_sec,
                                   const int32_t *dimL, const int32_t *dimR, const int64_t *pp_off,
-                                  const int64_t *pt_off, void *pp, void *pt, int64_t pp_lo, int64_t pt_lo) {
+                                  const int64_t *pt_off, void *pp, void *pt) {
   typedef typename FP<P>::E E;
   const int m = dimL[psi_sec[4 * s]], n = dimR[psi_sec[4 * s + 3]];
   const int lm = ld8(m), ln = ld8(n);
   const In *A = psi + psi_off[s];
-  E *P0 = reinterpret_cast<E *>(pp) + pp_off[s], *P1 = reinterpret_cast<E *>(pt) + pt_off[s];
+  E *P0 = reinterpret_cast<E *>(pp), *P1 = reinterpret_cast<E *>(pt);
+  const int64_t b0 = pp_off[s], b1 = pt_off[s];
   const int64_t step = (int64_t)gridDim.y * blockDim.x, e0 = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
   // padded rows (zeros beyond n), then padded transposed rows (zeros beyond m)
   for (int64_t e = e0; e < (int64_t)m * ln; e += step) {
@@ -801,10 +846,10 @@ __device__ inline void pad_sector(int s, const In *__restrict__ psi, const int64
     if constexpr (P == TNS_BF16X3) {
       const float v = j < n ? (float)A[(int64_t)i * n + j] : 0.f;
       const uint16_t h = f32_to_bf16_rne(v);
-      P0[e] = h;
-      P0[pp_lo + e] = f32_to_bf16_rne(v - bf16_to_f32(h));
+      P0[bfx_hi(b0 + e)] = h;
+      P0[bfx_hi(b0 + e) + 8] = f32_to_bf16_rne(v - bf16_to_f32(h));
     } else {
-      P0[e] = j < n ? (E)A[(int64_t)i * n + j] : E(0);
+      P0[b0 + e] = j < n ? (E)A[(int64_t)i * n + j] : E(0);
     }
   }
   for (int64_t e = e0; e < (int64_t)n * lm; e += step) {
@@ -812,10 +857,10 @@ __device__ inline void pad_sector(int s, const In *__restrict__ psi, const int64
     if constexpr (P == TNS_BF16X3) {
       const float v = i < m ? (float)A[(int64_t)i * n + j] : 0.f;
       const uint16_t h = f32_to_bf16_rne(v);
-      P1[e] = h;
-      P1[pt_lo + e] = f32_to_bf16_rne(v - bf16_to_f32(h));
+      P1[bfx_hi(b1 + e)] = h;
+      P1[bfx_hi(b1 + e) + 8] = f32_to_bf16_rne(v - bf16_to_f32(h));
     } else {
-      P1[e] = i < m ? (E)A[(int64_t)i * n + j] : E(0);
+      P1[b1 + e] = i < m ? (E)A[(int64_t)i * n + j] : E(0);
     }
   }
 }
@@ -823,8 +868,8 @@ __device__ inline void pad_sector(int s, const In *__restrict__ psi, const int64
 template <class In, int P>
 __global__ void k_pad_psi(const In *__restrict__ psi, const int64_t *psi_off, const int32_t *psi_sec,
                           const int32_t *dimL, const int32_t *dimR, const int64_t *pp_off, const int64_t *pt_off,
-                          void *pp, void *pt, int64_t pp_lo, int64_t pt_lo) {
-  pad_sector<In, P>(blockIdx.x, psi, psi_off, psi_sec, dimL, dimR, pp_off, pt_off, pp, pt, pp_lo, pt_lo);
+                          void *pp, void *pt) {
+  pad_sector<In, P>(blockIdx.x, psi, psi_off, psi_sec, dimL, dimR, pp_off, pt_off, pp, pt);
 }
 
 // ============================================================================
@@ -937,8 +982,7 @@ __global__ void k_pad_psi_batch(const InstArgs *tab) {
   const InstArgs &a = tab[blockIdx.z];
   if ((int)blockIdx.x >= a.nS) return;
   pad_sector<In, P>(blockIdx.x, reinterpret_cast<const In *>(a.psi), a.psi_off, a.g.psi_sec, a.g.dimL, a.g.dimR,
-                    a.g.pp_off, a.g.pt_off, const_cast<void *>(a.g.pp), const_cast<void *>(a.g.pt), a.g.pp_lo,
-                    a.g.pt_lo);
+                    a.g.pp_off, a.g.pt_off, const_cast<void *>(a.g.pp), const_cast<void *>(a.g.pt));
 }
 
 // sigma_i (+)= the sum of instance i's partial slots, as k_epilogue_psi.
@@ -975,7 +1019,8 @@ __global__ void k_put_args(PutArgs c, InstArgs *tab) {
 }
 
 // --- host side --------------------------------------------------------------------------
-// BF16X3 halves: the low half of an array of n elements starts at ld8(n).
+// BF16X3 arrays of n elements hold 2 ld8(n) halves (groups of 8 high halves,
+// each followed by its 8 low halves).
 static inline int64_t lo_of(int64_t n) { return (n + 7) & ~int64_t(7); }
 
 // Bytes of an operand array of n elements in a precision (BF16X3: both halves).
@@ -1038,15 +1083,15 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   g.tasks = p.tasks; g.ntasks = p.ntasks;
   g.psi_sec = p.psi_sec; g.dimL = p.dimL; g.dimR = p.dimR;
   g.blk_off = p.blk_off; g.blk_ld = p.blk_ld;
-  g.ops = ops; g.ops_lo = lo_of(p.n_vals);
-  g.pp = pp; g.pt = pt; g.pp_lo = lo_of(p.pp_elems); g.pt_lo = lo_of(p.pt_elems);
+  g.ops = ops;
+  g.pp = pp; g.pt = pt;
   g.pp_off = p.pp_off; g.pt_off = p.pt_off;
-  g.T = T; g.T_lo = lo_of(p.t_elems); g.t_off = p.t_off;
+  g.T = T; g.t_off = p.t_off;
   g.items = S.items; g.nitems = S.nitems; g.idx = S.idx; g.grp_rows = S.grp_rows; g.grp_cols = S.grp_cols;
   g.slot_off = S.slot_off; g.qbase = S.qbase; g.partial = part;
   g.queue = reinterpret_cast<int32_t *>(w); g.nq = S.nq;
   g.zero = w + 64;
-  g.ident = id; g.ident_lo = lo_of(ident_elems(p)); g.ident_ld = ld8(p.maxdim);
+  g.ident = id; g.ident_ld = ld8(p.maxdim);
   g.tiles = p.tiles;
   g.a_items = p.pa.items; g.a_qbase = p.pa.qbase; g.a_tb = p.pa.tb; g.a_gch = p.pa.gch;
   g.a_ch = p.pa.ch; g.a_idx = p.pa.idx;
@@ -1062,11 +1107,10 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   const FwdArgs g = fwd_args<P>(p, ops, w);
   hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, g.queue);
   hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, const_cast<void *>(g.ident),
-                     p.maxdim, ld8(p.maxdim), g.ident_lo);
+                     p.maxdim, ld8(p.maxdim));
   if (p.nS > 0)
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
-                       p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt), g.pp_lo,
-                       g.pt_lo);
+                       p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt));
   if (p.ntasks > 0) hipLaunchKernelGGL(k_chunk_recs, dim3(nblocks(p.ntasks)), dim3(256), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
@@ -1132,7 +1176,7 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
     a.g = fwd_args<P>(p, ops[i], region_of[i]);
     a.g.queue = queue;
     a.g.zero = w + 64;
-    a.g.ident = ident; a.g.ident_lo = lo_of(id_elems); a.g.ident_ld = ld8(md);
+    a.g.ident = ident; a.g.ident_ld = ld8(md);
     a.psi = psi[i]; a.sigma = sigma[i];
     a.psi_off = p.psi_off; a.grp_chunk_base = p.fwd.grp_chunk_base;
     a.psi_dim = p.psi_dim; a.nS = p.nS; a.beta = beta;
@@ -1156,7 +1200,7 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
     hipLaunchKernelGGL(k_put_args, dim3(1), dim3(64), 0, st, pa, tab);
   }
   hipLaunchKernelGGL(k_batch_cum, dim3(1), dim3(2 * NQ_MAX), 0, st, b);
-  hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(id_elems)), dim3(256), 0, st, ident, md, ld8(md), lo_of(id_elems));
+  hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(id_elems)), dim3(256), 0, st, ident, md, ld8(md));
   typedef typename std::conditional<P == TNS_F64, double, float>::type In;
   hipLaunchKernelGGL((k_pad_psi_batch<In, P>), dim3(max_nS, 8, n), dim3(256), 0, st, tab);
   hipLaunchKernelGGL(k_chunk_recs_batch, dim3(64, n), dim3(256), 0, st, tab);

@@ -33,6 +33,13 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
   return x;
 }
 
+// BF16X3 operand arrays keep each element as a high and a low BF16 half,
+// interleaved in groups of 8 elements: the 8 high halves of a group, then its
+// 8 low halves.  Element e's high half sits at u16 index bfx_hi(e), its low
+// half 8 further; an aligned run of 32 elements (a row step of the ring) is
+// 128 contiguous bytes.
+__host__ __device__ inline int64_t bfx_hi(int64_t e) { return 2 * e - (e & 7); }
+
 // --- MFMA wrappers ------------------------------------------------------------
 // 16 x 16 output tile; lane l supplies A[l % 16][k-slot l / 16] and
 // B[k-slot l / 16][l % 16].  Element v (0..3) of lane l's accumulator is

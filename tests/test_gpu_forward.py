@@ -92,3 +92,20 @@ def test_invalid_problem_rejected():
     P.op_dN[0] += 2  # blocks no longer at the operator's shift
     with pytest.raises(ValueError):
         HeffProblem(P)
+
+
+def test_bf16x3_operand_layout(built):
+    """tns_prepare_operands(BF16X3): element e's high half at u16 index
+    2e - (e mod 8), its low half 8 further; hi = bf16(x), lo = bf16(x - hi)
+    rounded to nearest even, so hi + lo is within 2^-16 |x| of float(x)."""
+    P, H, _, _ = built["ragged"]
+    ops = H.operands("bf16x3").cpu().numpy().view(np.uint16)
+    n = H.vals64.numel()
+    e = np.arange(n)
+    hi = ops[2 * e - (e % 8)].astype(np.uint32) << 16
+    lo = ops[2 * e - (e % 8) + 8].astype(np.uint32) << 16
+    x = P.op_vals.astype(np.float32)
+    rec = hi.view(np.float32).astype(np.float64) + lo.view(np.float32).astype(np.float64)
+    assert np.all(np.abs(rec - x) <= 2.0 ** -16 * np.abs(x) + 1e-45)
+    # the high half is float(x) rounded to 8 significant bits
+    assert np.all(np.abs(hi.view(np.float32) - x) <= 2.0 ** -8 * np.abs(x))
