@@ -293,6 +293,109 @@ tns_status tns_davidson(const tns_tasklist *tl, const tns_davidson_opts *opts, c
                         const double *op_vals_f64, double *psi_inout, double *energy,
                         tns_davidson_info *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Renormalisation (blocking) of block operators (Section IV.D): after a
+ * two-site step the block grows by one site and every operator built on it is
+ * carried over to the truncated basis of the enlarged block,
+ *   O~_nu = U^T ( sum over nu's terms of coef (O (x) m) ) U,
+ * each new operator nu an output of its own (no sum over operators).
+ * Enlarged sector Q = q(i) + q(s) (old sector i, site state s); its product
+ * basis lists the components (i, s) in ascending order, dim(i) states each;
+ * the product state is C_l C_s |0>, so a site factor m picks up
+ * (-1)^(parity(m) N(i)) from the old block's creators.  U_Q (full(Q) x
+ * keep(Q), row-major, orthonormal columns expected but not checked) spans the
+ * kept states.  The step runs as the chained products of Eq. (2) with the old
+ * block in the middle and transposed isometry slices outside, on the forward
+ * product's grouped GEMM phases.  All pointers of the problem are HOST
+ * pointers read during tns_renorm_build. */
+typedef struct {
+  int32_t nL;                /* sectors of the block before the step            */
+  const int32_t *qL;         /* [nL][2] (N, 2Sz) ascending                       */
+  const int32_t *dimL;       /* [nL] 1..32768                                    */
+  int32_t nOps, nBlk;        /* its operators and their blocks, as in tns_problem */
+  const int32_t *op_dN, *op_d2Sz;
+  const int32_t *blk_op, *blk_in, *blk_out, *blk_rows, *blk_cols, *blk_ld;
+  const int64_t *blk_off;
+  int64_t n_vals;
+  int32_t nQ;                /* sectors of the enlarged block                    */
+  const int32_t *qQ;         /* [nQ][2] ascending: exactly the sums qL[i] + q(s)  */
+  const int32_t *keep;       /* [nQ] kept states, 1 .. full(Q)                    */
+  const int64_t *u_off;      /* [nQ] element offset of U_Q in the isometry array  */
+  int64_t n_u;               /* elements of the isometry array                   */
+  int32_t nNew, nTerms;      /* new operators; terms new op += coef (O_op (x) m)  */
+  const int32_t *term_new;   /* [nTerms] 0..nNew-1                                */
+  const int32_t *term_op;    /* [nTerms] old operator or -1 (identity)            */
+  const int32_t *term_mono;  /* [nTerms] site monomial 0..15                      */
+  const double *term_coef;   /* [nTerms]                                          */
+} tns_renorm_problem;
+
+/* A built renormalisation step: the task table of its chained products (tl,
+ * views into the build workspace; its output sectors are the new blocks) and
+ * the output layout.  Output block k of new operator blk_new[k] maps enlarged
+ * sector blk_in[k] to blk_out[k] = blk_in[k] + shift(new op): keep(out) rows,
+ * keep(in) columns, leading dimension ld8(columns), at element offset off[k]
+ * of out_vals (tns_renorm_out_table). */
+typedef struct {
+  int64_t ntasks, n_out_blk, out_elems, total_flops;
+  tns_tasklist tl;
+  uint8_t opaque[1024];
+} tns_renorm_plan;
+
+/* Build workspace bytes (host only; 0 when the problem fails validation:
+ * shapes, ranges, quantum numbers of every block, the enlarged sector list,
+ * one shift per new operator). */
+size_t tns_renorm_workspace_bytes(const tns_renorm_problem *prob);
+/* Validates, lists the tasks on the host (in term, block, site-state order),
+ * copies the tables into `ws` and builds the schedules on the device;
+ * synchronises the stream.  `ws` must stay untouched while the plan is used. */
+tns_status tns_renorm_build(const tns_renorm_problem *prob, void *ws, size_t ws_bytes, tns_renorm_plan *out,
+                            hipStream_t stream);
+/* Host copies of the output block table (arrays of n_out_blk entries). */
+tns_status tns_renorm_out_table(const tns_renorm_plan *plan, int32_t *blk_new, int32_t *blk_in, int32_t *blk_out,
+                                int32_t *rows, int32_t *cols, int32_t *ld, int64_t *off);
+/* One renormalisation step: op_vals (device, FP64, the old blocks' values at
+ * blk_off), u_vals (device, FP64 isometries at u_off) -> out_vals (device,
+ * out_elems of double for TNS_F64, float otherwise; padding zero).  The
+ * products run in `prec` (operands converted on the device on every call).
+ * Asynchronous on `stream`; deterministic. */
+size_t tns_renorm_apply_workspace_bytes(const tns_renorm_plan *plan, tns_prec prec);
+tns_status tns_renormalize(const tns_renorm_plan *plan, tns_prec prec, const double *op_vals, const double *u_vals,
+                           void *out_vals, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Out-of-HBM products (Section II.B, Alg. 1: tree-traversal cache).  The
+ * operator values stay in host memory (pinned for asynchronous copies) and
+ * stream through a device cache of cache_elems elements managed as a stack:
+ * the terms form a data dependency tree (left operator, then right operator,
+ * then the terms), a depth-first walk loads an operator onto the stack on
+ * entering its node and pops it on leaving, so a left operator stays resident
+ * for all of its right partners and allocating is moving an offset.  The terms
+ * pending when the stack is full or a left subtree ends form an epoch, run as
+ * one product accumulating into sigma (its task list built at plan time with
+ * the blocks' cache offsets).  Each operator's blocks are loaded as the element
+ * range from its first to the end of its last block.
+ * tns_ttcache_sizes: host and device bytes of the plan (host only: the walk,
+ * the epochs' problems and their validation); TNS_ERR_WORKSPACE when a left
+ * and a right operator together exceed the cache.  tns_ttcache_build: builds
+ * every epoch's task list into dev_ws (synchronises the stream); host_buf and
+ * dev_ws must outlive the plan.  tns_apply_heff_streamed: sigma := H_eff psi
+ * (FP64 or FP32; host_vals in that type, the problem's value layout), one
+ * copy per load and one product per epoch, in order on `stream`.  The sum over
+ * epochs runs in a fixed order (deterministic); it differs from
+ * tns_apply_heff's order only by the grouping of terms. */
+typedef struct {
+  int64_t n_epochs, n_loads;
+  int64_t loaded_elems;  /* operator elements copied per product                    */
+  int64_t naive_elems;   /* elements a per-term load of both operators would copy   */
+  int64_t ntasks, total_flops, cache_elems;
+  uint8_t opaque[256];
+} tns_ttcache_plan;
+tns_status tns_ttcache_sizes(const tns_problem *prob, int64_t cache_elems, size_t *host_bytes, size_t *dev_bytes,
+                             int64_t *n_epochs);
+tns_status tns_ttcache_build(const tns_problem *prob, int64_t cache_elems, void *host_buf, size_t host_bytes,
+                             void *dev_ws, size_t dev_bytes, tns_ttcache_plan *out, hipStream_t stream);
+size_t tns_ttcache_apply_workspace_bytes(const tns_ttcache_plan *plan, tns_prec prec);
+tns_status tns_apply_heff_streamed(const tns_ttcache_plan *plan, tns_prec prec, const void *host_vals, void *cache,
+                                   const void *psi, void *sigma, void *ws, size_t ws_bytes, hipStream_t stream);
+
 const char *tns_status_string(tns_status s);
 
 /* Profiling aid: when all three events are non-null, the next forward

@@ -749,7 +749,7 @@ extern "C" void tns_profile_events(hipEvent_t before, hipEvent_t mid, hipEvent_t
 }
 
 extern "C" size_t tns_backward_workspace_bytes(const tns_tasklist *tl, tns_prec prec) {
-  if (!tl || (prec != TNS_F64 && prec != TNS_F32)) return 0;
+  if (!tl || (prec != TNS_F64 && prec != TNS_F32) || plan_of(tl).no_backward) return 0;
   return bwd_workspace(plan_of(tl), prec);
 }
 
@@ -759,6 +759,7 @@ extern "C" tns_status tns_apply_heff_backward(const tns_tasklist *tl, tns_prec p
   if (!tl || !op_vals || !psi || !grad_sigma || !ws) return TNS_ERR_ARG;
   if (prec != TNS_F64 && prec != TNS_F32) return TNS_ERR_ARG;
   const Plan &p = plan_of(tl);
+  if (p.no_backward) return TNS_ERR_ARG;
   if (ws_bytes < bwd_workspace(p, prec)) return TNS_ERR_WORKSPACE;
   if (!grad_psi && !grad_ops) return TNS_OK;
   if (prec == TNS_F64) return backward_impl<TNS_F64>(p, op_vals, psi, grad_sigma, grad_psi, grad_ops, ws, st);

@@ -19,8 +19,10 @@
 // inner dimension of the second GEMM.
 //
 // Both phases compute tiles C(i, j) = sum over segments of sum_k A(i, k) B(j, k)
-// with every operand k-contiguous (rows of L, R, T, of the identity and of the
-// padded copies of A and A^T).  Tiles are 32, 64 or 128 rows / columns per the
+// with every operand k-contiguous (rows of L, R, T and of the padded copies of
+// A and A^T).  Identity factors are never multiplied: an identity X makes T a
+// scaled copy of the padded input sector (k_ident_T), an identity Y adds T
+// into the phase-B accumulators directly.  Tiles are 32, 64 or 128 rows / columns per the
 // tile table of the task list (per sector-size bucket), the last tile along a
 // dimension 32, 64, 96 or 128 to fit what remains.  Operands stream from
 // global memory straight into a 4-stage LDS ring (16-byte direct loads), the
@@ -81,8 +83,6 @@ struct FwdArgs {
   int32_t *queue;  // [0, 8): phase A queues, [8, 16): phase B queues
   int32_t nq;
   const void *zero;  // 64 zero bytes
-  const void *ident;  // identity matrix maxdim x ld8(maxdim)
-  int32_t ident_ld;
   uint32_t tiles;     // tile table
   // phase-A panels
   const Item *a_items;
@@ -145,8 +145,8 @@ __device__ inline int pop_work(const FwdArgs &g) {
 // work; a stage is consumed after a counted vector-memory wait and one
 // barrier (no fence, in-flight stages stay in flight).  Out-of-range rows and
 // whole k-vectors beyond K read the zero region; the library's own operands
-// (T, padded psi, the identity) hold zeros beyond K, so the k-tail of an
-// operator row always meets zeros.
+// (T, padded psi) hold zeros beyond K, so the k-tail of an operator row
+// always meets zeros.
 typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
 
 // KS: k-halves per stage of FP32 / FP64 (each half 4 k-vectors of 16 bytes
@@ -512,8 +512,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = acc2[i][j] = vzero<A4>();
-  int seg = it.tb, lj = 0, lK;
-  bool ldone = false;  // every segment has lK >= 1
+  int lj = 0, lK = 0;
   LoadSetT<P> LS;
   // segment records through scalar loads; the next one is fetched while the
   // current segment streams
@@ -522,26 +521,68 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     r.a_off = cld(&q->a_off); r.b_off = cld(&q->b_off);
     r.K = cld(&q->K); r.arows = cld(&q->arows); r.brows = cld(&q->brows); r.bld = cld(&q->bld);
   };
-  SegRec cur, nxt;
-  fetch(seg, cur);
-  if (seg + 1 < it.te) fetch(seg + 1, nxt);
+  // Identity second factors (b_off < 0) contribute their intermediate T as
+  // it stands: added into the accumulators here, element by element, and
+  // left out of the operand stream.  Only items flagged at build time hold any.
+  const bool idy = (it.mode & ITEM_IDENT_Y) != 0;
+  if (idy) {
+    for (int sp = it.tb; sp < it.te; ++sp) {
+      SegRec r;
+      fetch(sp, r);
+      if (r.b_off >= 0) continue;
+      const int ldT = ld8(r.K);  // T: arows x K, K = the output's columns
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int col = it.c0 + wn * 16 * TN + j * 16 + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
+            if (row < r.arows && col < r.K) {
+              const int64_t e = r.a_off + (int64_t)row * ldT + col;
+              if constexpr (P == TNS_BF16X3) {
+                const uint16_t *Tu = reinterpret_cast<const uint16_t *>(g.T) + bfx_hi(e);
+                acc[i][j][v] += bf16_to_f32(Tu[0]) + bf16_to_f32(Tu[8]);
+              } else {
+                acc[i][j][v] += reinterpret_cast<const typename FP<P>::E *>(g.T)[e];
+              }
+            }
+          }
+        }
+    }
+  }
+  // next segment with a product at or after pos
+  auto live_from = [&](int pos) {
+    if (idy)
+      while (pos < it.te && cld(&g.segb[pos].b_off) < 0) ++pos;
+    return pos;
+  };
+  int seg = live_from(it.tb), nseg = it.te;
+  bool ldone = seg >= it.te;  // every segment has lK >= 1
   auto load_seg = [&](const SegRec &r) {
-    typedef typename FP<P>::E E;
     Mat LA, LB;
     lK = r.K;
     LA.p = elem_ptr<P>(g.T, r.a_off);
     LA.ld = ld8(r.K); LA.rows = r.arows;
-    if (r.b_off >= 0) {
-      LB.p = elem_ptr<P>(g.ops, r.b_off);
-      LB.ld = r.bld;
-    } else {  // identity operator block
-      LB.p = g.ident; LB.ld = g.ident_ld;
-    }
-    LB.rows = r.brows;
+    LB.p = elem_ptr<P>(g.ops, r.b_off);
+    LB.ld = r.bld; LB.rows = r.brows;
     ls_mat<P>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
     ls_mat<P>(LS, 2, LB, it.c0, min(LB.rows, it.c0 + 32 * TN), lK);
   };
-  load_seg(cur);
+  SegRec nxt;
+  if (!ldone) {
+    SegRec cur;
+    fetch(seg, cur);
+    nseg = live_from(seg + 1);
+    if (nseg < it.te) fetch(nseg, nxt);
+    load_seg(cur);
+  } else {  // no products: the ring runs on the zero region only
+    Mat Z;
+    Z.p = g.zero; Z.ld = 0; Z.rows = 0;
+    ls_mat<P>(LS, 0, Z, 0, 0, 0);
+    ls_mat<P>(LS, 2, Z, 0, 0, 0);
+  }
   typedef Frags<P, KS, TM, TN> FR;
   ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR>(
       rg, [&](Stage<P, KS> &st) { ring_issue<P, KS>(st, LS, lj * BK, !ldone, g.zero); },
@@ -549,9 +590,11 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
         if (ldone) return 0;
         if (++lj * BK >= lK) {
           lj = 0;
-          if (++seg < it.te) {
+          seg = nseg;
+          if (seg < it.te) {
             load_seg(nxt);
-            if (seg + 1 < it.te) fetch(seg + 1, nxt);
+            nseg = live_from(seg + 1);
+            if (nseg < it.te) fetch(nseg, nxt);
           } else {
             ldone = true;
           }
@@ -628,14 +671,9 @@ __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g
       const ChunkRec *r = g.recs + c;
       const int64_t off = cld(&r->off);
       const int vr = cld(&r->vrows);
-      int64_t e;  // element index of the lane's row at k = 0
-      if (off >= 0) {
-        e = off + (int64_t)row * cld(&r->ld);
-        ls.ptr[u] = reinterpret_cast<const char *>(elem_ptr<P>(g.ops, e));
-      } else {  // identity side: rows of the identity matrix
-        e = (-1 - off + row) * (int64_t)g.ident_ld;
-        ls.ptr[u] = reinterpret_cast<const char *>(elem_ptr<P>(g.ident, e));
-      }
+      // element index of the lane's row at k = 0
+      const int64_t e = off + (int64_t)row * cld(&r->ld);
+      ls.ptr[u] = reinterpret_cast<const char *>(elem_ptr<P>(g.ops, e));
       ls.klim[u] = row < vr ? K : 0;
     }
   }
@@ -764,15 +802,16 @@ __device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs 
 __device__ inline void chunk_recs_of(const FwdArgs &g, int64_t i) {
   const int t = g.a_idx[i];
   const tns_task &k = g.tasks[t];
+  if (ident_x(k)) return;  // no chunks: its intermediate is a scaled copy (k_ident_T)
   const int *so = g.psi_sec + 4 * k.out;
   const int rows = k.order == 0 ? g.dimL[so[0]] : g.dimR[so[3]];
   const int blk = k.order == 0 ? k.lblk : k.rblk;
   ChunkRec *r = const_cast<ChunkRec *>(g.recs) + g.a_ch[i];
-  const int64_t bo = blk >= 0 ? g.blk_off[blk] : 0;
-  const int ld = blk >= 0 ? g.blk_ld[blk] : 0;
+  const int64_t bo = g.blk_off[blk];
+  const int ld = g.blk_ld[blk];
   for (int j = 0; j * PCH < rows; ++j) {
     ChunkRec x;
-    x.off = blk >= 0 ? bo + (int64_t)j * PCH * ld : -1 - (int64_t)j * PCH;
+    x.off = bo + (int64_t)j * PCH * ld;
     x.ld = ld;
     x.vrows = min(PCH, rows - j * PCH);
     x.alpha = k.alpha;
@@ -810,20 +849,39 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
   ring_drain();
 }
 
-// Identity matrix n x ld (BF16X3: halves interleaved, low halves zero).
+// Intermediates of the tasks whose first factor is the identity: T = alpha M
+// with M the padded input sector (class 0: psi_s, m x ld8(n); class 1: its
+// transpose, n x ld8(m)), which has T's shape and leading dimension, so T is
+// a scaled copy of it, zero columns included.  One workgroup per task in turn.
 template <int P>
-__global__ void k_ident(void *p, int n, int ld) {
+__device__ inline void ident_t_of(const FwdArgs &g, int t) {
   typedef typename FP<P>::E E;
-  E *q = reinterpret_cast<E *>(p);
-  GRID_STRIDE(e, (int64_t)n * ld) {
-    const int64_t i = e / ld, j = e % ld;
+  const tns_task k = g.tasks[t];
+  if (!ident_x(k)) return;
+  const int m = g.dimL[g.psi_sec[4 * k.in]], n = g.dimR[g.psi_sec[4 * k.in + 3]];
+  const int64_t cnt = k.order == 0 ? (int64_t)m * ld8(n) : (int64_t)n * ld8(m);
+  const int64_t src = k.order == 0 ? g.pp_off[k.in] : g.pt_off[k.in];
+  const E *S = reinterpret_cast<const E *>(k.order == 0 ? g.pp : g.pt);
+  E *D = reinterpret_cast<E *>(g.T);
+  const int64_t dst = g.t_off[t];
+  for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
     if constexpr (P == TNS_BF16X3) {
-      q[bfx_hi(e)] = i == j ? (uint16_t)0x3f80 : (uint16_t)0;
-      q[bfx_hi(e) + 8] = 0;
+      const int64_t a = bfx_hi(src + e), b = bfx_hi(dst + e);
+      const float x = (float)k.alpha * (bf16_to_f32(S[a]) + bf16_to_f32(S[a + 8]));
+      const uint16_t h = f32_to_bf16_rne(x);
+      D[b] = h;
+      D[b + 8] = f32_to_bf16_rne(x - bf16_to_f32(h));
+    } else if constexpr (P == TNS_F32) {
+      D[dst + e] = (float)k.alpha * S[src + e];
     } else {
-      q[e] = i == j ? E(1) : E(0);
+      D[dst + e] = k.alpha * S[src + e];
     }
   }
+}
+
+template <int P>
+__global__ void k_ident_T(FwdArgs g) {
+  for (int64_t t = blockIdx.x; t < g.ntasks; t += gridDim.x) ident_t_of<P>(g, (int)t);
 }
 
 // --- padded copies of psi ----------------------------------------------------------
@@ -977,6 +1035,12 @@ __global__ void k_chunk_recs_batch(const InstArgs *tab) {
     chunk_recs_of(g, i);
 }
 
+template <int P>
+__global__ void k_ident_T_batch(const InstArgs *tab) {
+  const FwdArgs &g = tab[blockIdx.y].g;
+  for (int64_t t = blockIdx.x; t < g.ntasks; t += gridDim.x) ident_t_of<P>(g, (int)t);
+}
+
 template <class In, int P>
 __global__ void k_pad_psi_batch(const InstArgs *tab) {
   const InstArgs &a = tab[blockIdx.z];
@@ -1030,16 +1094,12 @@ static size_t region(int64_t n, tns_prec p) {
   return align_up(b + 64, 256);
 }
 
-// Identity matrix operand (blocks of identity operators): maxdim x ld8(maxdim).
-static int64_t ident_elems(const Plan &p) { return (int64_t)p.maxdim * ld8(p.maxdim); }
-
 // Workspace of the forward product: [queue counters, zero bytes | partial
-// slots | T | padded psi | padded psi^T | identity | chunk sources].
+// slots | T | padded psi | padded psi^T | chunk sources].
 static size_t recs_bytes(const Plan &p) { return align_up((size_t)std::max<int64_t>(p.pa.nchunks, 1) * sizeof(ChunkRec), 256); }
 size_t fwd_workspace(const Plan &p, tns_prec prec) {
   return 256 + align_up((size_t)std::max<int64_t>(p.fwd.partial_elems, 1) * (prec == TNS_F64 ? 8 : 4), 256) +
-         region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec) +
-         region(ident_elems(p), prec) + recs_bytes(p);
+         region(p.t_elems, prec) + region(p.pp_elems, prec) + region(p.pt_elems, prec) + recs_bytes(p);
 }
 
 // queue counters (bytes 0..63) and the 64-byte zero region that out-of-range
@@ -1075,8 +1135,6 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   c += region(p.pp_elems, prec);
   void *pt = c;
   c += region(p.pt_elems, prec);
-  void *id = c;
-  c += region(ident_elems(p), prec);
   void *recs = c;
   FwdArgs g;
   memset(&g, 0, sizeof(g));
@@ -1091,7 +1149,6 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   g.slot_off = S.slot_off; g.qbase = S.qbase; g.partial = part;
   g.queue = reinterpret_cast<int32_t *>(w); g.nq = S.nq;
   g.zero = w + 64;
-  g.ident = id; g.ident_ld = ld8(p.maxdim);
   g.tiles = p.tiles;
   g.a_items = p.pa.items; g.a_qbase = p.pa.qbase; g.a_tb = p.pa.tb; g.a_gch = p.pa.gch;
   g.a_ch = p.pa.ch; g.a_idx = p.pa.idx;
@@ -1106,12 +1163,13 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   const Sched &S = p.fwd;
   const FwdArgs g = fwd_args<P>(p, ops, w);
   hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, g.queue);
-  hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(ident_elems(p))), dim3(256), 0, st, const_cast<void *>(g.ident),
-                     p.maxdim, ld8(p.maxdim));
   if (p.nS > 0)
     hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
                        p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt));
-  if (p.ntasks > 0) hipLaunchKernelGGL(k_chunk_recs, dim3(nblocks(p.ntasks)), dim3(256), 0, st, g);
+  if (p.ntasks > 0) {
+    hipLaunchKernelGGL(k_chunk_recs, dim3(nblocks(p.ntasks)), dim3(256), 0, st, g);
+    hipLaunchKernelGGL(k_ident_T<P>, dim3((unsigned)std::min<int64_t>(p.ntasks, 4096)), dim3(256), 0, st, g);
+  }
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
@@ -1122,18 +1180,10 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
 }
 
 // --- batched products -------------------------------------------------------------------
-static int max_maxdim(const tns_tasklist *const *tls, int n) {
-  int md = 1;
-  for (int i = 0; i < n; ++i) md = std::max(md, plan_of(tls[i]).maxdim);
-  return md;
-}
-
-// [queue counters, zero bytes | argument table | prefix sums | shared
-// identity | one forward workspace per instance]
+// [queue counters, zero bytes | argument table | prefix sums | one forward
+// workspace per instance]
 static size_t batch_bytes(const tns_tasklist *const *tls, int n, tns_prec prec) {
   size_t b = 256 + align_up((size_t)n * sizeof(InstArgs), 256) + align_up((size_t)2 * NQ_MAX * (n + 1) * 8, 256);
-  const int md = max_maxdim(tls, n);
-  b += region((int64_t)md * ld8(md), prec);
   for (int i = 0; i < n; ++i) b += fwd_workspace(plan_of(tls[i]), prec);
   return b;
 }
@@ -1150,10 +1200,6 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
   c += align_up((size_t)n * sizeof(InstArgs), 256);
   int64_t *cum = reinterpret_cast<int64_t *>(c);
   c += align_up((size_t)2 * NQ_MAX * (n + 1) * 8, 256);
-  const int md = max_maxdim(tls, n);
-  const int64_t id_elems = (int64_t)md * ld8(md);
-  void *ident = c;
-  c += region(id_elems, prec);
   // instances by descending cost: the big ones start first, the small ones fill the tail
   std::vector<int> perm(n);
   for (int i = 0; i < n; ++i) perm[i] = i;
@@ -1176,7 +1222,6 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
     a.g = fwd_args<P>(p, ops[i], region_of[i]);
     a.g.queue = queue;
     a.g.zero = w + 64;
-    a.g.ident = ident; a.g.ident_ld = ld8(md);
     a.psi = psi[i]; a.sigma = sigma[i];
     a.psi_off = p.psi_off; a.grp_chunk_base = p.fwd.grp_chunk_base;
     a.psi_dim = p.psi_dim; a.nS = p.nS; a.beta = beta;
@@ -1200,10 +1245,10 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
     hipLaunchKernelGGL(k_put_args, dim3(1), dim3(64), 0, st, pa, tab);
   }
   hipLaunchKernelGGL(k_batch_cum, dim3(1), dim3(2 * NQ_MAX), 0, st, b);
-  hipLaunchKernelGGL(k_ident<P>, dim3(nblocks(id_elems)), dim3(256), 0, st, ident, md, ld8(md));
   typedef typename std::conditional<P == TNS_F64, double, float>::type In;
   hipLaunchKernelGGL((k_pad_psi_batch<In, P>), dim3(max_nS, 8, n), dim3(256), 0, st, tab);
   hipLaunchKernelGGL(k_chunk_recs_batch, dim3(64, n), dim3(256), 0, st, tab);
+  hipLaunchKernelGGL(k_ident_T_batch<P>, dim3(64, n), dim3(256), 0, st, tab);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (any_tasks)
     hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);

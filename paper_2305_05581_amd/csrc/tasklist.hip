@@ -267,18 +267,21 @@ __global__ void k_chunks(Plan p, Sched S) {
     const int b = S.grp_begin[g], mode = S.grp_mode[g];
     int64_t cur = 0;
     int start = b;
+    bool idy = false;
     const int64_t cb = FILL ? S.grp_chunk_base[g] : 0;
     for (int i = b; i < b + n; ++i) {
       const int64_t c = mode_cost(p, p.tasks[S.idx[i]], mode);
       if (i > start && cur + c > cap) {
-        if (FILL) { Chunk ch{g, start, i, 0, cur, 0, 0}; S.chunks[cb + nc] = ch; }
+        if (FILL) { Chunk ch{g, start, i, 0, cur, 0, idy ? CHUNK_IDENT_Y : 0}; S.chunks[cb + nc] = ch; }
         ++nc;
         start = i;
         cur = 0;
+        idy = false;
       }
       cur += c;
+      if (FILL && mode <= M_FWD1) idy |= ident_y(p.tasks[S.idx[i]]);
     }
-    if (FILL) { Chunk ch{g, start, b + n, 0, cur, 0, 0}; S.chunks[cb + nc] = ch; }
+    if (FILL) { Chunk ch{g, start, b + n, 0, cur, 0, idy ? CHUNK_IDENT_Y : 0}; S.chunks[cb + nc] = ch; }
     ++nc;
   }
   if (!FILL) S.scratch[g] = nc;
@@ -314,7 +317,8 @@ __global__ void k_items(Sched S) {
     it.c0 = (k % ncol) * tc;
     it.nc = min(tc, cols - it.c0);
     it.mode = S.grp_mode[ch.grp] |
-              (S.tiles ? ((tail_ext(it.np, tr) / 32) << 8) | ((tail_ext(it.nc, tc) / 32) << 16) : 0);
+              (S.tiles ? ((tail_ext(it.np, tr) / 32) << 8) | ((tail_ext(it.nc, tc) / 32) << 16) : 0) |
+              ((ch.flags & CHUNK_IDENT_Y) ? ITEM_IDENT_Y : 0);
     it.tb = ch.tb;
     it.te = ch.te;
     it.slot = (int32_t)c;
@@ -421,11 +425,23 @@ __global__ void k_pan_bounds(Plan p, int64_t n) {
   for (int G = prev + 1; G <= cur; ++G) p.pa.grp[G] = i;
 }
 
-// Chunks of each panel-order position (scanned into ch afterwards).
+// Chunks of each panel-order position (scanned into ch afterwards); a task
+// whose first factor is the identity takes no chunk: its intermediate is a
+// scaled copy of the padded input sector, sized here (scanned into id_off).
 __global__ void k_pan_nch(Plan p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  p.pa.scratch[i] = (task_t_rows(p, p.tasks[p.pa.idx[i]]) + PCH - 1) / PCH;
+  const tns_task t = p.tasks[p.pa.idx[i]];
+  const int rows = task_t_rows(p, t);
+  if (ident_x(t)) {
+    int K, N;
+    panel_dims(p, 2 * t.in + t.order, &K, &N);
+    p.pa.scratch[i] = 0;
+    p.pa.id_sz[i] = (int64_t)rows * ld8(N);
+  } else {
+    p.pa.scratch[i] = (rows + PCH - 1) / PCH;
+    p.pa.id_sz[i] = 0;
+  }
 }
 
 // Per panel: first chunk, intermediate size (scanned into tb afterwards), cost.
@@ -450,7 +466,14 @@ __global__ void k_pan_toff(Plan p, int64_t n) {
   const int G = A.keys_out[i];
   int K, N;
   panel_dims(p, G, &K, &N);
-  p.t_off[A.idx[i]] = A.tb[G] + (A.ch[i] - A.gch[G]) * PCH * ld8(N);
+  const int64_t ng = A.ngroups;
+  p.t_off[A.idx[i]] = ident_x(p.tasks[A.idx[i]]) ? A.tb[ng] + A.id_off[i]
+                                                 : A.tb[G] + (A.ch[i] - A.gch[G]) * PCH * ld8(N);
+}
+
+// Elements of all intermediates: the panels', then the identity-X copies.
+__global__ void k_pan_t_total(Plan p, int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p.pa.scalars[3] = p.pa.tb[p.pa.ngroups] + p.pa.id_off[n];
 }
 
 // Phase-B segment records, one per position of the forward schedule's task
@@ -867,6 +890,8 @@ static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int m
   A.keys_in = cv.take<int32_t>(ntcap); A.keys_out = cv.take<int32_t>(ntcap);
   A.vals_in = cv.take<int32_t>(ntcap); A.idx = cv.take<int32_t>(ntcap);
   A.ch = cv.take<int64_t>(ntcap + 1);
+  A.id_sz = cv.take<int64_t>(ntcap);
+  A.id_off = cv.take<int64_t>(ntcap + 1);
   A.grp = cv.take<int64_t>(g1); A.gch = cv.take<int64_t>(g1); A.tb = cv.take<int64_t>(g1);
   A.cost = cv.take<int64_t>(g1);
   A.rank = cv.take<int32_t>(g1); A.xcd = cv.take<int32_t>(g1);
@@ -882,15 +907,18 @@ static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int m
 }
 
 // Lays out (or, with base == nullptr, sizes) the build workspace.
+// ntasks_explicit >= 0: a task table given by the caller (that many tasks)
+// instead of one enumerated from the terms.
+// backward: also the backward's schedules and the adjoint plan.
 static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_cu, int n_xcd, char *base,
-                     Plan *pl) {
+                     Plan *pl, int64_t ntasks_explicit = -1, bool backward = true) {
   Carve cv{base, 0, 0};
   Plan p;
   memset(&p, 0, sizeof(p));
   p.nL = P->nL; p.nR = P->nR; p.nS = P->nS; p.nOps = P->nOps; p.nBlk = P->nBlk; p.nTerms = P->nTerms;
   p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals; p.maxdim = maxdim; p.tiles = TILES_DEFAULT;
   p.psi_dim = P->psi_off[P->nS];
-  const int64_t ntcap = std::max<int64_t>(1, (int64_t)P->nTerms * P->nS);
+  const int64_t ntcap = std::max<int64_t>(1, ntasks_explicit >= 0 ? ntasks_explicit : (int64_t)P->nTerms * P->nS);
   p.qL = cv.take<int32_t>(2 * P->nL); p.dimL = cv.take<int32_t>(P->nL);
   p.qR = cv.take<int32_t>(2 * P->nR); p.dimR = cv.take<int32_t>(P->nR);
   p.psi_sec = cv.take<int32_t>(4 * (size_t)std::max(1, P->nS)); p.psi_off = cv.take<int64_t>(P->nS + 1);
@@ -918,31 +946,33 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   for (int s = 0; s < P->nS; ++s)
     ftiles += 2 * (int64_t)((P->dimL[P->psi_sec[4 * s]] + 31) / 32) * ((P->dimR[P->psi_sec[4 * s + 3]] + 31) / 32);
   layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
-  // backward schedule: one group per sector (d psi) and one per block (d L / d R)
-  const int64_t bent = 3 * ntcap;
-  p.bkeys_in = cv.take<int32_t>(bent); p.bkeys_out = cv.take<int32_t>(bent); p.bvals_in = cv.take<int32_t>(bent);
-  p.bwd.idx = cv.take<int32_t>(bent);
-  p.bsort_tmp_bytes = radix_tmp_i32(bent);
-  p.bsort_tmp = cv.take<char>(p.bsort_tmp_bytes + 256);
-  const int32_t bgroups = P->nS + P->nBlk;
-  const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
-  int64_t btiles = 0;  // row panels of the operator-block groups (the sector groups stay empty)
-  for (int b = 0; b < P->nBlk; ++b) btiles += (P->blk_rows[b] + TQ - 1) / TQ;
-  layout_sched(cv, p.bwd, bgroups, bent, bchunks, btiles, n_cu, TQ, 0, 0u, n_xcd, false);
   layout_panels(cv, p.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
-  // adjoint task list (d psi of the backward) and its forward schedule
+  const int64_t bent = backward ? 3 * ntcap : 0;
   Adjoint &J = p.adj;
-  J.tasks = cv.take<tns_task>(ntcap);
-  J.out_ptr = cv.take<int32_t>(P->nS + 1);
-  J.scalars = cv.take<int64_t>(8);
-  J.blk_off = cv.take<int64_t>(nb);
-  J.blk_ld = cv.take<int32_t>(nb);
-  J.t_off = cv.take<int64_t>(ntcap + 1);
-  J.segb = cv.take<SegRec>(ntcap);
-  J.n_vals = 0;
-  for (int b = 0; b < P->nBlk; ++b) J.n_vals += (int64_t)P->blk_cols[b] * ld8(P->blk_rows[b]);
-  layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
-  layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
+  if (backward) {
+    // backward schedule: one group per sector (d psi) and one per block (d L / d R)
+    p.bkeys_in = cv.take<int32_t>(bent); p.bkeys_out = cv.take<int32_t>(bent); p.bvals_in = cv.take<int32_t>(bent);
+    p.bwd.idx = cv.take<int32_t>(bent);
+    p.bsort_tmp_bytes = radix_tmp_i32(bent);
+    p.bsort_tmp = cv.take<char>(p.bsort_tmp_bytes + 256);
+    const int32_t bgroups = P->nS + P->nBlk;
+    const int64_t bchunks = 2 * (int64_t)ITEMS_PER_CU * n_cu + 2 * (int64_t)bgroups + 16;
+    int64_t btiles = 0;  // row panels of the operator-block groups (the sector groups stay empty)
+    for (int b = 0; b < P->nBlk; ++b) btiles += (P->blk_rows[b] + TQ - 1) / TQ;
+    layout_sched(cv, p.bwd, bgroups, bent, bchunks, btiles, n_cu, TQ, 0, 0u, n_xcd, false);
+    // adjoint task list (d psi of the backward) and its forward schedule
+    J.tasks = cv.take<tns_task>(ntcap);
+    J.out_ptr = cv.take<int32_t>(P->nS + 1);
+    J.scalars = cv.take<int64_t>(8);
+    J.blk_off = cv.take<int64_t>(nb);
+    J.blk_ld = cv.take<int32_t>(nb);
+    J.t_off = cv.take<int64_t>(ntcap + 1);
+    J.segb = cv.take<SegRec>(ntcap);
+    J.n_vals = 0;
+    for (int b = 0; b < P->nBlk; ++b) J.n_vals += (int64_t)P->blk_cols[b] * ld8(P->blk_rows[b]);
+    layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
+    layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
+  }
   // counts that the sorts and item indices hold in 32 bits
   const int64_t caps[] = {bent, p.fwd.items_cap, p.bwd.items_cap, J.fwd.items_cap, p.pa.items_cap, J.pa.items_cap,
                           p.fwd.chunks_cap, p.bwd.chunks_cap};
@@ -1013,7 +1043,9 @@ static tns_status pan_items(const Plan &p, hipStream_t st) {
   const int B = 256;
   const Panels &A = p.pa;
   const int ng = A.ngroups;
-  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(8), 0, st, A.scalars, (int64_t)8, (int64_t)0);
+  // scalars 0..2 (item cost total, target, items); 3 holds the intermediate
+  // size written when the panels were built
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(8), 0, st, A.scalars, (int64_t)3, (int64_t)0);
   if (ng > 0) hipLaunchKernelGGL(k_pan_total, dim3(nblk(ng, B)), dim3(B), 0, st, p);
   hipLaunchKernelGGL(k_pan_target, dim3(1), dim3(1), 0, st, p);
   hipLaunchKernelGGL(k_pan_count, dim3(nblk(A.items_cap, B)), dim3(B), 0, st, p);
@@ -1045,9 +1077,11 @@ static tns_status build_panels(const Plan &p, hipStream_t st) {
   hipLaunchKernelGGL(k_pan_bounds, dim3(nblk(n + 1, B)), dim3(B), 0, st, p, n);
   if (n > 0) hipLaunchKernelGGL(k_pan_nch, dim3(nblk(n, B)), dim3(B), 0, st, p, n);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, A.scratch, A.ch, n);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, A.id_sz, A.id_off, n);
   hipLaunchKernelGGL(k_pan_sizes, dim3(nblk(ng + 1, B)), dim3(B), 0, st, p);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, A.scratch, A.tb, (int64_t)ng);
   if (n > 0) hipLaunchKernelGGL(k_pan_toff, dim3(nblk(n, B)), dim3(B), 0, st, p, n);
+  hipLaunchKernelGGL(k_pan_t_total, dim3(1), dim3(1), 0, st, p, n);
   if (ng > 0) {
     hipLaunchKernelGGL(k_pan_rank_keys, dim3(nblk(ng, B)), dim3(B), 0, st, p);
     size_t tmp = A.sort_tmp_bytes;
@@ -1115,7 +1149,7 @@ static tns_status build_adjoint(Plan &p, const int64_t *boff, const int32_t *bld
   if (q.ntasks > 0) hipLaunchKernelGGL(k_segb, dim3(nblk(q.ntasks, B)), dim3(B), 0, st, q, q.ntasks);
   TNS_HIP(hipGetLastError());
   int64_t ext[3];
-  TNS_HIP(hipMemcpyAsync(ext, q.pa.tb + q.pa.ngroups, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext, q.pa.scalars + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 1, q.pa.ch + q.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 2, q.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
@@ -1133,24 +1167,38 @@ static tns_status build_adjoint(Plan &p, const int64_t *boff, const int32_t *bld
 
 using namespace tns;
 
+tns_status tns::validate_problem(const tns_problem *P, int32_t *nmax, int32_t *maxdim) {
+  return validate(P, nmax, maxdim);
+}
+
+size_t tns::plan_workspace(const tns_problem *P, int32_t nmax, int32_t maxdim, int64_t nx_explicit, bool backward) {
+  return layout(P, nmax, maxdim, device_cu_count(), device_xcd_count(), nullptr, nullptr, nx_explicit, backward);
+}
+
 extern "C" size_t tns_tasklist_workspace_bytes(const tns_problem *prob) {
   int32_t nmax = 0, maxdim = 0;
   if (validate(prob, &nmax, &maxdim) != TNS_OK) return 0;
   return layout(prob, nmax, maxdim, device_cu_count(), device_xcd_count(), nullptr, nullptr);
 }
 
-extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t ws_bytes, tns_tasklist *out,
-                                         hipStream_t st) {
-  if (!out || !ws) return TNS_ERR_ARG;
-  int32_t nmax = 0, maxdim = 0;
-  tns_status s = validate(P, &nmax, &maxdim);
-  if (s != TNS_OK) return s;
+namespace tns {
+
+// The plan of a validated problem in the caller's workspace.  Without xtasks
+// the task table is enumerated on the device from the terms (levels 1-2);
+// with xtasks (nx tasks, sorted by output sector, CSR xptr[nS + 1], host
+// memory valid until the call returns) that table is taken as it stands.
+// backward: also the backward grouping and the adjoint plan.
+tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const tns_task *xtasks,
+                      const int32_t *xptr, int64_t nx, bool backward, void *ws, size_t ws_bytes, tns_tasklist *out,
+                      hipStream_t st) {
   const int n_cu = device_cu_count(), n_xcd = device_xcd_count();
-  const size_t need = layout(P, nmax, maxdim, n_cu, n_xcd, nullptr, nullptr);
+  const int64_t ntx = xtasks ? nx : -1;
+  const size_t need = layout(P, nmax, maxdim, n_cu, n_xcd, nullptr, nullptr, ntx, backward);
   if (need == 0) return TNS_ERR_SHAPE;  // schedule counts beyond 32-bit indices
   if (ws_bytes < need) return TNS_ERR_WORKSPACE;
   Plan p;
-  layout(P, nmax, maxdim, n_cu, n_xcd, (char *)ws, &p);
+  layout(P, nmax, maxdim, n_cu, n_xcd, (char *)ws, &p, ntx, backward);
+  tns_status s = TNS_OK;
   TNS_HIP(up(p.qL, P->qL, 2 * (size_t)P->nL, st));
   TNS_HIP(up(p.dimL, P->dimL, P->nL, st));
   TNS_HIP(up(p.qR, P->qR, 2 * (size_t)P->nR, st));
@@ -1174,32 +1222,33 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   TNS_HIP(up(p.term_coef, P->term_coef, P->nTerms, st));
 
   const int B = 256;
-  hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)P->nL * 16, B)), dim3(B), 0, st, p.psi_index,
-                     (int64_t)P->nL * 16, -1);
-  hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)std::max(1, P->nOps) * nmax, B)), dim3(B), 0, st,
-                     p.blk_of_out, (int64_t)std::max(1, P->nOps) * nmax, -1);
-  if (P->nS > 0) {
-    hipLaunchKernelGGL(k_psi_index, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
-    hipLaunchKernelGGL(k_pad_sizes, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
-  }
+  if (P->nS > 0) hipLaunchKernelGGL(k_pad_sizes, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.pp_off, p.pp_off, (int64_t)P->nS);
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.pt_off, p.pt_off, (int64_t)P->nS);
-  if (P->nBlk > 0) hipLaunchKernelGGL(k_blk_of_out, dim3(nblk(P->nBlk, B)), dim3(B), 0, st, p);
-  TNS_HIP(hipGetLastError());
   const unsigned wblk = nblk(std::max(1, P->nS), 4);
-  // levels 1-2: task counts per output sector -> CSR -> canonical fill
-  if (P->nS > 0) {
-    hipLaunchKernelGGL(k_tasks<false>, dim3(wblk), dim3(256), 0, st, p);
-    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.scan_tmp, p.scan_tmp, (int64_t)P->nS);
+  if (xtasks) {
+    TNS_HIP(up(p.tasks, xtasks, (size_t)nx, st));
+    TNS_HIP(up(p.out_ptr, xptr, (size_t)P->nS + 1, st));
   } else {
-    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(1), 0, st, p.scan_tmp, (int64_t)1, (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)P->nL * 16, B)), dim3(B), 0, st, p.psi_index,
+                       (int64_t)P->nL * 16, -1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk((int64_t)std::max(1, P->nOps) * nmax, B)), dim3(B), 0, st,
+                       p.blk_of_out, (int64_t)std::max(1, P->nOps) * nmax, -1);
+    if (P->nS > 0) hipLaunchKernelGGL(k_psi_index, dim3(nblk(P->nS, B)), dim3(B), 0, st, p);
+    if (P->nBlk > 0) hipLaunchKernelGGL(k_blk_of_out, dim3(nblk(P->nBlk, B)), dim3(B), 0, st, p);
+    TNS_HIP(hipGetLastError());
+    // levels 1-2: task counts per output sector -> CSR -> canonical fill
+    if (P->nS > 0) {
+      hipLaunchKernelGGL(k_tasks<false>, dim3(wblk), dim3(256), 0, st, p);
+      hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.scan_tmp, p.scan_tmp, (int64_t)P->nS);
+    } else {
+      hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(1), 0, st, p.scan_tmp, (int64_t)1, (int64_t)0);
+    }
+    hipLaunchKernelGGL(k_i64_to_i32, dim3(nblk(P->nS + 1, B)), dim3(B), 0, st, p.scan_tmp, p.out_ptr,
+                       (int64_t)P->nS + 1);
+    if (P->nS > 0) hipLaunchKernelGGL(k_tasks<true>, dim3(wblk), dim3(256), 0, st, p);
   }
-  hipLaunchKernelGGL(k_i64_to_i32, dim3(nblk(P->nS + 1, B)), dim3(B), 0, st, p.scan_tmp, p.out_ptr,
-                     (int64_t)P->nS + 1);
-  if (P->nS > 0) {
-    hipLaunchKernelGGL(k_tasks<true>, dim3(wblk), dim3(256), 0, st, p);
-    hipLaunchKernelGGL(k_fwd_groups, dim3(wblk), dim3(256), 0, st, p, p.fwd);
-  }
+  if (P->nS > 0) hipLaunchKernelGGL(k_fwd_groups, dim3(wblk), dim3(256), 0, st, p, p.fwd);
   TNS_HIP(hipGetLastError());
   s = finish_sched(p, p.fwd, st);
   if (s != TNS_OK) return s;
@@ -1218,6 +1267,22 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   if (p.ntasks > 0) hipLaunchKernelGGL(k_segb, dim3(nblk(p.ntasks, B)), dim3(B), 0, st, p, p.ntasks);
   TNS_HIP(hipGetLastError());
 
+  if (!backward) {
+    int64_t ext[5];
+    TNS_HIP(hipMemcpyAsync(ext, p.pa.scalars + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TNS_HIP(hipMemcpyAsync(ext + 1, p.pp_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TNS_HIP(hipMemcpyAsync(ext + 2, p.pt_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TNS_HIP(hipMemcpyAsync(ext + 3, p.pa.ch + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TNS_HIP(hipMemcpyAsync(ext + 4, p.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TNS_HIP(hipStreamSynchronize(st));
+    p.t_elems = p.pa.t_elems = ext[0];
+    p.pp_elems = ext[1];
+    p.pt_elems = ext[2];
+    p.pa.nchunks = ext[3];
+    p.pa.nitems = ext[4];
+    if (p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
+    p.no_backward = 1;
+  } else {
   // backward grouping: stable sort of (key, task) entries by key
   const int64_t nent = 3 * p.ntasks;
   if (nent > 0) {
@@ -1236,7 +1301,7 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   if (s != TNS_OK) return s;
   TNS_HIP(hipMemcpyAsync(h, p.bwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
   int64_t ext[5];
-  TNS_HIP(hipMemcpyAsync(ext, p.pa.tb + p.pa.ngroups, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext, p.pa.scalars + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 1, p.pp_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 2, p.pt_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 3, p.pa.ch + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -1262,6 +1327,7 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   }
   s = build_adjoint(p, toff.data(), tld.data(), st);
   if (s != TNS_OK) return s;
+  }
 
   memset(out, 0, sizeof(*out));
   out->ntasks = p.ntasks;
@@ -1274,6 +1340,17 @@ extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t 
   out->out_ptr = p.out_ptr;
   memcpy(out->opaque, &p, sizeof(p));
   return TNS_OK;
+}
+
+}  // namespace tns
+
+extern "C" tns_status tns_build_tasklist(const tns_problem *P, void *ws, size_t ws_bytes, tns_tasklist *out,
+                                         hipStream_t st) {
+  if (!out || !ws) return TNS_ERR_ARG;
+  int32_t nmax = 0, maxdim = 0;
+  const tns_status s = validate(P, &nmax, &maxdim);
+  if (s != TNS_OK) return s;
+  return build_plan(P, nmax, maxdim, nullptr, nullptr, 0, true, ws, ws_bytes, out, st);
 }
 
 extern "C" tns_status tns_set_tiles(tns_tasklist *tl, uint32_t tiles, hipStream_t st) {

@@ -87,8 +87,20 @@ __host__ __device__ inline bool tiles_valid(uint32_t tab) {
 struct Chunk {
   int32_t grp, tb, te, xcd;  // xcd: queue the chunk's tiles go to
   int64_t cost;
-  int32_t rank, pad_;        // position in descending cost order
+  int32_t rank;              // position in descending cost order
+  int32_t flags;             // CHUNK_IDENT_Y: some task's second factor is an identity
 };
+constexpr int32_t CHUNK_IDENT_Y = 1;
+// Work-item mode bit: the item's chunk holds identity second factors, whose
+// intermediates are added into the accumulators without a product.
+constexpr int32_t ITEM_IDENT_Y = 1 << 24;
+
+// Identity factors are not multiplied.  A task's first factor X (class 0: L,
+// class 1: R) being the identity makes its intermediate T = alpha M a scaled
+// copy of the padded input sector; its second factor Y (class 0: R, class 1:
+// L) being the identity makes its contribution T itself.
+__host__ __device__ inline bool ident_x(const tns_task &t) { return t.order == 0 ? t.lblk < 0 : t.rblk < 0; }
+__host__ __device__ inline bool ident_y(const tns_task &t) { return t.order == 0 ? t.rblk < 0 : t.lblk < 0; }
 
 // A schedule: groups of tasks that share one output matrix, cut into chunks
 // (partial slots) and row panels (work items), longest item first.
@@ -125,9 +137,9 @@ constexpr int PCH = 16;
 constexpr int PTILE_CH = GM / PCH;
 
 // Source of one stacked chunk, written before each product: element offset
-// of the chunk's first row in the operator values (off >= 0, leading
-// dimension ld) or, for an identity side, -(1 + first row) of the identity
-// matrix; vrows = rows of the chunk inside its task (1..16); alpha of the task.
+// of the chunk's first row in the operator values (leading dimension ld);
+// vrows = rows of the chunk inside its task (1..16); alpha of the task.
+// Tasks whose first factor is the identity have no chunks.
 struct ChunkRec {
   int64_t off;
   int32_t ld, vrows;
@@ -142,7 +154,9 @@ struct Panels {
   int64_t ntcap, items_cap;
   int64_t nchunks, nitems, t_elems;
   int32_t *keys_in, *keys_out, *vals_in, *idx;  // [ntcap]: idx = tasks in panel order
-  int64_t *ch;         // [ntcap + 1] first chunk of each panel-order position
+  int64_t *ch;         // [ntcap + 1] first chunk of each panel-order position (none for identity X)
+  int64_t *id_sz;      // [ntcap] intermediate size of identity-X tasks (panel order), else 0
+  int64_t *id_off;     // [ntcap + 1] their offsets after the panels' intermediates
   int64_t *grp;        // [ngroups + 1] first panel-order position of each panel
   int64_t *gch;        // [ngroups + 1] first chunk of each panel
   int64_t *tb;         // [ngroups + 1] element offset of each panel's intermediates
@@ -156,7 +170,7 @@ struct Panels {
   size_t sort_tmp_bytes;
   int64_t *qbase;      // [NQ_MAX + 1]: queue q = items[qbase[q], qbase[q+1])
   int64_t *scratch;    // [max(ngroups, ntcap, items_cap) + 1]
-  int64_t *scalars;    // [8]
+  int64_t *scalars;    // [8]: total item cost, item target cost, items, intermediate elements
 };
 
 // One segment of a phase-B work item (a task of its chunk), in the order of
@@ -198,6 +212,7 @@ struct Plan {
   int32_t nL, nR, nS, nOps, nBlk, nTerms, nmax, n_cu;
   int32_t maxdim;        // largest sector dimension
   uint32_t tiles;        // forward tile table
+  int32_t no_backward, pad0_;  // 1: built without the backward's schedules
   int64_t n_vals, psi_dim, ntasks;
   // copied tables
   int32_t *qL, *dimL, *qR, *dimR, *psi_sec;
@@ -297,6 +312,18 @@ __host__ __device__ inline void mono_shift(int m, int *dN, int *d2Sz) {
   *dN = du + dd;
   *d2Sz = du - dd;
 }
+
+// Plan of a validated problem (tasklist.hip): the task table enumerated on the
+// device from the terms, or (xtasks) one given by the caller, sorted by output
+// sector with CSR xptr; backward: with the backward's schedules.
+tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const tns_task *xtasks,
+                      const int32_t *xptr, int64_t nx, bool backward, void *ws, size_t ws_bytes, tns_tasklist *out,
+                      hipStream_t st);
+// Host validation of a problem (shapes, ranges, quantum numbers); returns the
+// largest sector count and dimension.
+tns_status validate_problem(const tns_problem *P, int32_t *nmax, int32_t *maxdim);
+// Build-workspace bytes of build_plan (0 when counts exceed 32-bit indices).
+size_t plan_workspace(const tns_problem *P, int32_t nmax, int32_t maxdim, int64_t nx_explicit, bool backward);
 
 // Plan of the adjoint product (the tables of p with the adjoint task list,
 // block table and schedules of p.adj in place of the forward ones).

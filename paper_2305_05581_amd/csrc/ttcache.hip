@@ -1,0 +1,316 @@
+// Out-of-HBM products: the operator values stay in (pinned) host memory and
+// stream through a device cache managed as the paper's tree-traversal stack
+// (Section II.B, Alg. 1): the terms form a data dependency tree (level 1 the
+// left operator, level 2 the right operator, leaves the terms), a depth-first
+// walk loads a node's operator on top of the stack and pops it once the node's
+// subtree is done, so the left operator stays resident for all of its right
+// partners and allocation is a moving offset.  Execution is deferred until
+// the stack is full or a left subtree ends (an epoch): then every pending
+// term runs as one product (tns_apply_heff, accumulating into sigma) whose
+// task list was built at plan time with the blocks' cache offsets.
+#include <algorithm>
+#include <vector>
+
+#include "kern.hpp"
+#include "tns_internal.hpp"
+
+namespace tns {
+
+struct TtLoad {
+  int64_t host_off, cache_off, elems;  // elements of the operator value arrays
+};
+
+// Host-side plan, in the caller's host buffer: epoch records, loads, task lists.
+struct TtEpoch {
+  int64_t load_begin, load_end;  // loads issued before the epoch's product
+  int64_t dev_off;               // its task list's build workspace in the device buffer
+  int64_t ws_bytes;              // size of that workspace
+};
+
+struct TtHeader {
+  int64_t n_epochs, n_loads, cache_elems, psi_dim;
+  TtEpoch *epochs;
+  TtLoad *loads;
+  tns_tasklist *tls;  // one per epoch
+};
+static_assert(sizeof(TtHeader) <= 256, "TtHeader fits the plan's opaque bytes");
+
+static inline TtHeader &tt_of(tns_ttcache_plan *p) { return *reinterpret_cast<TtHeader *>(p->opaque); }
+static inline const TtHeader &tt_of(const tns_ttcache_plan *p) { return *reinterpret_cast<const TtHeader *>(p->opaque); }
+
+// One epoch while planning: loads, resident operators (cache offset per op),
+// terms to run.
+struct TtPlanEpoch {
+  std::vector<TtLoad> loads;
+  std::vector<std::pair<int, int64_t>> resident;  // (operator, cache offset of its first element)
+  std::vector<int> terms;
+};
+
+// Element range of every operator's blocks in the value array.
+static void op_extents(const tns_problem *P, std::vector<int64_t> &lo, std::vector<int64_t> &hi) {
+  lo.assign(P->nOps, INT64_MAX);
+  hi.assign(P->nOps, -1);
+  for (int b = 0; b < P->nBlk; ++b) {
+    const int o = P->blk_op[b];
+    lo[o] = std::min(lo[o], P->blk_off[b]);
+    hi[o] = std::max(hi[o], P->blk_off[b] + (int64_t)P->blk_rows[b] * P->blk_ld[b]);
+  }
+  for (int o = 0; o < P->nOps; ++o)
+    if (hi[o] < 0) lo[o] = hi[o] = 0;  // an operator without blocks loads nothing
+}
+
+// Depth-first walk of the dependency tree with the stack cache.  Returns
+// TNS_ERR_WORKSPACE when one left operator and one right operator together
+// exceed the cache.
+static tns_status tt_walk(const tns_problem *P, int64_t cap, std::vector<TtPlanEpoch> &epochs, int64_t *naive) {
+  std::vector<int64_t> lo, hi;
+  op_extents(P, lo, hi);
+  auto size_of = [&](int o) { return o >= 0 ? (hi[o] - lo[o] + 7) / 8 * 8 : 0; };
+  std::vector<int> order(P->nTerms);
+  for (int t = 0; t < P->nTerms; ++t) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return P->term_L[a] != P->term_L[b] ? P->term_L[a] < P->term_L[b] : P->term_R[a] < P->term_R[b];
+  });
+  *naive = 0;
+  for (int t = 0; t < P->nTerms; ++t) *naive += size_of(P->term_L[t]) + size_of(P->term_R[t]);
+  struct Slot { int op; int64_t off, size; };
+  std::vector<Slot> stack;
+  int64_t top = 0;
+  TtPlanEpoch cur;
+  auto push = [&](int o) {
+    const int64_t sz = size_of(o);
+    stack.push_back({o, top, sz});
+    if (sz) cur.loads.push_back({lo[o], top, hi[o] - lo[o]});
+    top += sz;
+  };
+  auto resident = [&](int o) {
+    for (auto &s : stack)
+      if (s.op == o) return true;
+    return false;
+  };
+  auto flush = [&]() {
+    if (cur.terms.empty() && cur.loads.empty()) return;
+    cur.resident.clear();
+    for (auto &s : stack) cur.resident.push_back({s.op, s.off});
+    epochs.push_back(cur);
+    cur = TtPlanEpoch();
+  };
+  size_t i = 0;
+  while (i < order.size()) {
+    const int oL = P->term_L[order[i]];
+    // level 1: the left operator at the bottom of the stack
+    stack.clear();
+    top = 0;
+    if (oL >= 0) {
+      if (size_of(oL) > cap) return TNS_ERR_WORKSPACE;
+      push(oL);
+    }
+    const size_t base = stack.size();
+    const int64_t base_top = top;
+    while (i < order.size() && P->term_L[order[i]] == oL) {
+      const int oR = P->term_R[order[i]];
+      if (oR >= 0 && oR != oL && !resident(oR)) {
+        if (top + size_of(oR) > cap) {
+          flush();  // run what is pending, then pop back to the left operator
+          stack.resize(base);
+          top = base_top;
+          if (top + size_of(oR) > cap) return TNS_ERR_WORKSPACE;
+        }
+        push(oR);
+      }
+      while (i < order.size() && P->term_L[order[i]] == oL && P->term_R[order[i]] == oR)
+        cur.terms.push_back(order[i++]);
+    }
+    flush();
+  }
+  return TNS_OK;
+}
+
+// The sub-problem of an epoch: its terms, the blocks of its resident
+// operators at their cache offsets; everything else of P.
+struct TtSub {
+  std::vector<int32_t> bop, bin, bout, brows, bcols, bld, tL, ta, tb, tR;
+  std::vector<int64_t> boff;
+  std::vector<double> tc;
+  tns_problem P;
+};
+
+static void tt_sub(const tns_problem *P, const TtPlanEpoch &e, int64_t cap, TtSub &s) {
+  std::vector<int64_t> lo, hi;
+  op_extents(P, lo, hi);
+  std::vector<int64_t> at(P->nOps, -1);
+  for (auto &r : e.resident)
+    if (r.first >= 0) at[r.first] = r.second;
+  for (int b = 0; b < P->nBlk; ++b) {
+    const int o = P->blk_op[b];
+    if (at[o] < 0) continue;
+    s.bop.push_back(o); s.bin.push_back(P->blk_in[b]); s.bout.push_back(P->blk_out[b]);
+    s.brows.push_back(P->blk_rows[b]); s.bcols.push_back(P->blk_cols[b]); s.bld.push_back(P->blk_ld[b]);
+    s.boff.push_back(at[o] + (P->blk_off[b] - lo[o]));
+  }
+  for (int t : e.terms) {
+    s.tL.push_back(P->term_L[t]); s.ta.push_back(P->term_ma[t]); s.tb.push_back(P->term_mb[t]);
+    s.tR.push_back(P->term_R[t]); s.tc.push_back(P->term_coef[t]);
+  }
+  s.P = *P;
+  s.P.nBlk = (int32_t)s.bop.size();
+  s.P.nTerms = (int32_t)s.tL.size();
+  s.P.n_vals = cap;
+  s.P.blk_op = s.bop.data(); s.P.blk_in = s.bin.data(); s.P.blk_out = s.bout.data();
+  s.P.blk_rows = s.brows.data(); s.P.blk_cols = s.bcols.data(); s.P.blk_ld = s.bld.data();
+  s.P.blk_off = s.boff.data();
+  s.P.term_L = s.tL.data(); s.P.term_ma = s.ta.data(); s.P.term_mb = s.tb.data(); s.P.term_R = s.tR.data();
+  s.P.term_coef = s.tc.data();
+}
+
+// Blocks are read at element offsets that are multiples of 8: the cache keeps
+// each operator's first element at a multiple of 8 (sizes rounded up), so the
+// rebased offsets stay multiples of 8 when the host ones are.
+static tns_status tt_plan(const tns_problem *P, int64_t cap, std::vector<TtPlanEpoch> &epochs,
+                          std::vector<size_t> &ws, int64_t *naive, int64_t *loaded) {
+  int32_t nmax = 0, maxdim = 0;
+  tns_status s = validate_problem(P, &nmax, &maxdim);
+  if (s != TNS_OK) return s;
+  if (cap <= 0) return TNS_ERR_ARG;
+  s = tt_walk(P, (cap / 8) * 8, epochs, naive);
+  if (s != TNS_OK) return s;
+  *loaded = 0;
+  ws.clear();
+  for (auto &e : epochs) {
+    for (auto &l : e.loads) *loaded += l.elems;
+    TtSub sub;
+    tt_sub(P, e, cap, sub);
+    int32_t nm = 0, md = 0;
+    s = validate_problem(&sub.P, &nm, &md);
+    if (s != TNS_OK) return s;
+    const size_t b = plan_workspace(&sub.P, nm, md, -1, false);
+    if (b == 0) return TNS_ERR_SHAPE;
+    ws.push_back(align_up(b, 256));
+  }
+  return TNS_OK;
+}
+
+template <class T>
+__global__ void k_tt_zero(T *p, int64_t n) {
+  GRID_STRIDE(i, n) p[i] = T(0);
+}
+
+}  // namespace tns
+
+using namespace tns;
+
+extern "C" tns_status tns_ttcache_sizes(const tns_problem *P, int64_t cache_elems, size_t *host_bytes,
+                                        size_t *dev_bytes, int64_t *n_epochs) {
+  if (!host_bytes || !dev_bytes) return TNS_ERR_ARG;
+  std::vector<TtPlanEpoch> epochs;
+  std::vector<size_t> ws;
+  int64_t naive = 0, loaded = 0;
+  const tns_status s = tt_plan(P, cache_elems, epochs, ws, &naive, &loaded);
+  if (s != TNS_OK) return s;
+  size_t nl = 0, db = 0;
+  for (auto &e : epochs) nl += e.loads.size();
+  for (size_t b : ws) db += b;
+  *host_bytes = align_up(epochs.size() * sizeof(TtEpoch), 64) + align_up(nl * sizeof(TtLoad), 64) +
+                epochs.size() * sizeof(tns_tasklist) + 64;
+  *dev_bytes = db;
+  if (n_epochs) *n_epochs = (int64_t)epochs.size();
+  return TNS_OK;
+}
+
+extern "C" tns_status tns_ttcache_build(const tns_problem *P, int64_t cache_elems, void *host_buf, size_t host_bytes,
+                                        void *dev_ws, size_t dev_bytes, tns_ttcache_plan *out, hipStream_t st) {
+  if (!host_buf || !dev_ws || !out) return TNS_ERR_ARG;
+  std::vector<TtPlanEpoch> epochs;
+  std::vector<size_t> ws;
+  int64_t naive = 0, loaded = 0;
+  tns_status s = tt_plan(P, cache_elems, epochs, ws, &naive, &loaded);
+  if (s != TNS_OK) return s;
+  size_t hb = 0, db = 0;
+  int64_t ne = 0;
+  s = tns_ttcache_sizes(P, cache_elems, &hb, &db, &ne);
+  if (s != TNS_OK) return s;
+  if (host_bytes < hb || dev_bytes < db) return TNS_ERR_WORKSPACE;
+  memset(out, 0, sizeof(*out));
+  TtHeader &h = tt_of(out);
+  char *c = reinterpret_cast<char *>(host_buf);
+  h.epochs = reinterpret_cast<TtEpoch *>(c);
+  c += align_up(epochs.size() * sizeof(TtEpoch), 64);
+  h.loads = reinterpret_cast<TtLoad *>(c);
+  size_t nl = 0;
+  for (auto &e : epochs) nl += e.loads.size();
+  c += align_up(nl * sizeof(TtLoad), 64);
+  h.tls = reinterpret_cast<tns_tasklist *>(c);
+  h.n_epochs = (int64_t)epochs.size();
+  h.n_loads = (int64_t)nl;
+  h.cache_elems = cache_elems;
+  h.psi_dim = P->psi_off[P->nS];
+  int64_t li = 0, doff = 0, tasks = 0, flops = 0;
+  char *dws = reinterpret_cast<char *>(dev_ws);
+  for (size_t k = 0; k < epochs.size(); ++k) {
+    TtEpoch &E = h.epochs[k];
+    E.load_begin = li;
+    for (auto &l : epochs[k].loads) h.loads[li++] = l;
+    E.load_end = li;
+    E.dev_off = doff;
+    E.ws_bytes = (int64_t)ws[k];
+    TtSub sub;
+    tt_sub(P, epochs[k], cache_elems, sub);
+    int32_t nm = 0, md = 0;
+    s = validate_problem(&sub.P, &nm, &md);
+    if (s != TNS_OK) return s;
+    s = build_plan(&sub.P, nm, md, nullptr, nullptr, 0, false, dws + doff, ws[k], &h.tls[k], st);
+    if (s != TNS_OK) return s;
+    tasks += h.tls[k].ntasks;
+    flops += h.tls[k].total_flops;
+    doff += (int64_t)ws[k];
+  }
+  out->n_epochs = h.n_epochs;
+  out->n_loads = h.n_loads;
+  out->loaded_elems = loaded;
+  out->naive_elems = naive;
+  out->ntasks = tasks;
+  out->total_flops = flops;
+  out->cache_elems = cache_elems;
+  return TNS_OK;
+}
+
+extern "C" size_t tns_ttcache_apply_workspace_bytes(const tns_ttcache_plan *p, tns_prec prec) {
+  if (!p || (prec != TNS_F64 && prec != TNS_F32)) return 0;
+  const TtHeader &h = tt_of(p);
+  size_t b = 256;
+  for (int64_t k = 0; k < h.n_epochs; ++k) b = std::max(b, fwd_workspace(plan_of(&h.tls[k]), prec));
+  return b;
+}
+
+extern "C" tns_status tns_apply_heff_streamed(const tns_ttcache_plan *p, tns_prec prec, const void *host_vals,
+                                              void *cache, const void *psi, void *sigma, void *ws, size_t ws_bytes,
+                                              hipStream_t st) {
+  if (!p || !host_vals || !cache || !psi || !sigma || !ws) return TNS_ERR_ARG;
+  if (prec != TNS_F64 && prec != TNS_F32) return TNS_ERR_ARG;
+  if (ws_bytes < tns_ttcache_apply_workspace_bytes(p, prec)) return TNS_ERR_WORKSPACE;
+  const TtHeader &h = tt_of(p);
+  const size_t es = prec == TNS_F64 ? 8 : 4;
+  const char *hv = reinterpret_cast<const char *>(host_vals);
+  char *cv = reinterpret_cast<char *>(cache);
+  if (h.n_epochs == 0) {  // no terms: sigma = 0
+    if (h.psi_dim > 0) {
+      const unsigned nb = (unsigned)std::min<int64_t>((h.psi_dim + 255) / 256, 1 << 16);
+      if (prec == TNS_F64) hipLaunchKernelGGL(k_tt_zero<double>, dim3(nb), dim3(256), 0, st, (double *)sigma, h.psi_dim);
+      else hipLaunchKernelGGL(k_tt_zero<float>, dim3(nb), dim3(256), 0, st, (float *)sigma, h.psi_dim);
+    }
+    return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
+  }
+  for (int64_t k = 0; k < h.n_epochs; ++k) {
+    const TtEpoch &E = h.epochs[k];
+    // the epoch's loads follow the previous epoch's product on the stream,
+    // so they never overwrite operators that product still reads
+    for (int64_t l = E.load_begin; l < E.load_end; ++l) {
+      const TtLoad &L = h.loads[l];
+      TNS_HIP(hipMemcpyAsync(cv + L.cache_off * es, hv + L.host_off * es, (size_t)L.elems * es,
+                             hipMemcpyHostToDevice, st));
+    }
+    const tns_status s = tns_apply_heff(&h.tls[k], prec, cache, psi, sigma, k == 0 ? 0.0 : 1.0, ws, ws_bytes, st);
+    if (s != TNS_OK) return s;
+  }
+  return TNS_OK;
+}

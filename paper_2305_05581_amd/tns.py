@@ -55,6 +55,19 @@ class TnsDavidsonInfo(ctypes.Structure):
                 ("res_norm", ctypes.c_double), ("e_lo", ctypes.c_double)]
 
 
+class TnsRenormProblem(ctypes.Structure):
+    _fields_ = [("nL", _i32), ("qL", _P), ("dimL", _P), ("nOps", _i32), ("nBlk", _i32), ("op_dN", _P),
+                ("op_d2Sz", _P), ("blk_op", _P), ("blk_in", _P), ("blk_out", _P), ("blk_rows", _P), ("blk_cols", _P),
+                ("blk_ld", _P), ("blk_off", _P), ("n_vals", _i64), ("nQ", _i32), ("qQ", _P), ("keep", _P),
+                ("u_off", _P), ("n_u", _i64), ("nNew", _i32), ("nTerms", _i32), ("term_new", _P), ("term_op", _P),
+                ("term_mono", _P), ("term_coef", _P)]
+
+
+class TnsRenormPlan(ctypes.Structure):
+    _fields_ = [("ntasks", _i64), ("n_out_blk", _i64), ("out_elems", _i64), ("total_flops", _i64),
+                ("tl", TnsTasklist), ("opaque", ctypes.c_uint8 * 1024)]
+
+
 EXPORTS = ("tns_tasklist_workspace_bytes", "tns_build_tasklist", "tns_apply_workspace_bytes",
            "tns_prepare_operands", "tns_apply_heff", "tns_backward_workspace_bytes", "tns_apply_heff_backward",
            "tns_davidson_workspace_bytes", "tns_davidson", "tns_status_string")
@@ -125,6 +138,17 @@ def library(path=LIB_PATH):
         L.tns_apply_heff_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(TnsTasklist)), ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                            ctypes.c_double, _P, sz, _P]
+    if hasattr(L, "tns_renorm_build"):
+        L.tns_renorm_workspace_bytes.restype = sz
+        L.tns_renorm_workspace_bytes.argtypes = [ctypes.POINTER(TnsRenormProblem)]
+        L.tns_renorm_build.restype = ctypes.c_int
+        L.tns_renorm_build.argtypes = [ctypes.POINTER(TnsRenormProblem), _P, sz, ctypes.POINTER(TnsRenormPlan), _P]
+        L.tns_renorm_out_table.restype = ctypes.c_int
+        L.tns_renorm_out_table.argtypes = [ctypes.POINTER(TnsRenormPlan)] + [_P] * 7
+        L.tns_renorm_apply_workspace_bytes.restype = sz
+        L.tns_renorm_apply_workspace_bytes.argtypes = [ctypes.POINTER(TnsRenormPlan), ctypes.c_int]
+        L.tns_renormalize.restype = ctypes.c_int
+        L.tns_renormalize.argtypes = [ctypes.POINTER(TnsRenormPlan), ctypes.c_int, _P, _P, _P, _P, sz, _P]
     L.tns_status_string.restype = ctypes.c_char_p
     L.tns_status_string.argtypes = [ctypes.c_int]
     _lib = L
@@ -522,3 +546,91 @@ def mfma_peak(prec, iters=20000):
     out = ctypes.c_double(0.0)
     _check(L.tns_mfma_peak(prec_id(prec), int(iters), _ptr(ws), n, ctypes.byref(out), _stream()), "tns_mfma_peak")
     return out.value
+
+
+def renorm_problem_struct(R):
+    """``(tns_renorm_problem, host arrays)`` of a renormalisation input; the
+    arrays back the struct's pointers and must outlive its use."""
+    host = {}
+    cp = TnsRenormProblem()
+    for name, dt in RenormStep._INT:
+        a = np.ascontiguousarray(getattr(R, name), dtype=dt)
+        host[name] = a
+        setattr(cp, name, a.ctypes.data_as(ctypes.c_void_p) if a.size else None)
+    cp.nL, cp.nOps, cp.nBlk = len(R.dimL), len(R.op_dN), len(R.blk_op)
+    cp.n_vals, cp.nQ, cp.n_u = len(R.op_vals), len(R.keep), len(R.u_vals)
+    cp.nNew, cp.nTerms = int(R.n_new), len(R.term_new)
+    return cp, host
+
+
+def renorm_workspace_bytes(R):
+    """Build-workspace bytes of a renormalisation step, 0 when it fails the
+    library's host validation (no device call beyond unit-count queries)."""
+    cp, host = renorm_problem_struct(R)
+    return int(library().tns_renorm_workspace_bytes(ctypes.byref(cp)))
+
+
+class RenormStep:
+    """One renormalisation (blocking) step resident on the GPU
+    (``tns_renorm_build`` / ``tns_renormalize``): ``R`` holds the block's
+    sectors and operators, the enlarged block's sectors, kept dimensions and
+    isometry offsets, and the terms of the new operators (see
+    :mod:`synth.renorm` for the array names)."""
+
+    _INT = (("qL", np.int32), ("dimL", np.int32), ("op_dN", np.int32), ("op_d2Sz", np.int32), ("blk_op", np.int32),
+            ("blk_in", np.int32), ("blk_out", np.int32), ("blk_rows", np.int32), ("blk_cols", np.int32),
+            ("blk_ld", np.int32), ("blk_off", np.int64), ("qQ", np.int32), ("keep", np.int32), ("u_off", np.int64),
+            ("term_new", np.int32), ("term_op", np.int32), ("term_mono", np.int32), ("term_coef", np.float64))
+
+    def __init__(self, R, device="cuda"):
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        L = library()
+        cp, self._host = renorm_problem_struct(R)
+        self.cprob = cp
+        nb = L.tns_renorm_workspace_bytes(ctypes.byref(cp))
+        if nb == 0:
+            raise ValueError("renormalisation problem failed host validation")
+        self.ws_build = torch.empty(int(nb), dtype=torch.uint8, device=dev)
+        self.plan = TnsRenormPlan()
+        with torch.cuda.device(dev):
+            _check(L.tns_renorm_build(ctypes.byref(cp), _ptr(self.ws_build), int(nb), ctypes.byref(self.plan),
+                                      _stream()), "tns_renorm_build")
+        self.ntasks = int(self.plan.ntasks)
+        self.n_out_blk = int(self.plan.n_out_blk)
+        self.out_elems = int(self.plan.out_elems)
+        self.total_flops = int(self.plan.total_flops)
+        self._ws = {}
+
+    def out_table(self):
+        """``dict`` of numpy arrays ``new, q_in, q_out, rows, cols, ld, off``
+        (one entry per output block)."""
+        n = self.n_out_blk
+        t = {k: np.zeros(n, dtype=np.int32) for k in ("new", "q_in", "q_out", "rows", "cols", "ld")}
+        t["off"] = np.zeros(n, dtype=np.int64)
+        if n:
+            args = [t[k].ctypes.data_as(ctypes.c_void_p) for k in ("new", "q_in", "q_out", "rows", "cols", "ld", "off")]
+            _check(library().tns_renorm_out_table(ctypes.byref(self.plan), *args), "tns_renorm_out_table")
+        return t
+
+    def apply(self, op_vals, u_vals, prec="f64", out=None):
+        """Renormalised blocks (tensor of ``out_elems``, layout of
+        :meth:`out_table`) from FP64 device tensors of operator values and
+        isometries; products in ``prec``."""
+        p = prec_id(prec)
+        dt = torch.float64 if p == F64 else torch.float32
+        for x, what in ((op_vals, "op_vals"), (u_vals, "u_vals")):
+            if x.dtype != torch.float64 or x.device != self.device or not x.is_contiguous():
+                raise ValueError("%s must be a contiguous float64 tensor on %s" % (what, self.device))
+        if out is None:
+            out = torch.empty(max(self.out_elems, 1), dtype=dt, device=self.device)
+        L = library()
+        if p not in self._ws:
+            n = L.tns_renorm_apply_workspace_bytes(ctypes.byref(self.plan), p)
+            self._ws[p] = torch.empty(int(max(n, 256)), dtype=torch.uint8, device=self.device)
+        ws = self._ws[p]
+        _check(L.tns_renormalize(ctypes.byref(self.plan), p, _ptr(op_vals), _ptr(u_vals), _ptr(out), _ptr(ws),
+                                 ws.numel(), _stream()), "tns_renormalize")
+        return out

@@ -20,6 +20,9 @@ def _instances():
         "small_gapped": lambda: synthetic_problem(16, 16, 0, 96, 8, 24, 60, seed=5, gapped=True),
         "cfg1_exact": lambda: Construction(*molecular_integrals(8, 1), 8, 0).problem(),
         "ragged": lambda: synthetic_problem(22, 22, 0, 700, 23, 187, 120, seed=12),
+        # exact blocks of 4 orbitals (256 states each) at L = 10: 13 % of the
+        # tasks have an identity factor, which the kernels add without a product
+        "exact10": lambda: Construction(*molecular_integrals(10, 21), 10, 0).problem(),
     }
 
 

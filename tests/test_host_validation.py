@@ -62,3 +62,33 @@ def test_malformed_tables_rejected(lib_ok, base):
     cases["term operator out of range"] = _with(P, term_L=tl)
     for name, Q in cases.items():
         assert _bytes(Q) == 0, name
+
+
+def _rn_bytes(R):
+    from paper_2305_05581_amd.tns import renorm_workspace_bytes
+    return renorm_workspace_bytes(R)
+
+
+def test_renorm_validation(lib_ok):
+    """Renormalisation steps: a well-formed step is accepted; a missing
+    enlarged sector, a new operator whose terms change the quantum numbers
+    differently, a block of the wrong shape and kept dimensions beyond the
+    full ones are rejected on the host."""
+    from synth.renorm import renorm_instance
+    R = renorm_instance(6, 64, 8, 24, 20, 30, seed=3)
+    assert _rn_bytes(R) > 0
+    assert _rn_bytes(dataclasses.replace(R, qQ=R.qQ[1:], keep=R.keep[1:], u_off=R.u_off[1:], full=R.full[1:])) == 0
+    # second term of new operator 0: its operator with a monomial of another shift
+    from synth.problem import MONO_SHIFT
+    m2 = next(m for m in range(16) if MONO_SHIFT[m] != MONO_SHIFT[int(R.term_mono[0])])
+    bad = dataclasses.replace(R, term_new=np.concatenate([R.term_new, [0]]),
+                              term_op=np.concatenate([R.term_op, [R.term_op[0]]]),
+                              term_mono=np.concatenate([R.term_mono, [m2]]),
+                              term_coef=np.concatenate([R.term_coef, [1.0]]))
+    assert _rn_bytes(bad) == 0
+    rows = R.blk_rows.copy()
+    rows[0] += 1
+    assert _rn_bytes(dataclasses.replace(R, blk_rows=rows)) == 0
+    keep = R.keep.copy()
+    keep[0] = R.full[0] + 1
+    assert _rn_bytes(dataclasses.replace(R, keep=keep)) == 0
