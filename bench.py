@@ -213,7 +213,8 @@ def make_problem(cfg):
         h, eri = molecular_integrals(cfg["L"], cfg["seed"])
         return Construction(h, eri, cfg["N"], cfg["twoSz"]).problem()
     return synthetic_problem(cfg["L"], cfg["N"], cfg["twoSz"], cfg["D"], cfg["mean"], cfg["dmax"], cfg["K"],
-                             seed=cfg["seed"], gapped=cfg["gapped"], threads=min(16, os.cpu_count() or 1))
+                             seed=cfg["seed"], gapped=cfg["gapped"], threads=min(16, os.cpu_count() or 1),
+                             share=cfg.get("share", 1))
 
 
 def log(*a):
@@ -392,7 +393,7 @@ def bench_sbmm4s(args):
     import torch
     from synth import synthetic_problem, gaussian_psi
     from paper_2305_05581_amd.tns import HeffProblem
-    cfg = CONFIGS["d1024"]
+    cfg = dict(CONFIGS["d1024"], share=8)
     prec = args.only or "f64"
     dt = torch.float64 if prec == "f64" else torch.float32
     dev = torch.device("cuda:0")
@@ -573,6 +574,172 @@ def bench_renorm(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_ttcache(args):
+    """Out-of-HBM products (tree-traversal cache): the D = 1024 workload
+    (L=30, 900 terms, seed 2; each operator pair serving up to 8 terms with
+    different site monomials) with its operator values in pinned host memory,
+    streamed through device caches of 1/8 and 1/2 of their size and of all of
+    it, against the in-HBM product.  Reports the elements copied per product
+    against a per-term load of both operators, the copy rate against a plain
+    pinned host-to-device copy, and sigma against the in-HBM product and the
+    oracle (FP64).  Prints one JSON line."""
+    import torch
+    from synth import gaussian_psi
+    from oracle import heff as oheff
+    from paper_2305_05581_amd.tns import HeffProblem, StreamedHeff
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = dict(CONFIGS["d1024"], share=8)
+    prec = args.only or "f64"
+    dt = torch.float64 if prec == "f64" else torch.float32
+    es = 8 if prec == "f64" else 4
+    P = make_problem(cfg)
+    H = HeffProblem(P, device=dev)
+    psi = gaussian_psi(P, 3)
+    x = torch.from_numpy(psi).to(dev, dtype=dt)
+    flops = H.total_flops
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    ref = H.apply(x, prec)
+    t_hbm = timed(lambda: H.apply(x, prec, out=ref), args.steps)
+    host = torch.from_numpy(np.ascontiguousarray(P.op_vals)).to(dt).pin_memory()
+    # plain pinned copy of all operator values: the link's rate
+    dst = torch.empty(host.numel(), dtype=dt, device=dev)
+    t_copy = timed(lambda: dst.copy_(host, non_blocking=True), 3)
+    link = host.numel() * es / t_copy / 1e9
+    del dst
+    log("ttcache: %d tasks, %.1f GFLOP, operators %.2f GB (%s); in-HBM product %.2f ms; pinned copy %.1f GB/s"
+        % (H.ntasks, flops / 1e9, host.numel() * es / 1e9, prec, t_hbm * 1e3, link))
+    t0 = time.perf_counter()
+    want, thr = oheff.sigma_threaded(P, psi)
+    t_or = time.perf_counter() - t0
+    ref64 = ref.double().cpu().numpy()
+    caches = {}
+    for name, frac in (("eighth", 8), ("half", 2), ("all", 1)):
+        n = (host.numel() + frac - 1) // frac
+        S = StreamedHeff(P, n, prec, device=dev, host_vals=host)
+        y = S.apply(x)
+        t_s = timed(lambda: S.apply(x, out=y), max(2, args.steps // 4))
+        got = y.double().cpu().numpy()
+        caches[name] = {
+            "cache_elems": S.cache_elems, "epochs": S.n_epochs, "loads": S.n_loads,
+            "loaded_GB": round(S.loaded_elems * es / 1e9, 3), "naive_GB": round(S.naive_elems * es / 1e9, 3),
+            "copy_saved": round(1 - S.loaded_elems / max(S.naive_elems, 1), 4),
+            "ms_per_product": round(t_s * 1e3, 2), "tflops": round(flops / t_s / 1e12, 3),
+            "copy_GBps": round(S.loaded_elems * es / t_s / 1e9, 1),
+            "frac_of_link": round(S.loaded_elems * es / t_s / 1e9 / link, 3),
+            "rel_err_vs_in_hbm": float("%.3g" % (np.linalg.norm(got - ref64) / np.linalg.norm(ref64))),
+            "rel_err_vs_oracle": float("%.3g" % (np.linalg.norm(got - want) / np.linalg.norm(want)))}
+        log("cache %-6s %s" % (name, caches[name]))
+        del S
+    head = caches["eighth"]
+    line = {
+        "metric": "out-of-HBM H_eff*psi (tree-traversal cache), copy bytes and rate", "value": head["tflops"],
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": head["ms_per_product"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "d1024: L=30 N=30 2Sz=0 D=1024 per block (mean sector 32, max 256), 900 terms "
+                               "(operator pairs shared by up to 8 terms), seed 2; operator values in pinned host "
+                               "memory, cache 1/8 of them",
+                   "tasks": H.ntasks, "flops_per_step": flops, "operator_GB": round(host.numel() * es / 1e9, 3)},
+        "in_hbm_ms": round(t_hbm * 1e3, 3), "pinned_copy_GBps": round(link, 1), "caches": caches,
+        "roofline": {"bound": "pcie", "achieved": head["copy_GBps"], "peak": round(link, 1), "unit": "GB/s",
+                     "frac": head["frac_of_link"], "peak_note": "plain pinned host-to-device copy of the same values"},
+        "oracle_seconds": round(t_or, 1), "oracle_threads": thr,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_su2(args):
+    """Spin-adapted (SU(2)) products: a synthetic two-block instance of
+    multiplet sectors (N within 4 of 15 per block, 2S <= 6, Gaussian profile
+    of 1024 multiplets per block, at most 160 per sector; about 3230 states per
+    block in U(1) terms), 150 tensor operators per side of rank 0, 1/2 or 1
+    and 900 terms, seed 6, target N = 30, S = 0.  Every precision timed over
+    the same steps; FP64 checked against the oracle's reduced route on the
+    instance cut to its first 40 terms.  Prints one JSON line."""
+    import torch
+    from synth.su2 import su2_synthetic
+    from paper_2305_05581_amd.tns import Su2Heff, KernelTimer
+    from oracle import su2 as osu
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    I = su2_synthetic(9, 1024, 160, 150, 900, (30, 0), seed=6, max_2S=6)
+    t_gen = time.time() - t0
+    t0 = time.time()
+    H = Su2Heff(I, device=dev)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    flops = H.total_flops
+    states = int(sum(int(d) * (int(q[1]) + 1) for d, q in zip(I.dimL, I.qL)))
+    log("su2: %d sectors, psi %d, %d tasks, %.1f GFLOP per product, build %.2f s (generate %.1f s)"
+        % (H.n_sectors, H.psi_dim, H.ntasks, flops / 1e9, t_build, t_gen))
+    psi = np.random.default_rng(3).standard_normal(H.psi_dim)
+    res, outs = {}, {}
+    order = [p for p in ("f64", "f32", "bf16x3") if p != args.prec] + [args.prec]
+    for prec in order:
+        dt = torch.float64 if prec == "f64" else torch.float32
+        x = torch.from_numpy(psi).to(dev, dtype=dt)
+        y = H.apply(x, prec)
+        for _ in range(args.warmup):
+            H.apply(x, prec, out=y)
+        kt = KernelTimer(args.steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            kt.arm()
+            H.apply(x, prec, out=y)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / args.steps
+        ka, kb = np.array(kt.times_ms()).mean(axis=0)
+        kt.close()
+        outs[prec] = y.double()
+        res[prec] = dict(ms_per_step=wall * 1e3, tflops=flops / wall / 1e12,
+                         pct_peak=100 * flops / wall / 1e12 / PEAK[prec], phaseA_ms=float(ka), phaseB_ms=float(kb),
+                         kernel_tflops=flops / ((ka + kb) / 1e3) / 1e12)
+        log("%-6s %8.3f ms/step %7.2f TFLOP/s (%.1f%% of peak; phase A %.3f ms, phase B %.3f ms)"
+            % (prec, wall * 1e3, res[prec]["tflops"], res[prec]["pct_peak"], ka, kb))
+    ref = outs["f64"]
+    for prec in ("f32", "bf16x3"):
+        res[prec]["rel_err_vs_f64"] = float(torch.linalg.norm(outs[prec] - ref) / torch.linalg.norm(ref))
+    # the oracle (reduced route) on the instance cut to its first 40 terms
+    import dataclasses
+    cut = dataclasses.replace(I, term_L=I.term_L[:40], term_R=I.term_R[:40], term_coef=I.term_coef[:40])
+    Hc = Su2Heff(cut, device=dev)
+    got = Hc.apply(torch.from_numpy(psi).to(dev), "f64").cpu().numpy()
+    t = time.perf_counter()
+    want = osu.sigma_reduced(cut, psi)
+    t_or = time.perf_counter() - t
+    parity = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    log("oracle check (first 40 terms): FP64 rel err %.2e (%.1f s)" % (parity, t_or))
+    head = res[args.prec]
+    line = {
+        "metric": "spin-adapted H_eff*psi TFLOP/s (% MFMA peak)", "value": round(head["tflops"], 3),
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "su2: synthetic SU(2) two-block instance, 1024 multiplets per block (%d states), "
+                               "2S <= 6, 150 operators per side, 900 terms, N=30 S=0, seed 6" % states,
+                   "sectors": H.n_sectors, "psi_dim": H.psi_dim, "tasks": H.ntasks, "flops_per_step": flops},
+        "precisions": {k: {kk: float("%.4g" % vv) for kk, vv in v.items()} for k, v in res.items()},
+        "oracle_parity_f64": {"terms": 40, "rel_frobenius": parity},
+        "roofline": {"bound": "mfma", "achieved_both_phases": round(head["kernel_tflops"], 3),
+                     "peak": round(PEAK[args.prec], 1), "unit": "TFLOP/s",
+                     "frac": round(head["kernel_tflops"] / PEAK[args.prec], 4)},
+        "setup_seconds": {"generate": round(t_gen, 2), "build": round(t_build, 2)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,7 +747,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "f32", "f64"])
     ap.add_argument("--config", default="d4096",
-                    choices=sorted(CONFIGS) + ["batch64", "grad1024", "sbmm4s", "renorm"],
+                    choices=sorted(CONFIGS) + ["batch64", "grad1024", "sbmm4s", "renorm", "ttcache", "su2"],
                     help="batch64: many uneven instances, one launch per phase vs one product at a time; "
                          "grad1024: forward and backward at L=30, D=1024; sbmm4s: the paper's batched-GEMM "
                          "scheme with library GEMMs against the fused kernels at L=30, D=1024")
@@ -613,6 +780,12 @@ def main():
         return
     if args.config == "sbmm4s":
         bench_sbmm4s(args)
+        return
+    if args.config == "ttcache":
+        bench_ttcache(args)
+        return
+    if args.config == "su2":
+        bench_su2(args)
         return
     if args.config == "renorm":
         bench_renorm(args)

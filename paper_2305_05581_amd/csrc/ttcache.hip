@@ -2,12 +2,13 @@
 // stream through a device cache managed as the paper's tree-traversal stack
 // (Section II.B, Alg. 1): the terms form a data dependency tree (level 1 the
 // left operator, level 2 the right operator, leaves the terms), a depth-first
-// walk loads a node's operator on top of the stack and pops it once the node's
-// subtree is done, so the left operator stays resident for all of its right
-// partners and allocation is a moving offset.  Execution is deferred until
-// the stack is full or a left subtree ends (an epoch): then every pending
-// term runs as one product (tns_apply_heff, accumulating into sigma) whose
-// task list was built at plan time with the blocks' cache offsets.
+// walk loads a node's operator on top of the stack, so the left operator
+// stays resident for all of its right partners and allocation is a moving
+// offset.  Execution is deferred (one product of a few terms would not fill
+// the GPU) until the next operator does not fit (an epoch): then every
+// pending term runs as one product (tns_apply_heff, accumulating into sigma)
+// whose task list was built at plan time with the blocks' cache offsets, and
+// the space of the nodes already left is given back.
 #include <algorithm>
 #include <vector>
 
@@ -59,70 +60,136 @@ static void op_extents(const tns_problem *P, std::vector<int64_t> &lo, std::vect
     if (hi[o] < 0) lo[o] = hi[o] = 0;  // an operator without blocks loads nothing
 }
 
-// Depth-first walk of the dependency tree with the stack cache.  Returns
-// TNS_ERR_WORKSPACE when one left operator and one right operator together
-// exceed the cache.
-static tns_status tt_walk(const tns_problem *P, int64_t cap, std::vector<TtPlanEpoch> &epochs, int64_t *naive) {
+// Depth-first walk of the dependency tree with the stack cache: level 1 the
+// operator of side `lead` (0 left, 1 right) of each term, level 2 the other
+// one, leaves the terms.  Entering a node loads its operator at the top of
+// the stack unless it is still there; the terms are collected, not run.
+// Leaving a node would let its siblings reuse the space, but the collected
+// terms still read it, so the space is given back only when they run: a
+// level-1 subtree whose new operators do not all fit above the stack starts
+// at the bottom after the pending terms have formed an epoch, and inside a
+// subtree an operator that does not fit makes an epoch and pops back to the
+// level-1 operator.  Every level-1 operator is thus copied once and every
+// level-2 operator at most once per parent (never more than a per-term copy),
+// operators still on the stack are reused across subtrees, and a cache that
+// holds everything copies each operator once and runs one product.  Returns
+// TNS_ERR_WORKSPACE when two operators of one term together exceed the cache.
+static tns_status tt_walk(const tns_problem *P, int64_t cap, int lead, std::vector<TtPlanEpoch> &epochs,
+                          int64_t *naive, int64_t *loaded) {
   std::vector<int64_t> lo, hi;
   op_extents(P, lo, hi);
   auto size_of = [&](int o) { return o >= 0 ? (hi[o] - lo[o] + 7) / 8 * 8 : 0; };
+  auto ext = [&](int o) { return o >= 0 ? hi[o] - lo[o] : 0; };
+  const int32_t *first = lead ? P->term_R : P->term_L, *second = lead ? P->term_L : P->term_R;
   std::vector<int> order(P->nTerms);
   for (int t = 0; t < P->nTerms; ++t) order[t] = t;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return P->term_L[a] != P->term_L[b] ? P->term_L[a] < P->term_L[b] : P->term_R[a] < P->term_R[b];
+    return first[a] != first[b] ? first[a] < first[b] : second[a] < second[b];
   });
-  *naive = 0;
-  for (int t = 0; t < P->nTerms; ++t) *naive += size_of(P->term_L[t]) + size_of(P->term_R[t]);
-  struct Slot { int op; int64_t off, size; };
-  std::vector<Slot> stack;
+  *naive = *loaded = 0;
+  for (int t = 0; t < P->nTerms; ++t) *naive += ext(P->term_L[t]) + ext(P->term_R[t]);
+  std::vector<int64_t> at(P->nOps, -1);  // cache offset of each operator on the stack
+  std::vector<int> on;                   // operators on the stack
   int64_t top = 0;
   TtPlanEpoch cur;
   auto push = [&](int o) {
-    const int64_t sz = size_of(o);
-    stack.push_back({o, top, sz});
-    if (sz) cur.loads.push_back({lo[o], top, hi[o] - lo[o]});
-    top += sz;
-  };
-  auto resident = [&](int o) {
-    for (auto &s : stack)
-      if (s.op == o) return true;
-    return false;
+    at[o] = top;
+    on.push_back(o);
+    if (ext(o)) {
+      cur.loads.push_back({lo[o], top, ext(o)});
+      *loaded += ext(o);
+    }
+    top += size_of(o);
   };
   auto flush = [&]() {
-    if (cur.terms.empty() && cur.loads.empty()) return;
+    if (cur.terms.empty()) return;
+    // one copy for operators adjacent both in host memory and in the cache
+    std::vector<TtLoad> merged;
+    for (auto &l : cur.loads) {
+      if (!merged.empty()) {
+        TtLoad &m = merged.back();
+        const int64_t step = (m.elems + 7) / 8 * 8;  // its footprint: the gap up to the next is in range
+        if (l.host_off == m.host_off + step && l.cache_off == m.cache_off + step) {
+          m.elems = step + l.elems;
+          continue;
+        }
+      }
+      merged.push_back(l);
+    }
+    cur.loads.swap(merged);
     cur.resident.clear();
-    for (auto &s : stack) cur.resident.push_back({s.op, s.off});
+    for (int o : on) cur.resident.push_back({o, at[o]});
     epochs.push_back(cur);
     cur = TtPlanEpoch();
   };
+  // room for operator o (o1: the level-1 operator that must stay resident)
+  auto room = [&](int o, int o1) -> bool {
+    if (top + size_of(o) <= cap) return true;
+    bool kept = false;
+    if (cur.terms.empty()) {  // nothing pending reads this epoch's copies: drop them
+      bool bottom = false;
+      for (auto &l : cur.loads) {
+        *loaded -= l.elems;
+        bottom = bottom || l.cache_off == 0;
+      }
+      cur.loads.clear();
+      kept = o1 >= 0 && at[o1] == 0 && !bottom;  // a copy made before this epoch stays valid
+    } else {
+      flush();
+      kept = o1 >= 0 && at[o1] == 0;  // its copy at the bottom stays valid
+    }
+    for (int x : on) at[x] = -1;
+    on.clear();
+    top = 0;
+    if (o1 >= 0) {
+      if (size_of(o1) + size_of(o) > cap) return false;
+      if (kept) {
+        at[o1] = 0;
+        on.push_back(o1);
+        top = size_of(o1);
+      } else {
+        push(o1);  // reloaded at the bottom
+      }
+    }
+    return size_of(o) <= cap;
+  };
   size_t i = 0;
   while (i < order.size()) {
-    const int oL = P->term_L[order[i]];
-    // level 1: the left operator at the bottom of the stack
-    stack.clear();
-    top = 0;
-    if (oL >= 0) {
-      if (size_of(oL) > cap) return TNS_ERR_WORKSPACE;
-      push(oL);
+    const int o1 = first[order[i]];
+    size_t end = i;
+    while (end < order.size() && first[order[end]] == o1) ++end;
+    // the subtree's new operators; when they do not all fit above the stack,
+    // start it at the bottom (so that o1 is never copied twice)
+    int64_t need = o1 >= 0 ? size_of(o1) : 0;
+    for (size_t u = i; u < end; ++u) {
+      const int o2 = second[order[u]];
+      if (o2 >= 0 && at[o2] < 0 && (u == i || second[order[u - 1]] != o2)) need += size_of(o2);
     }
-    const size_t base = stack.size();
-    const int64_t base_top = top;
-    while (i < order.size() && P->term_L[order[i]] == oL) {
-      const int oR = P->term_R[order[i]];
-      if (oR >= 0 && oR != oL && !resident(oR)) {
-        if (top + size_of(oR) > cap) {
-          flush();  // run what is pending, then pop back to the left operator
-          stack.resize(base);
-          top = base_top;
-          if (top + size_of(oR) > cap) return TNS_ERR_WORKSPACE;
-        }
-        push(oR);
+    if (top + need > cap) {
+      if (cur.terms.empty()) {
+        for (auto &l : cur.loads) *loaded -= l.elems;
+        cur.loads.clear();
+      } else {
+        flush();
       }
-      while (i < order.size() && P->term_L[order[i]] == oL && P->term_R[order[i]] == oR)
-        cur.terms.push_back(order[i++]);
+      for (int x : on) at[x] = -1;
+      on.clear();
+      top = 0;
     }
-    flush();
+    if (o1 >= 0) {
+      if (size_of(o1) > cap) return TNS_ERR_WORKSPACE;
+      push(o1);
+    }
+    while (i < end) {
+      const int o2 = second[order[i]];
+      if (o2 >= 0 && at[o2] < 0) {
+        if (!room(o2, o1)) return TNS_ERR_WORKSPACE;
+        push(o2);
+      }
+      while (i < end && second[order[i]] == o2) cur.terms.push_back(order[i++]);
+    }
   }
+  flush();
   return TNS_OK;
 }
 
@@ -172,12 +239,21 @@ static tns_status tt_plan(const tns_problem *P, int64_t cap, std::vector<TtPlanE
   tns_status s = validate_problem(P, &nmax, &maxdim);
   if (s != TNS_OK) return s;
   if (cap <= 0) return TNS_ERR_ARG;
-  s = tt_walk(P, (cap / 8) * 8, epochs, naive);
+  // the tree is a choice: level 1 the left or the right operators; keep the
+  // one that copies fewer elements (left on a tie)
+  const int64_t c8 = (cap / 8) * 8;
+  std::vector<TtPlanEpoch> alt;
+  int64_t nv2 = 0, ld2 = 0;
+  s = tt_walk(P, c8, 0, epochs, naive, loaded);
+  const tns_status s2 = tt_walk(P, c8, 1, alt, &nv2, &ld2);
+  if (s2 == TNS_OK && (s != TNS_OK || ld2 < *loaded)) {
+    epochs.swap(alt);
+    *loaded = ld2;
+    s = TNS_OK;
+  }
   if (s != TNS_OK) return s;
-  *loaded = 0;
   ws.clear();
   for (auto &e : epochs) {
-    for (auto &l : e.loads) *loaded += l.elems;
     TtSub sub;
     tt_sub(P, e, cap, sub);
     int32_t nm = 0, md = 0;

@@ -68,6 +68,24 @@ class TnsRenormPlan(ctypes.Structure):
                 ("tl", TnsTasklist), ("opaque", ctypes.c_uint8 * 1024)]
 
 
+class TnsTtcachePlan(ctypes.Structure):
+    _fields_ = [("n_epochs", _i64), ("n_loads", _i64), ("loaded_elems", _i64), ("naive_elems", _i64),
+                ("ntasks", _i64), ("total_flops", _i64), ("cache_elems", _i64), ("opaque", ctypes.c_uint8 * 256)]
+
+
+class TnsSu2Problem(ctypes.Structure):
+    _fields_ = [("nL", _i32), ("nR", _i32), ("nOps", _i32), ("nBlk", _i32), ("nTerms", _i32), ("target_N", _i32),
+                ("target_2S", _i32), ("n_vals", _i64)] + \
+               [(n, _P) for n in ("qL", "dimL", "qR", "dimR", "op_side", "op_2k", "op_dN", "blk_op", "blk_in",
+                                  "blk_out", "blk_rows", "blk_cols", "blk_ld", "blk_off", "term_L", "term_R",
+                                  "term_coef")]
+
+
+class TnsSu2Plan(ctypes.Structure):
+    _fields_ = [("n_sectors", _i64), ("psi_dim", _i64), ("ntasks", _i64), ("total_flops", _i64),
+                ("tl", TnsTasklist)]
+
+
 EXPORTS = ("tns_tasklist_workspace_bytes", "tns_build_tasklist", "tns_apply_workspace_bytes",
            "tns_prepare_operands", "tns_apply_heff", "tns_backward_workspace_bytes", "tns_apply_heff_backward",
            "tns_davidson_workspace_bytes", "tns_davidson", "tns_status_string")
@@ -149,6 +167,26 @@ def library(path=LIB_PATH):
         L.tns_renorm_apply_workspace_bytes.argtypes = [ctypes.POINTER(TnsRenormPlan), ctypes.c_int]
         L.tns_renormalize.restype = ctypes.c_int
         L.tns_renormalize.argtypes = [ctypes.POINTER(TnsRenormPlan), ctypes.c_int, _P, _P, _P, _P, sz, _P]
+    if hasattr(L, "tns_ttcache_build"):
+        L.tns_ttcache_sizes.restype = ctypes.c_int
+        L.tns_ttcache_sizes.argtypes = [ctypes.POINTER(TnsProblem), _i64, ctypes.POINTER(ctypes.c_size_t),
+                                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i64)]
+        L.tns_ttcache_build.restype = ctypes.c_int
+        L.tns_ttcache_build.argtypes = [ctypes.POINTER(TnsProblem), _i64, _P, sz, _P, sz,
+                                        ctypes.POINTER(TnsTtcachePlan), _P]
+        L.tns_ttcache_apply_workspace_bytes.restype = sz
+        L.tns_ttcache_apply_workspace_bytes.argtypes = [ctypes.POINTER(TnsTtcachePlan), ctypes.c_int]
+        L.tns_apply_heff_streamed.restype = ctypes.c_int
+        L.tns_apply_heff_streamed.argtypes = [ctypes.POINTER(TnsTtcachePlan), ctypes.c_int, _P, _P, _P, _P, _P, sz,
+                                              _P]
+    if hasattr(L, "tns_su2_build"):
+        L.tns_su2_workspace_bytes.restype = sz
+        L.tns_su2_workspace_bytes.argtypes = [ctypes.POINTER(TnsSu2Problem)]
+        L.tns_su2_tables.restype = ctypes.c_int
+        L.tns_su2_tables.argtypes = [ctypes.POINTER(TnsSu2Problem), _P, _P, _P, _i64, _P, _P, _i64,
+                                     ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+        L.tns_su2_build.restype = ctypes.c_int
+        L.tns_su2_build.argtypes = [ctypes.POINTER(TnsSu2Problem), _P, sz, ctypes.POINTER(TnsSu2Plan), _P]
     L.tns_status_string.restype = ctypes.c_char_p
     L.tns_status_string.argtypes = [ctypes.c_int]
     _lib = L
@@ -634,3 +672,146 @@ class RenormStep:
         _check(L.tns_renormalize(ctypes.byref(self.plan), p, _ptr(op_vals), _ptr(u_vals), _ptr(out), _ptr(ws),
                                  ws.numel(), _stream()), "tns_renormalize")
         return out
+
+
+def ttcache_sizes(P, cache_elems):
+    """``(host_bytes, device_bytes, n_epochs)`` of a tree-traversal cache plan
+    (host only); raises :class:`TnsError` when two operators of one term do not
+    fit the cache together or the problem fails validation."""
+    cp, host = problem_struct(P)
+    hb, db, ne = ctypes.c_size_t(0), ctypes.c_size_t(0), _i64(0)
+    _check(library().tns_ttcache_sizes(ctypes.byref(cp), int(cache_elems), ctypes.byref(hb), ctypes.byref(db),
+                                       ctypes.byref(ne)), "tns_ttcache_sizes")
+    return int(hb.value), int(db.value), int(ne.value)
+
+
+class StreamedHeff:
+    """H_eff psi with the operator values in pinned host memory, streamed
+    through a device cache of ``cache_elems`` elements by the tree-traversal
+    stack (``tns_ttcache_build`` / ``tns_apply_heff_streamed``); FP64 or FP32.
+    psi and sigma stay on the device."""
+
+    def __init__(self, P, cache_elems, prec="f64", device="cuda", host_vals=None):
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        self.prec = prec_id(prec)
+        if self.prec not in (F64, F32):
+            raise ValueError("streamed products run in f64 or f32")
+        dt = torch.float64 if self.prec == F64 else torch.float32
+        L = library()
+        cp, self._host = problem_struct(P)
+        self.cprob = cp
+        hb, db, _ = ttcache_sizes(P, cache_elems)
+        self._hbuf = (ctypes.c_uint8 * max(hb, 64))()
+        self.ws_build = torch.empty(max(db, 256), dtype=torch.uint8, device=dev)
+        self.plan = TnsTtcachePlan()
+        with torch.cuda.device(dev):
+            _check(L.tns_ttcache_build(ctypes.byref(cp), int(cache_elems), ctypes.cast(self._hbuf, _P), hb,
+                                       _ptr(self.ws_build), self.ws_build.numel(), ctypes.byref(self.plan),
+                                       _stream()), "tns_ttcache_build")
+        if host_vals is None:
+            host_vals = torch.from_numpy(np.ascontiguousarray(P.op_vals)).to(dt).pin_memory()
+        if host_vals.dtype != dt or host_vals.device.type != "cpu" or not host_vals.is_contiguous():
+            raise ValueError("host values must be a contiguous CPU %s tensor" % dt)
+        self.host_vals = host_vals
+        self.cache = torch.empty(max(int(cache_elems), 8), dtype=dt, device=dev)
+        n = L.tns_ttcache_apply_workspace_bytes(ctypes.byref(self.plan), self.prec)
+        self.ws = torch.empty(int(max(n, 256)), dtype=torch.uint8, device=dev)
+        self.psi_dim = int(P.psi_off[-1])
+        self.dtype = dt
+        for k in ("n_epochs", "n_loads", "loaded_elems", "naive_elems", "ntasks", "total_flops", "cache_elems"):
+            setattr(self, k, int(getattr(self.plan, k)))
+
+    def apply(self, psi, out=None):
+        """sigma := H_eff psi (one copy per cache load, one product per epoch)."""
+        if psi.dtype != self.dtype or psi.device != self.device or psi.numel() != self.psi_dim \
+                or not psi.is_contiguous():
+            raise ValueError("psi must be a contiguous %s tensor of %d elements on %s"
+                             % (self.dtype, self.psi_dim, self.device))
+        if out is None:
+            out = torch.empty(self.psi_dim, dtype=self.dtype, device=self.device)
+        _check(library().tns_apply_heff_streamed(ctypes.byref(self.plan), self.prec, _ptr(self.host_vals),
+                                                 _ptr(self.cache), _ptr(psi), _ptr(out), _ptr(self.ws),
+                                                 self.ws.numel(), _stream()), "tns_apply_heff_streamed")
+        return out
+
+
+_SU2_TABLES = (("qL", np.int32), ("dimL", np.int32), ("qR", np.int32), ("dimR", np.int32), ("op_side", np.int32),
+               ("op_2k", np.int32), ("op_dN", np.int32), ("blk_op", np.int32), ("blk_in", np.int32),
+               ("blk_out", np.int32), ("blk_rows", np.int32), ("blk_cols", np.int32), ("blk_ld", np.int32),
+               ("blk_off", np.int64), ("term_L", np.int32), ("term_R", np.int32), ("term_coef", np.float64))
+
+
+def su2_problem_struct(I):
+    """``(tns_su2_problem, host arrays)`` of a spin-adapted instance; the
+    arrays back the struct's pointers and must outlive its use."""
+    host = {}
+    cp = TnsSu2Problem()
+    cp.nL, cp.nR, cp.nOps = len(I.dimL), len(I.dimR), len(I.op_side)
+    cp.nBlk, cp.nTerms = len(I.blk_op), len(I.term_L)
+    cp.target_N, cp.target_2S = int(I.target[0]), int(I.target[1])
+    cp.n_vals = len(I.op_vals)
+    for name, dt in _SU2_TABLES:
+        a = np.ascontiguousarray(getattr(I, name), dtype=dt)
+        host[name] = a
+        setattr(cp, name, a.ctypes.data_as(ctypes.c_void_p) if a.size else None)
+    return cp, host
+
+
+def su2_workspace_bytes(I):
+    """Build-workspace bytes of a spin-adapted problem, 0 when it fails the
+    library's host validation."""
+    cp, host = su2_problem_struct(I)
+    return int(library().tns_su2_workspace_bytes(ctypes.byref(cp)))
+
+
+def su2_tables(I):
+    """Host-only tables of the library: ``(sec_L, sec_R, psi_off, tasks,
+    task_ptr)`` (tasks as :data:`TASK_DTYPE`)."""
+    L = library()
+    cp, host = su2_problem_struct(I)
+    ns, nt = _i64(0), _i64(0)
+    _check(L.tns_su2_tables(ctypes.byref(cp), None, None, None, 0, None, None, 0, ctypes.byref(ns),
+                            ctypes.byref(nt)), "tns_su2_tables")
+    n, m = int(ns.value), int(nt.value)
+    sl, sr = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    off, ptr = np.zeros(n + 1, np.int64), np.zeros(n + 1, np.int32)
+    tasks = np.zeros(max(m, 1), dtype=TASK_DTYPE)
+    c = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(L.tns_su2_tables(ctypes.byref(cp), c(sl), c(sr), c(off), n, c(tasks), c(ptr), m, ctypes.byref(ns),
+                            ctypes.byref(nt)), "tns_su2_tables")
+    return sl, sr, off, tasks[:m], ptr
+
+
+class Su2Heff(HeffProblem):
+    """A spin-adapted problem resident on the GPU (``tns_su2_build``): the
+    plan's task list carries the recoupling scalars, so products, operand
+    copies and Davidson are :class:`HeffProblem`'s."""
+
+    def __init__(self, I, device="cuda"):
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        self.P = I
+        L = library()
+        cp, self._host = su2_problem_struct(I)
+        self.cprob = cp
+        nbytes = L.tns_su2_workspace_bytes(ctypes.byref(cp))
+        if nbytes == 0:
+            raise ValueError("spin-adapted problem failed host validation")
+        self.ws_build = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        self.plan = TnsSu2Plan()
+        with torch.cuda.device(dev):
+            _check(L.tns_su2_build(ctypes.byref(cp), _ptr(self.ws_build), int(nbytes), ctypes.byref(self.plan),
+                                   _stream()), "tns_su2_build")
+        self.tl = self.plan.tl
+        self.vals64 = torch.from_numpy(np.ascontiguousarray(I.op_vals)).to(dev)
+        self._ops = {F64: self.vals64}
+        self._ws = {}
+        self.psi_dim = int(self.plan.psi_dim)
+        self.ntasks = int(self.plan.ntasks)
+        self.total_flops = int(self.plan.total_flops)
+        self.n_sectors = int(self.plan.n_sectors)

@@ -346,7 +346,7 @@ SITE_ENERGIES = ((mono_id(1, 0), 0, 0.25), (mono_id(0, 1), 0, 0.5),
 
 
 def synthetic_problem(L, N, twoSz, D, mean, dmax, K, seed, gapped=False, lam=0.05,
-                      threads=None, with_values=True):
+                      threads=None, with_values=True, share=1):
     """Seeded synthetic block-sparse two-site problem.
 
     * Left block = ``L//2 - 1`` orbitals, right block the rest minus the two
@@ -362,6 +362,10 @@ def synthetic_problem(L, N, twoSz, D, mean, dmax, K, seed, gapped=False, lam=0.0
       size ``d`` whose distance from half filling is ``r``), spin-dependent
       site energies (:data:`SITE_ENERGIES`) and the random terms scaled by
       ``lam``, which isolates the lowest eigenvalue.
+    * ``share`` > 1: each random operator pair serves up to ``share`` terms
+      (the first monomial pair and further distinct ones of the same total
+      shift), as the normal and complementary operators of a block serve
+      several site monomials; the term count stays ``K``.
     """
     nl = L // 2 - 1
     nr = L - nl - 2
@@ -396,15 +400,25 @@ def synthetic_problem(L, N, twoSz, D, mean, dmax, K, seed, gapped=False, lam=0.0
         ops_meta += [(0, (-dL[0], -dL[1])), (1, (-dR[0], -dR[1]))]
         ops_shape += [[(o, i, c, r) for (i, o, r, c) in shL], [(o, i, c, r) for (i, o, r, c) in shR]]
         ops_src += [("adj", oL), ("adj", oR)]
-        ma2, ga = mono_adjoint(ma)
-        mb2, gb = mono_adjoint(mb)
-        pL, pa, pb = abs(dL[0]) % 2, mono_parity(ma), mono_parity(mb)
-        pR = abs(dR[0]) % 2
-        par = [pL, pa, pb, pR]
-        npair = sum(par[x] * par[y] for x in range(4) for y in range(x + 1, 4))
-        g = (-1.0 if npair % 2 else 1.0) * ga * gb
-        terms.append((oL, ma, mb, oR, coef))
-        terms.append((oL + 2, ma2, mb2, oR + 2, coef * g))
+        pL, pR = abs(dL[0]) % 2, abs(dR[0]) % 2
+        def pair_terms(ma, mb):
+            ma2, ga = mono_adjoint(ma)
+            mb2, gb = mono_adjoint(mb)
+            pa, pb = mono_parity(ma), mono_parity(mb)
+            par = [pL, pa, pb, pR]
+            npair = sum(par[x] * par[y] for x in range(4) for y in range(x + 1, 4))
+            g = (-1.0 if npair % 2 else 1.0) * ga * gb
+            return [(oL, ma, mb, oR, coef), (oL + 2, ma2, mb2, oR + 2, coef * g)]
+
+        terms += pair_terms(ma, mb)
+        if share > 1:
+            tot = (sa[0] + sb[0], sa[1] + sb[1])
+            alt = [(x, y) for x in range(16) for y in range(16) if (x, y) != (ma, mb)
+                   and (MONO_SHIFT[x][0] + MONO_SHIFT[y][0], MONO_SHIFT[x][1] + MONO_SHIFT[y][1]) == tot]
+            for k in rng.permutation(len(alt))[:share - 1]:
+                if len(terms) >= 2 * npairs:
+                    break
+                terms += pair_terms(*alt[int(k)])
     if gapped:
         for side, (q, dims) in enumerate(((qL, dimL), (qR, dimR))):
             ops_meta.append((side, (0, 0)))

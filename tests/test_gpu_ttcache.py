@@ -1,0 +1,104 @@
+"""GPU parity of the out-of-HBM product (tree-traversal cache, Section II.B,
+Alg. 1): operator values in pinned host memory, streamed through a device
+cache of a given size, sigma against the oracle's FP64 sigma and against the
+in-HBM product, for caches from every operator down to the smallest that
+holds the two operators of any one term; the copied elements between every
+operator once (what a cache holding everything copies, in one product) and
+a per-term copy of both operators."""
+import numpy as np
+import pytest
+import torch
+
+from synth import synthetic_problem, gaussian_psi, molecular_integrals
+from oracle import heff as oheff
+from oracle.blocks import Construction
+
+from gpu_common import say, rel, to_dev, SIGMA_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _instances():
+    return {
+        "tiny": lambda: synthetic_problem(10, 10, 0, 24, 3, 8, 40, seed=77),
+        "cfg1_exact": lambda: Construction(*molecular_integrals(8, 1), 8, 0).problem(),
+        "ragged": lambda: synthetic_problem(22, 22, 0, 700, 23, 187, 120, seed=12),
+        # operator pairs serving up to six terms each (different site monomials)
+        "shared": lambda: synthetic_problem(22, 22, 0, 700, 23, 187, 120, seed=12, share=6),
+    }
+
+
+def op_sizes(P):
+    """Elements of each operator's value range (first to end of last block),
+    and that rounded up to 8 (its footprint in the cache)."""
+    lo = np.full(P.nOps, np.iinfo(np.int64).max)
+    hi = np.full(P.nOps, -1)
+    for b in range(P.nBlk):
+        o = int(P.blk_op[b])
+        lo[o] = min(lo[o], int(P.blk_off[b]))
+        hi[o] = max(hi[o], int(P.blk_off[b]) + int(P.blk_rows[b]) * int(P.blk_ld[b]))
+    ext = np.where(hi >= 0, hi - lo, 0)
+    return ext, (ext + 7) // 8 * 8
+
+
+@pytest.fixture(scope="module")
+def built():
+    from paper_2305_05581_amd.tns import HeffProblem
+    out = {}
+    for name, mk in _instances().items():
+        say("ttcache build", name)
+        P = mk()
+        psi = gaussian_psi(P, 3)
+        tasks, _ = oheff.task_table(P)
+        ref = oheff.sigma(P, psi, [tuple(t) for t in tasks.tolist()])
+        out[name] = (P, HeffProblem(P), psi, ref)
+    return out
+
+
+def _caches(P):
+    ext, fp = op_sizes(P)
+    pair = max((int(fp[a]) if a >= 0 else 0) + (int(fp[b]) if b >= 0 else 0) for a, b in zip(P.term_L, P.term_R))
+    full = max(int(fp.sum()), 8)
+    return {"all": full, "quarter": max(pair, full // 4), "pair": max(pair, 8)}
+
+
+@pytest.mark.parametrize("cache", ["all", "quarter", "pair"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", list(_instances()))
+def test_streamed_parity(built, name, prec, cache):
+    from paper_2305_05581_amd.tns import StreamedHeff
+    P, H, psi, ref = built[name]
+    n = _caches(P)[cache]
+    S = StreamedHeff(P, n, prec)
+    say("ttcache", name, prec, cache, "cache", n, "epochs", S.n_epochs, "loads", S.n_loads,
+        "loaded", S.loaded_elems, "naive", S.naive_elems)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    x = to_dev(psi, dt)
+    got = S.apply(x)
+    inhbm = H.apply(x, prec)
+    torch.cuda.synchronize()
+    e_or = rel(got.cpu().numpy(), ref)
+    e_in = rel(got.cpu().numpy(), inhbm.cpu().numpy())
+    say("  rel err vs oracle %.2e, vs in-HBM product %.2e" % (e_or, e_in))
+    assert e_or <= SIGMA_TOL[prec]
+    assert e_in <= SIGMA_TOL[prec]
+    assert S.ntasks == H.ntasks and S.total_flops == H.total_flops
+    ext, fp = op_sizes(P)
+    naive = sum((int(ext[a]) if a >= 0 else 0) + (int(ext[b]) if b >= 0 else 0) for a, b in zip(P.term_L, P.term_R))
+    used = np.unique(np.concatenate([P.term_L, P.term_R]))
+    assert S.naive_elems == naive
+    assert int(ext[used[used >= 0]].sum()) <= S.loaded_elems <= naive
+    if cache == "all":  # every operator copied once, all terms in one product
+        assert S.loaded_elems == int(ext[used[used >= 0]].sum())
+        assert S.n_epochs == 1
+
+
+def test_streamed_deterministic(built):
+    from paper_2305_05581_amd.tns import StreamedHeff
+    P, H, psi, ref = built["ragged"]
+    S = StreamedHeff(P, _caches(P)["pair"], "f32")
+    x = to_dev(psi, torch.float32)
+    a = S.apply(x)
+    b = S.apply(x)
+    assert S.n_epochs > 1
+    assert torch.equal(a, b)

@@ -92,3 +92,33 @@ def test_renorm_validation(lib_ok):
     keep = R.keep.copy()
     keep[0] = R.full[0] + 1
     assert _rn_bytes(dataclasses.replace(R, keep=keep)) == 0
+
+
+def test_ttcache_plan_sizes(lib_ok, base):
+    """Tree-traversal cache plans (host only): a cache holding everything runs
+    one product, the smallest one holding the two operators of any term runs
+    several, and a cache below that size, an empty cache or a malformed
+    problem are rejected."""
+    from paper_2305_05581_amd.tns import ttcache_sizes, TnsError
+    P = synthetic_problem(16, 16, 0, 96, 8, 24, 60, seed=5)
+    lo = np.full(P.nOps, np.iinfo(np.int64).max)
+    hi = np.full(P.nOps, -1)
+    for b in range(P.nBlk):
+        o = int(P.blk_op[b])
+        lo[o] = min(lo[o], int(P.blk_off[b]))
+        hi[o] = max(hi[o], int(P.blk_off[b]) + int(P.blk_rows[b]) * int(P.blk_ld[b]))
+    fp = np.where(hi >= 0, (hi - lo + 7) // 8 * 8, 0)
+    pair = max((int(fp[a]) if a >= 0 else 0) + (int(fp[b]) if b >= 0 else 0) for a, b in zip(P.term_L, P.term_R))
+    hb, db, e_all = ttcache_sizes(P, int(fp.sum()))
+    assert hb > 0 and db > 0 and e_all == 1  # everything fits: one product
+    _, _, e_pair = ttcache_sizes(P, pair)
+    # the smallest cache holds one term's operators: at least the copies of the
+    # largest operators' terms run apart
+    assert e_pair > 1
+    for cap in (pair - 8, 0):
+        with pytest.raises(TnsError):
+            ttcache_sizes(P, cap)
+    tl = P.term_L.copy()
+    tl[0] = P.nOps
+    with pytest.raises(TnsError):
+        ttcache_sizes(_with(P, term_L=tl), int(fp.sum()))
