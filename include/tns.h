@@ -396,6 +396,67 @@ size_t tns_ttcache_apply_workspace_bytes(const tns_ttcache_plan *plan, tns_prec 
 tns_status tns_apply_heff_streamed(const tns_ttcache_plan *plan, tns_prec prec, const void *host_vals, void *cache,
                                    const void *psi, void *sigma, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Spin-adapted (SU(2)) two-block products (Section IV.E).  Each block's
+ * sectors are spin multiplets q = (N, 2S), ascending, holding dim multiplets
+ * (one row per multiplet: its highest-weight state M = S).  Operators are
+ * tensor operators of rank k (op_2k = 2k) changing N by op_dN (odd exactly for
+ * half-integer k), given by reduced blocks (out x in, rows padded to blk_ld,
+ * at blk_off in the value array, both multiples of 8 elements; at most one
+ * block per (op, in, out); |S_in - k| <= S_out <= S_in + k) in the
+ * Clebsch-Gordan convention <j' m'| T_q |j m> = <j m; k q | j' m'> <j'||T||j>.
+ * A term is coef [T_L x T_R]^0 = coef sum_q <k q; k -q | 0 0> T_L,q T_R,-q
+ * (left factor first; -1 = identity, rank 0; equal ranks, opposite dN).
+ * Wavefunction sectors: the pairs (iL, iR) with N_L + N_R = target_N and
+ * |S_L - S_R| <= S <= S_L + S_R, ascending (iL major), each a dimL[iL] x
+ * dimR[iR] row-major matrix over the coupled states
+ * sum_mL <S_L mL; S_R S-mL | S S> |a S_L mL> |b S_R S-mL>.
+ * Each task of Eq. (2) (term, input sector, one reduced block per side) gets
+ * alpha = coef x W x (-1)^(p_R N_L): W, the precalculated recoupling scalar
+ * of the sectors' spins and the rank, sum_{mL, q} <S_L' mL+q; S_R' S-mL-q|S S>
+ * <S_L mL; S_R S-mL|S S> <k q; k -q|0 0> <S_L mL; k q|S_L' mL+q>
+ * <S_R S-mL; k -q|S_R' S-mL-q>, and the fermionic sign of the right factor's
+ * parity p_R and the input's left electrons N_L.  Tasks with W = 0 are left
+ * out; the rest is the U(1) path: the plan's task list runs on
+ * tns_apply_heff (every precision, operand copies from tns_prepare_operands
+ * over the value array) and tns_davidson. */
+typedef struct {
+  int32_t nL, nR, nOps, nBlk, nTerms;
+  int32_t target_N, target_2S;
+  int64_t n_vals;
+  const int32_t *qL, *dimL;       /* [2 nL] (N, 2S) ascending, [nL] multiplets      */
+  const int32_t *qR, *dimR;       /* [2 nR], [nR]                                    */
+  const int32_t *op_side;         /* [nOps] 0 left, 1 right                          */
+  const int32_t *op_2k, *op_dN;   /* [nOps] twice the rank, electron change          */
+  const int32_t *blk_op, *blk_in, *blk_out, *blk_rows, *blk_cols, *blk_ld;  /* [nBlk] */
+  const int64_t *blk_off;         /* [nBlk]                                          */
+  const int32_t *term_L, *term_R; /* [nTerms] operator or -1                         */
+  const double *term_coef;        /* [nTerms]                                        */
+} tns_su2_problem;
+
+typedef struct {
+  int64_t n_sectors, psi_dim, ntasks, total_flops;
+  tns_tasklist tl; /* forward-only task list: tns_apply_heff, tns_davidson */
+} tns_su2_plan;
+
+/* Build workspace bytes (host only; 0 when the problem fails validation:
+ * shapes, ranges, layout, quantum numbers and triangle rules of every block,
+ * equal ranks and conserved N of every term, a target with no sector). */
+size_t tns_su2_workspace_bytes(const tns_su2_problem *prob);
+/* Host only: the wavefunction sectors (sec_L, sec_R [n_sectors], psi_off
+ * [n_sectors + 1]) and the task table (tasks [n_tasks], task_ptr
+ * [n_sectors + 1] CSR over output sectors, term order kept inside a sector).
+ * Counts always returned; arrays written when given (all four sector arrays
+ * together; TNS_ERR_WORKSPACE when a capacity is short); TNS_ERR_QN when the
+ * target has no sector. */
+tns_status tns_su2_tables(const tns_su2_problem *prob, int32_t *sec_L, int32_t *sec_R, int64_t *psi_off,
+                          int64_t cap_sectors, tns_task *tasks, int32_t *task_ptr, int64_t cap_tasks,
+                          int64_t *n_sectors, int64_t *n_tasks);
+/* Validates, lists the tasks with their scalars on the host and builds the
+ * schedules into `ws` on the device (synchronises the stream); `ws` must stay
+ * untouched while the plan is used. */
+tns_status tns_su2_build(const tns_su2_problem *prob, void *ws, size_t ws_bytes, tns_su2_plan *out,
+                         hipStream_t stream);
+
 const char *tns_status_string(tns_status s);
 
 /* Profiling aid: when all three events are non-null, the next forward

@@ -17,9 +17,12 @@ reading of the conventions documented with the instance generator:
   the block states |a S m> obtained from the given highest-weight vectors by
   repeated lowering with the block's S- and normalisation.
 
-No recoupling coefficient enters: the Clebsch-Gordan coefficients here only
-build the coupled states and the scalar products (sympy's exact values).
-The block Hamiltonians are rebuilt from their parameters.
+In :func:`sigma` no recoupling coefficient enters: the Clebsch-Gordan
+coefficients (sympy's exact values) only build the coupled states and the
+scalar products, and the block Hamiltonians are rebuilt from their
+parameters.  :func:`sigma_reduced` is the Wigner-Eckart route on the reduced
+blocks (each sector pair's coefficient by expanding the coupled states),
+for instances that have no Fock space; it is pinned to :func:`sigma`.
 """
 
 from functools import lru_cache
@@ -115,7 +118,7 @@ def hamiltonian(inst, F=None):
     return H.tocsr()
 
 
-def _lowered(hw, lsize, twoS, l):
+def _lowered(hw, twoS, l):
     """Block states |a S m> for m = S, S-1, ..., -S (doubled: twoS .. -twoS)
     of the highest-weight columns ``hw`` (4^l Fock coordinates)."""
     Fb = _block_space(l)
@@ -146,7 +149,7 @@ def coupled_basis(inst):
     low = {}
     for side, q, hws, l in ((0, inst.qL, inst.hw_L, inst.lL), (1, inst.qR, inst.hw_R, inst.lR)):
         for k, V in enumerate(hws):
-            low[(side, k)] = _lowered(V, 4 ** l, int(q[k][1]), l)
+            low[(side, k)] = _lowered(V, int(q[k][1]), l)
     for a, b in inst.psi_sectors():
         sl, sr = int(inst.qL[a][1]), int(inst.qR[b][1])
         A, B = low[(0, a)], low[(1, b)]
@@ -196,3 +199,57 @@ def total_spin(F, n):
     Sm = sum((F.s_minus(i) for i in range(n)), sp.csr_matrix((F.dim, F.dim)))
     Sz = sum((F.s_z(i) for i in range(n)), sp.csr_matrix((F.dim, F.dim)))
     return (Sm @ Sp + Sz @ Sz + Sz).tocsr(), Sz.tocsr()
+
+
+def recoupling(slp, srp, s, sl, sr, k):
+    """<(SL' SR') S S| [T^k x U^k]^0 |(SL SR) S S> per unit reduced elements
+    (Clebsch-Gordan convention), spins doubled: the coupled states expanded
+    and the components applied by the Wigner-Eckart theorem."""
+    w = 0.0
+    for ml in range(-sl, sl + 1, 2):
+        c_in = _cg(sl, ml, sr, s - ml, s, s)
+        if c_in == 0.0:
+            continue
+        for q in range(-k, k + 1, 2):
+            w += (c_in * _cg(k, q, k, -q, 0, 0) * _cg(sl, ml, k, q, slp, ml + q)
+                  * _cg(sr, s - ml, k, -q, srp, s - ml - q) * _cg(slp, ml + q, srp, s - ml - q, s, s))
+    return w
+
+
+def sigma_reduced(inst, psi):
+    """The same product on reduced blocks, sector by sector: for every term,
+    input sector (iL, iR) and reduced blocks L: iL -> iL', R: iR -> iR' with
+    (iL', iR') a wavefunction sector, sigma_(iL',iR') += coef
+    (-1)^(p_R N_L) recoupling(...) L psi_(iL,iR) R^T (identity = -1).  Valid for
+    instances without a Fock space (synthetic reduced blocks); pinned against
+    :func:`sigma` where both apply."""
+    secs = inst.psi_sectors()
+    off = inst.psi_off()
+    idx = {sec: n for n, sec in enumerate(secs)}
+    N, s2 = inst.target
+    out = np.zeros(int(off[-1]))
+    blocks = {}
+    for b in range(len(inst.blk_op)):
+        blocks.setdefault((int(inst.blk_op[b]), int(inst.blk_in[b])), []).append(b)
+    for oL, oR, coef in zip(inst.term_L, inst.term_R, inst.term_coef):
+        oL, oR = int(oL), int(oR)
+        k = int(inst.op_2k[oL]) if oL >= 0 else 0
+        pR = abs(int(inst.op_dN[oR])) % 2 if oR >= 0 else 0
+        for n, (a, b) in enumerate(secs):
+            x = psi[off[n]:off[n + 1]].reshape(int(inst.dimL[a]), int(inst.dimR[b]))
+            Ls = [(int(inst.blk_out[lb]), inst.block(lb)) for lb in blocks.get((oL, a), [])] if oL >= 0 \
+                else [(a, None)]
+            Rs = [(int(inst.blk_out[rb]), inst.block(rb)) for rb in blocks.get((oR, b), [])] if oR >= 0 \
+                else [(b, None)]
+            for a2, Lb in Ls:
+                for b2, Rb in Rs:
+                    m = idx.get((a2, b2))
+                    if m is None:
+                        continue
+                    w = recoupling(int(inst.qL[a2][1]), int(inst.qR[b2][1]), s2, int(inst.qL[a][1]),
+                                   int(inst.qR[b][1]), k)
+                    sign = -1.0 if (pR * int(inst.qL[a][0])) % 2 else 1.0
+                    y = x if Lb is None else Lb @ x
+                    y = y if Rb is None else y @ Rb.T
+                    out[off[m]:off[m + 1]] += float(coef) * w * sign * y.reshape(-1)
+    return out

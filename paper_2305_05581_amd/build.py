@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtns.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["tasklist.hip", "fwd.hip", "apply.hip", "davidson.hip", "peak.hip", "renorm.hip", "ttcache.hip"]
+SOURCES = ["tasklist.hip", "fwd.hip", "apply.hip", "davidson.hip", "peak.hip", "renorm.hip", "ttcache.hip", "su2.hip"]
 
 
 def flags():

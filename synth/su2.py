@@ -227,6 +227,10 @@ class Su2Instance:
                     out.append((a, b))
         return out
 
+    @property
+    def nS(self):
+        return len(self.psi_sectors())
+
     def psi_off(self):
         secs = self.psi_sectors()
         off = [0]
@@ -351,7 +355,7 @@ def su2_synthetic(nsec_N, D, dmax, n_ops, n_terms, target, seed, max_2S=6):
                     j = idx.get((n + dN, s2o))
                     if j is None:
                         continue
-                    g = np.random.Generator(np.random.Philox(key=[seed, 1 + o, i, j]))
+                    g = np.random.Generator(np.random.Philox(key=[seed, ((1 + o) << 32) | (i << 16) | j]))
                     blocks.append((o, i, j, g.standard_normal((int(dims[j]), int(dims[i]))) / np.sqrt(dims[i])))
     left = [k for k, o in enumerate(ops) if o[0] == 0]
     right = [k for k, o in enumerate(ops) if o[0] == 1]

@@ -83,3 +83,15 @@ def test_truncated_compression():
     assert ef[0] - 1e-10 <= e[0] and e[-1] <= ef[-1] + 1e-10
     psi = np.random.default_rng(0).standard_normal(inst.psi_dim)
     assert np.allclose(osu.sigma(inst, psi, H, V), A @ psi, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_reduced_route_equals_projection(case):
+    """The Wigner-Eckart route on reduced blocks equals V^T H V psi."""
+    lL, lR, target = CASES[case]
+    for keep in (1.0, 0.6):
+        inst = su2_instance(lL, lR, target, seed=15, keep_frac=keep)
+        psi = np.random.default_rng(1).standard_normal(inst.psi_dim)
+        want = osu.sigma(inst, psi)
+        got = osu.sigma_reduced(inst, psi)
+        assert np.allclose(got, want, atol=1e-12 * np.linalg.norm(want))
