@@ -213,10 +213,12 @@ tns_status tns_apply_heff_batch(const tns_tasklist *const *tls, int n, tns_prec 
 /* Tile shapes of the two forward GEMM phases per sector-size bucket (level 3
  * work decomposition, Alg. 2's batched products; the bucket choice is this
  * library's).  `tiles` packs four bytes: byte b is the tile extent (32, 64 or
- * 128 rows/columns) used along any output dimension d of bucket b =
- * [d <= 32, d <= 64, d <= 128, d > 128]; the last tile along a dimension
- * shrinks to the multiple of 32 that covers what remains.  Default
- * 0x80804020 (32, 64, 128, 128).  tns_set_tiles rebuilds the forward work items on the device (the
+ * 128 rows/columns, or 0 for 256 columns and 128 rows) used along any output
+ * dimension d of bucket b = [d <= 32, d <= 64, d <= 128, d > 128]; the last
+ * tile along a dimension shrinks to the multiple of 32 that covers what
+ * remains.  Default 0x00804020 (32, 64, 128, 256 columns).  BF16X3 runs
+ * tiles up to 128 x 256 whole; FP32 and FP64 run a tile wider than 128
+ * columns as two.  tns_set_tiles rebuilds the forward work items on the device (the
  * backward's adjoint product keeps the default table) and
  * synchronises the stream (no product may be in flight on the task list);
  * workspaces and results do not depend on the table (the sums are taken in

@@ -463,7 +463,15 @@ __global__ void k_epilogue_psi(const int64_t *__restrict__ psi_off, int nS, int 
     const int64_t loc = e - psi_off[s];
     double acc = beta ? (double)out[e] : 0.0;
     const int64_t c0 = grp_chunk_base[gps * s], c1 = grp_chunk_base[gps * s + gps];
-    for (int64_t c = c0; c < c1; ++c) acc += (double)part[slot_off[c] + loc];
+    // eight slots' loads in flight at a time, added in slot order
+    for (int64_t c = c0; c < c1; c += 8) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = c + u < c1 ? part[slot_off[c + u] + loc] : T(0);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c + u < c1) acc += (double)v[u];
+    }
     out[e] = (T)acc;
   }
 }

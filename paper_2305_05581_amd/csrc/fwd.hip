@@ -36,7 +36,12 @@
 
 namespace tns {
 
-constexpr int GTH = 256;  // threads per workgroup: 4 waves in a 2 x 2 grid of wave tiles
+// Threads per workgroup: FP32 / FP64 4 waves in a 2 x 2 grid of wave tiles,
+// BF16X3 8 waves in a 2 x 4 grid (wider column tiles: fewer operand bytes per
+// flop, two waves per SIMD).
+template <int P> constexpr int gth() { return P == TNS_BF16X3 ? 512 : 256; }
+// waves across the columns of a tile
+template <int P> constexpr int wgn() { return P == TNS_BF16X3 ? 4 : 2; }
 
 // Operand: element (i, k) at index i * ld + k for i < rows, k < K of the
 // segment (BF16X3: of the interleaved halves, see bfx_hi).  Identity
@@ -115,9 +120,12 @@ template <> struct FP<TNS_BF16X3> {
 
 // --- work queues --------------------------------------------------------------------
 // Phase A: panel items, phase B: the schedule's items; queue q of a phase is
-// items[qbase[q], qbase[q+1]).
-// Thread 0: next work id of phase PH (own XCD queue first), -1 when drained.
-template <int PH>
+// items[qbase[q], qbase[q+1]).  FP32 / FP64 take every item as two units of
+// work (its first 128 columns and the rest, if any): MULT = 2.
+template <int P> constexpr int work_mult() { return P == TNS_BF16X3 ? 1 : 2; }
+// Thread 0: next work id of phase PH (own XCD queue first), -1 when drained:
+// item MULT id + unit.
+template <int PH, int MULT>
 __device__ inline int pop_work(const FwdArgs &g) {
   const int home = blockIdx.x % g.nq;
   const int64_t *qb = PH == 0 ? g.a_qbase : g.qbase;
@@ -126,7 +134,7 @@ __device__ inline int pop_work(const FwdArgs &g) {
     const int64_t b = qb[q], n = qb[q + 1] - b;
     if (n <= 0) continue;
     const int j = atomicAdd(g.queue + 8 * PH + q, 1);
-    if (j < n) return (int)(b + j);
+    if (j < MULT * n) return (int)(MULT * b + j);
   }
   return -1;
 }
@@ -136,11 +144,12 @@ __device__ inline int pop_work(const FwdArgs &g) {
 // target of one global_load_lds_dwordx4 of a wave.  FP32 [A, B] (BK = 16) and
 // FP64 [A, B] (BK = 8): arrays of 8 chunks of 16 rows x 64 bytes (4 16-byte
 // k-vectors), 16 KB per stage, so that two workgroups share a CU; the
-// k-vectors of row r sit at slots kv ^ ((r >> 1) & 3).  BF16X3 [A, B]
-// (BK = 32): arrays of 16 chunks of 8 rows x 128 bytes, the interleaved high
-// and low halves of 32 k, so that every row of a stage is one whole 128-byte
-// line in memory; vector v of row r sits at slot v ^ (r & 7); 32 KB per
-// stage, one workgroup per CU.  Either way the 16 rows read by one MFMA
+// k-vectors of row r sit at slots kv ^ ((r >> 1) & 3).  BF16X3 (BK = 32):
+// chunks of 8 rows x 128 bytes, the interleaved high and low halves of 32 k,
+// so that every row of a stage is one whole 128-byte line in memory; 16
+// chunks for the 128 rows of A, 32 for the up to 256 rows of B; vector v of
+// row r sits at slot v ^ (r & 7); 48 KB per stage, three stages, one
+// workgroup of 8 waves per CU.  Either way the 16 rows read by one MFMA
 // operand fetch fall into distinct LDS banks.  Loads run NS - 1 stages ahead of the MFMA
 // work; a stage is consumed after a counted vector-memory wait and one
 // barrier (no fence, in-flight stages stay in flight).  Out-of-range rows and
@@ -157,9 +166,9 @@ template <> struct RingP<TNS_BF16X3> { static constexpr int VEC = 8; };
 template <> struct RingP<TNS_F32> { static constexpr int VEC = 4; };
 template <> struct RingP<TNS_F64> { static constexpr int VEC = 2; };
 template <int P, int KS> struct RingL {
-  static constexpr int ARR = P == TNS_BF16X3 ? 4 : 2 * KS;  // 8 chunks each (BF16X3: A and B of 16)
-  static constexpr int CH = 8 * ARR;                        // chunks per stage
-  static constexpr int LOADS = CH / 4;                      // global_load_lds per wave and stage
+  static constexpr int ARR = 2 * KS;                           // FP32 / FP64: arrays of 8 chunks
+  static constexpr int CH = P == TNS_BF16X3 ? 48 : 8 * ARR;    // chunks per stage (BF16X3: A 16, B 32)
+  static constexpr int LOADS = CH / 4;                         // FP32 / FP64 loads per wave and stage
   static constexpr int BK = P == TNS_BF16X3 ? 32 : KS * 4 * RingP<P>::VEC;
 };
 // The NS stages (2 to 5) are separate LDS arrays and every access names its
@@ -219,9 +228,9 @@ __device__ inline void gl_lds(const void *src, void *dst) {
 // (vector-memory loads complete in order) and, with LGKM, until its LDS reads
 // are complete, then joins the workgroup.  No fence: only the LDS written by
 // this kernel's ring loads is exchanged here.
-template <int P, int KS, int NS, bool LGKM>
+template <int P, int KS, int NS, bool LGKM, int NL>
 __device__ inline void ring_sync() {
-  constexpr int E = (7 << 4) | ((LGKM ? 0 : 15) << 8), N = (NS - 2) * RingL<P, KS>::LOADS;  // expcnt: no wait
+  constexpr int E = (7 << 4) | ((LGKM ? 0 : 15) << 8), N = (NS - 2) * NL;  // expcnt: no wait
   static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt(E | (N & 15) | ((N >> 4) << 14));
   __builtin_amdgcn_s_barrier();
@@ -240,28 +249,39 @@ __device__ inline void ring_drain() { __builtin_amdgcn_s_waitcnt((7 << 4) | (15 
 // array.
 // BF16X3 (high and low halves interleaved in groups of 8 elements, so 32 k of
 // a row are 128 contiguous bytes): a chunk is 8 rows x 128 bytes (8 lanes per
-// row); wave w loads rows [32 w, 32 w + 32) of each operand, q = u (A) and
-// 4 + u (B) the chunk 4 w + u of the 16 in each array, u < 4.
+// row); of the 8 waves, wave w loads rows [16 w, 16 w + 16) of A (q = u < 2:
+// A chunk 2 w + u) and, with NB chunks of B per wave (B rows 64 NB), rows
+// [8 NB w, 8 NB w + 8 NB) of B (q = 2 + u, u < NB: B chunk NB w + u).
 template <int P> struct LoadSetT {
-  static constexpr int N = P == TNS_BF16X3 ? 8 : 4;
+  static constexpr int N = P == TNS_BF16X3 ? 6 : 4;
   const char *ptr[N];
   int32_t klim[N];
 };
 
-// Rows [r0, r0 + 128) of M into the slots of one operand (q0 = 0: A, else B;
-// rows beyond rlim read zeros).
-template <int P>
+// Rows of M from r0 on into the slots of one operand (q0 = 0: A, else B; rows
+// beyond rlim read zeros): FP32 / FP64 128 rows; BF16X3 128 rows of A or
+// 64 NB rows of B.
+template <int P, int NB = 4>
 __device__ __attribute__((always_inline)) inline void ls_mat(LoadSetT<P> &ls, int q0, const Mat &M, int r0, int rlim,
                                                              int K) {
   typedef typename FP<P>::E E;
   const int w = threadIdx.x >> 6;
   if constexpr (P == TNS_BF16X3) {
-    const int rin = (threadIdx.x & 63) >> 3, base = q0 ? 4 : 0;
+    const int rin = (threadIdx.x & 63) >> 3;
+    if (q0 == 0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int row = r0 + 32 * w + 8 * u + rin;
-      ls.ptr[base + u] = reinterpret_cast<const char *>(M.p) + 4 * ((int64_t)row * M.ld);
-      ls.klim[base + u] = row < rlim ? K : 0;
+      for (int u = 0; u < 2; ++u) {
+        const int row = r0 + 16 * w + 8 * u + rin;
+        ls.ptr[u] = reinterpret_cast<const char *>(M.p) + 4 * ((int64_t)row * M.ld);
+        ls.klim[u] = row < rlim ? K : 0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int row = r0 + 8 * NB * w + 8 * u + rin;
+        ls.ptr[2 + u] = reinterpret_cast<const char *>(M.p) + 4 * ((int64_t)row * M.ld);
+        ls.klim[2 + u] = row < rlim ? K : 0;
+      }
     }
   } else {
     const int rin = (threadIdx.x & 63) >> 2, base = q0 ? 2 : 0;
@@ -275,8 +295,9 @@ __device__ __attribute__((always_inline)) inline void ls_mat(LoadSetT<P> &ls, in
 }
 
 // Stage <- one K step (k in [k0, k0 + BK)) of the chunks of ls; with live
-// false every load reads the zero region.  Branch-free.
-template <int P, int KS>
+// false every load reads the zero region.  Branch-free.  NB: BF16X3 B chunks
+// per wave.
+template <int P, int KS, int NB = 4>
 __device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &st, const LoadSetT<P> &ls, int k0,
                                                                  bool live, const void *zero) {
   typedef typename FP<P>::E E;
@@ -291,8 +312,8 @@ __device__ __attribute__((always_inline)) inline void ring_issue(Stage<P, KS> &s
     const int k = k0 + 8 * (v >> 1);
     const int64_t boff = 4 * (int64_t)k0 + 16 * v;
 #pragma unroll
-    for (int u = 0; u < L; ++u) {
-      const int c = (u >> 2) * 16 + 4 * w + (u & 3);  // chunk of the stage (A 0..15, B 16..31)
+    for (int u = 0; u < 2 + NB; ++u) {
+      const int c = u < 2 ? 2 * w + u : 16 + NB * w + (u - 2);  // chunk of the stage (A 0..15, B 16..47)
       const bool in = live && k < ls.klim[u];
       gl_lds(in ? ls.ptr[u] + boff : z, &st.b[c * 1024]);
     }
@@ -371,16 +392,16 @@ template <int P, int KS, int TM, int TN> struct Frags {
 template <int P, int KS, int TM, int TN>
 __device__ __attribute__((always_inline)) inline void ring_read(const Stage<P, KS> &st, Frags<P, KS, TM, TN> &f) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, g = lane >> 4;
+  const int wm = w / wgn<P>(), wn = w % wgn<P>(), l16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int i = 0; i < TM; ++i) f.a[i] = ring_frag<P, KS>(st, 0, wm * 16 * TM + 16 * i, l16, g);
 #pragma unroll
   for (int j = 0; j < TN; ++j) f.b[j] = ring_frag<P, KS>(st, 1, wn * 16 * TN + 16 * j, l16, g);
 }
 
-template <int P, int KS, int TM, int TN, bool SWAP>
+template <int P, int KS, int TM, int TN, bool SWAP, int AM, int AN>
 __device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS, TM, TN> &f,
-                                                               typename FP<P>::A4 (&acc)[4][4]) {
+                                                               typename FP<P>::A4 (&acc)[AM][AN]) {
   if (SWAP) {
 #pragma unroll
     for (int i = 0; i < TN; ++i)
@@ -395,14 +416,17 @@ __device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS
 }
 
 // Ring geometry of each (precision, phase): KS k-halves per stage, WG
-// workgroups per CU, PF register prefetch of the next stage's fragments.
-// FP32 and FP64 use 16 KB stages at two workgroups per CU, BF16X3 32 KB
-// stages at one.
+// workgroups per CU, NS stages, PF register prefetch of the next stage's
+// fragments.  FP32 and FP64 use four 16 KB stages at two workgroups per CU,
+// BF16X3 three 48 KB stages at one.  BF16X3 phase B reads each stage's
+// fragments in the step that uses them: the second fragment set of the
+// prefetch does not fit its registers next to the segment bookkeeping at two
+// waves per SIMD (spilled, phase B took 14.8 ms at D = 4096 against 12.7).
 template <int P, int PH> struct Geo {
   static constexpr int KS = 1;
   static constexpr int WG = P == TNS_BF16X3 ? 1 : 2;
-  static constexpr int NS = 4;
-  static constexpr bool PF = true;
+  static constexpr int NS = P == TNS_BF16X3 ? 3 : 4;
+  static constexpr bool PF = !(P == TNS_BF16X3 && PH == 1);
 };
 
 // Drives the ring over one stream of K steps.  dma(stage) fills a stage
@@ -417,17 +441,18 @@ template <int P, int PH> struct Geo {
 // can interleave, and with the direct loads on every path of a loop without
 // early exits the compiler keeps track of which stage each read depends on.
 //
-// PF (prefetch, four stages): the fragments of stage s + 1 are read into
-// registers during step s, while the MFMA work of stage s (read one step
+// PF (prefetch, three or four stages): the fragments of stage s + 1 are read
+// into registers during step s, while the MFMA work of stage s (read one step
 // earlier) runs; the slot of stage s is then free at step s and receives
-// stage s + 4.  Each step waits for this wave's outstanding LDS reads before
-// the barrier, so no slot is overwritten while a read of it is in flight.
+// stage s + NS.  Each step waits for this wave's outstanding LDS reads before
+// the barrier, so no slot is overwritten while a read of it is in flight.  NL:
+// loads per wave and stage.
 template <int... J, class F>
 __device__ __attribute__((always_inline)) inline void static_for(std::integer_sequence<int, J...>, F &&f) {
   (f(std::integral_constant<int, J>{}), ...);
 }
 
-template <int P, int KS, int NS, bool PF, class FR, class Dma, class Adv, class Mma, class Post>
+template <int P, int KS, int NS, bool PF, class FR, int NL, class Dma, class Adv, class Mma, class Post>
 __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &rg, Dma &&dma, Adv &&adv, Mma &&mma,
                                                                Post &&post) {
   int issued = 0;
@@ -436,33 +461,36 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &
     issued += adv();
   });
   if constexpr (PF) {
-    static_assert(NS == 4, "prefetch alternates two fragment sets over four stages");
+    static_assert(NS == 3 || NS == 4, "prefetch alternates two fragment sets over three or four stages");
     FR f0, f1;
-    ring_sync<P, KS, NS, false>();
-    dma(rg.s3);
+    ring_sync<P, KS, NS, false, NL>();
+    dma(stage<NS - 1>(rg));
     issued += adv();
     ring_read(rg.s0, f0);
     auto step = [&](auto J, int s, FR &cur, FR &nxt) {
       constexpr int j = decltype(J)::value;
-      ring_sync<P, KS, NS, true>();
+      ring_sync<P, KS, NS, true, NL>();
       dma(stage<j>(rg));
       ring_read(stage<(j + 1) % NS>(rg), nxt);
       mma(cur, J);
       issued += adv();
       if (s < issued) post();
     };
-    for (int s = 0; s < issued; s += NS) {
-      step(std::integral_constant<int, 0>{}, s, f0, f1);
-      step(std::integral_constant<int, 1>{}, s + 1, f1, f0);
-      step(std::integral_constant<int, 2>{}, s + 2, f0, f1);
-      step(std::integral_constant<int, 3>{}, s + 3, f1, f0);
+    // steps in groups of lcm(2, NS): the fragment sets alternate, the stages cycle
+    constexpr int U = NS == 4 ? 4 : 6;
+    for (int s = 0; s < issued; s += U) {
+      static_for(std::make_integer_sequence<int, U>{}, [&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (i & 1) step(std::integral_constant<int, i % NS>{}, s + i, f1, f0);
+        else step(std::integral_constant<int, i % NS>{}, s + i, f0, f1);
+      });
     }
   } else {
     FR f;
     for (int s = 0; s < issued; s += NS) {
       static_for(std::make_integer_sequence<int, NS>{}, [&](auto J) {
         constexpr int j = decltype(J)::value;
-        ring_sync<P, KS, NS, false>();
+        ring_sync<P, KS, NS, false, NL>();
         dma(stage<(j + NS - 1) % NS>(rg));
         ring_read(stage<j>(rg), f);
         mma(f, J);
@@ -495,23 +523,28 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &
   }
 
 // --- phase B: one item (output tile, chunk of tasks) ------------------------------------
+// TM, TN: 16-row / 16-column MFMA tiles per wave (a workgroup tile of
+// 32 TM rows x 16 TN wgn columns); ncols: the item's columns (the rest of the
+// tile reads zeros and stores nothing).
 template <int P, int KS, int TM, int TN>
 __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
-                                                                    const Item &it, int mode) {
+                                                                    const Item &it, int mode, int ncols) {
   typedef typename FP<P>::A4 A4;
   constexpr int BK = RingL<P, KS>::BK;
+  constexpr int NL = P == TNS_BF16X3 ? 2 + TN : RingL<P, KS>::LOADS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  const int wm = w / wgn<P>(), wn = w % wgn<P>(), l16 = lane & 15, lg = lane >> 4;
+  const int cend = it.c0 + ncols;
   // FP32: the MFMA accumulators take NS steps at a time and are then added
   // into a second set (two-level summation), so that the rounding error over
   // a long inner dimension grows with the square roots of the steps per fold
   // and of the number of folds rather than with that of the whole dimension.
   constexpr bool TWO = P == TNS_F32;
-  A4 acc[4][4], acc2[4][4];
+  A4 acc[TM][TN], acc2[TM][TN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = acc2[i][j] = vzero<A4>();
+    for (int j = 0; j < TN; ++j) acc[i][j] = acc2[i][j] = vzero<A4>();
   int lj = 0, lK = 0;
   LoadSetT<P> LS;
   // segment records through scalar loads; the next one is fetched while the
@@ -539,7 +572,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
-            if (row < r.arows && col < r.K) {
+            if (row < r.arows && col < r.K && col < cend) {
               const int64_t e = r.a_off + (int64_t)row * ldT + col;
               if constexpr (P == TNS_BF16X3) {
                 const uint16_t *Tu = reinterpret_cast<const uint16_t *>(g.T) + bfx_hi(e);
@@ -567,8 +600,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     LA.ld = ld8(r.K); LA.rows = r.arows;
     LB.p = elem_ptr<P>(g.ops, r.b_off);
     LB.ld = r.bld; LB.rows = r.brows;
-    ls_mat<P>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
-    ls_mat<P>(LS, 2, LB, it.c0, min(LB.rows, it.c0 + 32 * TN), lK);
+    ls_mat<P, TN>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
+    ls_mat<P, TN>(LS, 2, LB, it.c0, min(LB.rows, cend), lK);
   };
   SegRec nxt;
   if (!ldone) {
@@ -580,12 +613,12 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   } else {  // no products: the ring runs on the zero region only
     Mat Z;
     Z.p = g.zero; Z.ld = 0; Z.rows = 0;
-    ls_mat<P>(LS, 0, Z, 0, 0, 0);
-    ls_mat<P>(LS, 2, Z, 0, 0, 0);
+    ls_mat<P, TN>(LS, 0, Z, 0, 0, 0);
+    ls_mat<P, TN>(LS, 2, Z, 0, 0, 0);
   }
   typedef Frags<P, KS, TM, TN> FR;
-  ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR>(
-      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS>(st, LS, lj * BK, !ldone, g.zero); },
+  ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR, NL>(
+      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS, TN>(st, LS, lj * BK, !ldone, g.zero); },
       [&]() -> int {
         if (ldone) return 0;
         if (++lj * BK >= lK) {
@@ -624,7 +657,7 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = it.p0 + wm * 16 * TM + i * 16 + mrow(acc[i][j], lg, v);
-        if (row < R && col < C) {
+        if (row < R && col < C && col < cend) {
           const int64_t o = mode == M_FWD1 ? ((int64_t)col * R + row) : ((int64_t)row * C + col);
           slot[o] = TWO ? acc2[i][j][v] + acc[i][j][v] : acc[i][j][v];
         }
@@ -632,39 +665,51 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     }
 }
 
+// Item dispatch: BF16X3 covers up to 256 columns per tile (16 TN per wave
+// over 4 waves, TN = ceil(tn / 2)); FP32 / FP64 run unit 0 (the first 128
+// columns) or unit 1 (the rest, nothing if none) of an item.
 template <int P, int KS>
 __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
-                                                                  int wk) {
-  const Item it = load_item(g.items + wk);
+                                                                  int wk, int unit) {
+  Item it = load_item(g.items + wk);
   const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
-#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode)
-  TNS_TILE_SWITCH(tm, tn, TNS_CALL_B)
+  if constexpr (P == TNS_BF16X3) {
+    const int cw = (tn + 1) >> 1;
+#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode, 32 * tn)
+    TNS_TILE_SWITCH(tm, cw, TNS_CALL_B)
 #undef TNS_CALL_B
+  } else {
+    const int t = unit ? tn - 4 : (tn < 4 ? tn : 4);
+    if (t <= 0) return;
+    if (unit) it.c0 += 128;
+#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode, 32 * t)
+    TNS_TILE_SWITCH(tm, t, TNS_CALL_B)
+#undef TNS_CALL_B
+  }
 }
 
 // --- phase A: row tiles of a panel as one stream of K steps ---------------------------
 // A panel item covers chunks [p0, p0 + np) of its panel's stacked rows (whole
-// 128-row tiles) and columns [c0, c0 + 32 TN) of T; its row tiles share the
+// 128-row tiles) and columns [c0, c0 + ncols) of T; its row tiles share the
 // right operand (the padded psi sector), and the ring keeps loading across
 // tile boundaries.
 
 // Sources of this wave's A rows in the tile starting at chunk ch, inner
 // dimension K (chunks at or beyond ch_end read zeros).  FP32 / FP64: the 16
-// rows of chunks ch + w and ch + w + 4 (slots 0, 1); BF16X3: rows [32 w,
-// 32 w + 32) of the tile, i.e. rows u & 1 ? 8..15 : 0..7 of chunk
-// ch + 2 w + (u >> 1) for slot u < 4.
+// rows of chunks ch + w and ch + w + 4 (slots 0, 1); BF16X3 (8 waves): the
+// 16 rows of chunk ch + w, rows 8 u .. 8 u + 7 in slot u < 2.
 template <int P>
 __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g, LoadSetT<P> &ls, int ch, int ch_end,
                                                                 int K) {
   typedef typename FP<P>::E E;
   const int w = threadIdx.x >> 6;
   constexpr bool BF = P == TNS_BF16X3;
-  constexpr int NU = BF ? 4 : 2;
+  constexpr int NU = 2;
   const int rin = BF ? (threadIdx.x & 63) >> 3 : (threadIdx.x & 63) >> 2;
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    const int c = __builtin_amdgcn_readfirstlane(BF ? ch + 2 * w + (u >> 1) : ch + w + 4 * u);  // uniform: scalar loads
-    const int row = BF ? 8 * (u & 1) + rin : rin;  // row inside the chunk
+    const int c = __builtin_amdgcn_readfirstlane(BF ? ch + w : ch + w + 4 * u);  // uniform: scalar loads
+    const int row = BF ? 8 * u + rin : rin;  // row inside the chunk
     ls.ptr[u] = reinterpret_cast<const char *>(g.zero);
     ls.klim[u] = 0;
     if (c < ch_end) {
@@ -682,14 +727,15 @@ __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g
 // Epilogue of a stacked T tile starting at chunk ch (swapped accumulator:
 // acc[i][j] rows = T columns c0 + wn 16 TN + 16 i + .., columns = the rows of
 // chunk ch + 4 wm + j).  Row r of chunk c lies at tbase + (16 c + r) ldT;
-// rows beyond the chunk's task are not stored.  FP32 and BF16X3 write 4
-// consecutive columns per lane as one vector.
+// rows beyond the chunk's task and columns at or beyond cend are not stored.
+// FP32 and BF16X3 write 4 consecutive columns per lane as one vector.
 template <int P, int TN>
-__device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[4][4], int ch, int ch_end,
-                                      int64_t tbase, int c0, int ldT) {
+__device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[TN][4],
+                                                                     int ch, int ch_end, int64_t tbase, int c0,
+                                                                     int cend, int ldT) {
   typedef typename FP<P>::A4 A4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w >> 1, wn = w & 1, l16 = lane & 15, lg = lane >> 4;
+  const int wm = w / wgn<P>(), wn = w % wgn<P>(), l16 = lane & 15, lg = lane >> 4;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = __builtin_amdgcn_readfirstlane(ch + 4 * wm + j);
@@ -707,11 +753,11 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int col = col0 + mrow(acc[i][j], lg, v);
-              if (col < ldT) Tt[col] = alpha * acc[i][j][v];
+              if (col < ldT && col < cend) Tt[col] = alpha * acc[i][j][v];
             }
           } else {
             const int col = col0 + 4 * lg;  // FP32 / BF16 accumulators: rows 4 lg .. 4 lg + 3
-            if (col < ldT) {
+            if (col < ldT && col < cend) {
               const f4 x = (float)alpha * acc[i][j];
               const int64_t o = orow + col;
               if constexpr (P == TNS_F32) {
@@ -732,16 +778,18 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i][j] = vzero<A4>();
+    for (int i = 0; i < TN; ++i) acc[i][j] = vzero<A4>();
   }
 }
 
 template <int P, int KS, int TN>
 __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
-                                                                    const Item &it) {
+                                                                    const Item &it, int ncols) {
   typedef typename FP<P>::A4 A4;
   typedef typename FP<P>::E E;
   constexpr int BK = RingL<P, KS>::BK;
+  constexpr int NL = P == TNS_BF16X3 ? 2 + TN : RingL<P, KS>::LOADS;
+  const int cend = it.c0 + ncols;
   const int G = it.grp, sec = G >> 1, cls = G & 1;
   const int m = cld(&g.dimL[cld(&g.psi_sec[4 * sec])]), n = cld(&g.dimR[cld(&g.psi_sec[4 * sec + 3])]);
   const int K = cls ? n : m, N = cls ? m : n, ldT = ld8(N);
@@ -760,15 +808,15 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
   bool ldone = false;
   LoadSetT<P> LS;
   ls_chunks<P>(g, LS, lch, ch_end, K);
-  ls_mat<P>(LS, 2, B, it.c0, min(B.rows, it.c0 + 32 * TN), K);
-  A4 acc[4][4];
+  ls_mat<P, TN>(LS, 2, B, it.c0, min(B.rows, cend), K);
+  A4 acc[TN][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TN; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
   typedef Frags<P, KS, 4, TN> FR;
-  ring_run<P, KS, Geo<P, 0>::NS, Geo<P, 0>::PF, FR>(
-      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS>(st, LS, lk0, !ldone, g.zero); },
+  ring_run<P, KS, Geo<P, 0>::NS, Geo<P, 0>::PF, FR, NL>(
+      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS, TN>(st, LS, lk0, !ldone, g.zero); },
       [&]() -> int {
         if (ldone) return 0;
         if ((lk0 += BK) < K) return 1;
@@ -781,20 +829,35 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
       [&]() {
         if ((ck0 += BK) < K) return;
         ck0 = 0;
-        ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, ldT);
+        ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, cend, ldT);
         cch += PTILE_CH;
       });
 }
 
+// Item dispatch as in phase B: BF16X3 up to 256 columns per tile, FP32 / FP64
+// unit 0 (the first 128 columns) or unit 1 (the rest) of an item.
 template <int P, int KS>
 __device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
-                                                                  int wk) {
-  const Item it = load_item(g.a_items + wk);
-  switch ((it.mode >> 16) & 0xff) {
-    case 1: ring_item_a_t<P, KS, 1>(g, rg, it); break;
-    case 2: ring_item_a_t<P, KS, 2>(g, rg, it); break;
-    case 3: ring_item_a_t<P, KS, 3>(g, rg, it); break;
-    default: ring_item_a_t<P, KS, 4>(g, rg, it); break;
+                                                                  int wk, int unit) {
+  Item it = load_item(g.a_items + wk);
+  const int tn = (it.mode >> 16) & 0xff;
+  if constexpr (P == TNS_BF16X3) {
+    switch ((tn + 1) >> 1) {
+      case 1: ring_item_a_t<P, KS, 1>(g, rg, it, 32 * tn); break;
+      case 2: ring_item_a_t<P, KS, 2>(g, rg, it, 32 * tn); break;
+      case 3: ring_item_a_t<P, KS, 3>(g, rg, it, 32 * tn); break;
+      default: ring_item_a_t<P, KS, 4>(g, rg, it, 32 * tn); break;
+    }
+  } else {
+    const int t = unit ? tn - 4 : (tn < 4 ? tn : 4);
+    if (t <= 0) return;
+    if (unit) it.c0 += 128;
+    switch (t) {
+      case 1: ring_item_a_t<P, KS, 1>(g, rg, it, 32); break;
+      case 2: ring_item_a_t<P, KS, 2>(g, rg, it, 64); break;
+      case 3: ring_item_a_t<P, KS, 3>(g, rg, it, 96); break;
+      default: ring_item_a_t<P, KS, 4>(g, rg, it, 128); break;
+    }
   }
 }
 
@@ -825,7 +888,7 @@ __global__ void k_chunk_recs(FwdArgs g) {
 }
 
 template <int P, int PH>
-__global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
+__global__ __launch_bounds__(gth<P>(), (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
   constexpr int KS = Geo<P, PH>::KS, NS = Geo<P, PH>::NS;
   __shared__ Stage<P, KS> st0, st1;
   __shared__ StageJ<P, KS, NS, 2> st2;
@@ -833,18 +896,19 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
   __shared__ StageJ<P, KS, NS, 4> st4;
   Ring<P, KS, NS> rg{st0, st1, st2, st3, st4};
   int *s_work = reinterpret_cast<int *>(st0.b);  // the ring is idle between items
+  constexpr int MULT = work_mult<P>();
   for (;;) {
     ring_drain();  // the previous item's trailing (zero) loads have landed
     __syncthreads();
-    if (threadIdx.x == 0) *s_work = pop_work<PH>(g);
+    if (threadIdx.x == 0) *s_work = pop_work<PH, MULT>(g);
     __syncthreads();
     // uniform: the item's metadata then comes through scalar loads, which
     // leave the vector-memory count (ring loads in flight) alone
     const int wk = __builtin_amdgcn_readfirstlane(*s_work);
     __syncthreads();
     if (wk < 0) break;
-    if (PH == 0) ring_item_a<P, KS>(g, rg, wk);
-    else ring_item_b<P, KS>(g, rg, wk);
+    if (PH == 0) ring_item_a<P, KS>(g, rg, wk / MULT, wk % MULT);
+    else ring_item_b<P, KS>(g, rg, wk / MULT, wk % MULT);
   }
   ring_drain();
 }
@@ -981,7 +1045,9 @@ __global__ void k_batch_cum(BatchArgs b) {
   c[b.n] = run;
 }
 
-// Thread 0: next (instance, work id) of phase ph, own XCD queue first.
+// Thread 0: next (instance, work id) of phase ph, own XCD queue first; work
+// id = item MULT id + unit as in pop_work.
+template <int MULT>
 __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk) {
   const int home = blockIdx.x % b.nq;
   for (int k = 0; k < b.nq; ++k) {
@@ -989,8 +1055,9 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
     const int64_t *c = b.cum + ((int64_t)ph * NQ_MAX + q) * (b.n + 1);
     const int64_t tot = c[b.n];
     if (tot <= 0) continue;
-    const int j = atomicAdd(b.queue + 8 * ph + q, 1);
-    if (j >= tot) continue;
+    const int jm = atomicAdd(b.queue + 8 * ph + q, 1);
+    if (jm >= MULT * tot) continue;
+    const int j = jm / MULT;
     int lo = 0, hi = b.n - 1;  // last instance with c[i] <= j
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -998,7 +1065,7 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
     }
     const int64_t loc = j - c[lo];
     *inst = lo;
-    *wk = (int)((ph == 0 ? b.tab[lo].g.a_qbase : b.tab[lo].g.qbase)[q] + loc);
+    *wk = MULT * (int)((ph == 0 ? b.tab[lo].g.a_qbase : b.tab[lo].g.qbase)[q] + loc) + jm % MULT;
     return;
   }
   *inst = -1;
@@ -1006,7 +1073,7 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
 }
 
 template <int P, int PH>
-__global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b) {
+__global__ __launch_bounds__(gth<P>(), (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b) {
   constexpr int KS = Geo<P, PH>::KS, NS = Geo<P, PH>::NS;
   __shared__ Stage<P, KS> st0, st1;
   __shared__ StageJ<P, KS, NS, 2> st2;
@@ -1017,14 +1084,15 @@ __global__ __launch_bounds__(GTH, (Geo<P, PH>::WG)) void k_fwd_batch(BatchArgs b
   for (;;) {
     ring_drain();  // the previous item's trailing (zero) loads have landed
     __syncthreads();
-    if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
+    if (threadIdx.x == 0) pop_batch<work_mult<P>()>(b, PH, &s_w[0], &s_w[1]);
     __syncthreads();
     const int inst = __builtin_amdgcn_readfirstlane(s_w[0]), wk = __builtin_amdgcn_readfirstlane(s_w[1]);
     __syncthreads();
     if (inst < 0) break;
     const FwdArgs g = load_words(&b.tab[inst].g);
-    if (PH == 0) ring_item_a<P, KS>(g, rg, wk);
-    else ring_item_b<P, KS>(g, rg, wk);
+    constexpr int MULT = work_mult<P>();
+    if (PH == 0) ring_item_a<P, KS>(g, rg, wk / MULT, wk % MULT);
+    else ring_item_b<P, KS>(g, rg, wk / MULT, wk % MULT);
   }
   ring_drain();
 }
@@ -1113,9 +1181,9 @@ static inline unsigned nblocks(int64_t n) {
 }
 
 template <class K>
-static int grid_of(K kern, int n_cu) {
+static int grid_of(K kern, int threads, int n_cu) {
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, GTH, 0) != hipSuccess || per <= 0) per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, 0) != hipSuccess || per <= 0) per = 1;
   return per * n_cu;
 }
 
@@ -1171,10 +1239,11 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
     hipLaunchKernelGGL(k_ident_T<P>, dim3((unsigned)std::min<int64_t>(p.ntasks, 4096)), dim3(256), 0, st, g);
   }
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
-  if (p.ntasks > 0) hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, p.n_cu)), dim3(GTH), 0, st, g);
+  if (p.ntasks > 0)
+    hipLaunchKernelGGL((k_fwd<P, 0>), dim3(grid_of(k_fwd<P, 0>, gth<P>(), p.n_cu)), dim3(gth<P>()), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
   if (p.ntasks > 0 && S.nitems > 0)
-    hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, p.n_cu)), dim3(GTH), 0, st, g);
+    hipLaunchKernelGGL((k_fwd<P, 1>), dim3(grid_of(k_fwd<P, 1>, gth<P>(), p.n_cu)), dim3(gth<P>()), 0, st, g);
   if (ev) TNS_HIP(hipEventRecord(ev[2], st));
   return launch_epilogue_psi(p, P == TNS_F64, g.partial, sigma, beta, st);
 }
@@ -1251,10 +1320,12 @@ static tns_status batch_launch(const tns_tasklist *const *tls, int n, const void
   hipLaunchKernelGGL(k_ident_T_batch<P>, dim3(64, n), dim3(256), 0, st, tab);
   if (ev) TNS_HIP(hipEventRecord(ev[0], st));
   if (any_tasks)
-    hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, n_cu)), dim3(GTH), 0, st, b);
+    hipLaunchKernelGGL((k_fwd_batch<P, 0>), dim3(grid_of(k_fwd_batch<P, 0>, gth<P>(), n_cu)), dim3(gth<P>()), 0, st,
+                       b);
   if (ev) TNS_HIP(hipEventRecord(ev[1], st));
   if (any_tasks && any_items)
-    hipLaunchKernelGGL((k_fwd_batch<P, 1>), dim3(grid_of(k_fwd_batch<P, 1>, n_cu)), dim3(GTH), 0, st, b);
+    hipLaunchKernelGGL((k_fwd_batch<P, 1>), dim3(grid_of(k_fwd_batch<P, 1>, gth<P>(), n_cu)), dim3(gth<P>()), 0, st,
+                       b);
   if (ev) TNS_HIP(hipEventRecord(ev[2], st));
   const unsigned gx = (unsigned)std::min<int64_t>(4096, (max_dim + 255) / 256);
   hipLaunchKernelGGL(k_epilogue_batch<Acc>, dim3(gx, n), dim3(256), 0, st, tab);
@@ -1317,11 +1388,11 @@ static tns_status time_median(F run, int reps, hipStream_t st, float *ms) {
 template <class F>
 static tns_status autotune(tns_tasklist *const *tls, int n, F run, hipStream_t st, uint32_t *best) {
   uint32_t cur = plan_of(tls[0]).tiles;
-  static const int EXT[3] = {128, 64, 32};
+  static const int EXT[4] = {0, 128, 64, 32};  // 0: 256 columns
   for (int b = 3; b >= 0; --b) {
     float tbest = 0.f;
     uint32_t pick = cur;
-    for (int e = 0; e < 3; ++e) {
+    for (int e = 0; e < 4; ++e) {
       const uint32_t cand = (cur & ~(0xffu << (8 * b))) | ((uint32_t)EXT[e] << (8 * b));
       for (int i = 0; i < n; ++i) {
         const tns_status s = tns_set_tiles(tls[i], cand, st);

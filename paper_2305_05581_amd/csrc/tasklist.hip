@@ -224,8 +224,8 @@ __global__ __launch_bounds__(256) void k_group_cost(Plan p, Sched S) {
 // Tile extents of a group with a rows x cols output.
 __device__ inline void tile_dims(const Sched &S, int rows, int cols, int *tr, int *tc) {
   if (S.tiles) {
-    *tr = tile_ext(S.tiles, rows);
-    *tc = tile_ext(S.tiles, cols);
+    *tr = tile_ext_r(S.tiles, rows);
+    *tc = tile_ext_c(S.tiles, cols);
   } else {
     *tr = S.tile_r;
     *tc = S.tile_c > 0 ? S.tile_c : cols;
@@ -522,7 +522,7 @@ __device__ inline void pan_split(const Plan &p, int G, int *tc, int *ncol, int *
   int K, N;
   panel_dims(p, G, &K, &N);
   const int64_t nch = A.gch[G + 1] - A.gch[G];
-  *tc = tile_ext(A.tiles, N);
+  *tc = tile_ext_c(A.tiles, N);
   *ncol = nch > 0 ? (N + *tc - 1) / *tc : 0;
   *nrt = (int)((nch + PTILE_CH - 1) / PTILE_CH);
   const int64_t cost_col = 2 * (int64_t)*nrt * GM * *tc * K;
@@ -540,7 +540,7 @@ __global__ void k_pan_total(Plan p) {
   panel_dims(p, G, &K, &N);
   const int64_t nch = A.gch[G + 1] - A.gch[G];
   if (nch == 0) return;
-  const int tc = tile_ext(A.tiles, N), ncol = (N + tc - 1) / tc;
+  const int tc = tile_ext_c(A.tiles, N), ncol = (N + tc - 1) / tc;
   const int64_t nrt = (nch + PTILE_CH - 1) / PTILE_CH;
   atomicAdd((unsigned long long *)&A.scalars[0], (unsigned long long)(2 * nrt * GM * (int64_t)tc * K * ncol));
 }
@@ -973,11 +973,12 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
     layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
     layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
   }
-  // counts that the sorts and item indices hold in 32 bits
+  // counts that the sorts and item indices hold in 32 bits (item indices
+  // twice over: the products count column halves of wide items)
   const int64_t caps[] = {bent, p.fwd.items_cap, p.bwd.items_cap, J.fwd.items_cap, p.pa.items_cap, J.pa.items_cap,
                           p.fwd.chunks_cap, p.bwd.chunks_cap};
   for (int64_t c : caps)
-    if (c >= INT32_MAX) return 0;
+    if (c >= INT32_MAX / 2) return 0;
   if (pl) *pl = p;
   return cv.off + 256;
 }

@@ -62,16 +62,25 @@ static_assert(sizeof(Item) == 48, "Item layout");
 constexpr int GM = 128, GN = 128;
 
 // Tile extents of the forward GEMMs chosen per dimension: a table of four
-// bytes, entry b the extent (32, 64 or 128) used along a dimension d in bucket
-// b = [d <= 32, d <= 64, d <= 128, d > 128]; the last tile along a dimension
-// takes the extent tail_ext of what remains.  Items carry their extents in
-// bits 8..15 (rows / 32) and 16..23 (columns / 32) of Item::mode.
-constexpr uint32_t TILES_DEFAULT = 0x80804020u;  // 32, 64, 128, 128
+// bytes, entry b the extent used along a dimension d in bucket b = [d <= 32,
+// d <= 64, d <= 128, d > 128]: 32, 64 or 128, or 0 for 256 columns (rows then
+// take 128); the last tile along a dimension takes the extent tail_ext of what
+// remains.  Items carry their extents in bits 8..15 (rows / 32) and 16..23
+// (columns / 32) of Item::mode.
+constexpr uint32_t TILES_DEFAULT = 0x00804020u;  // 32, 64, 128, 256 columns (128 rows)
 __host__ __device__ inline int tile_bucket(int d) { return d <= 32 ? 0 : d <= 64 ? 1 : d <= 128 ? 2 : 3; }
-__host__ __device__ inline int tile_ext(uint32_t tab, int d) { return (int)((tab >> (8 * tile_bucket(d))) & 0xffu); }
-// Extent of the last tile along a dimension whose other tiles have extent e
-// (32, 64 or 128): the smallest multiple of 32 that covers the rem <= e
-// remaining rows, so that only the last tile is padded, by less than 32.
+__host__ __device__ inline int tile_byte(uint32_t tab, int d) { return (int)((tab >> (8 * tile_bucket(d))) & 0xffu); }
+__host__ __device__ inline int tile_ext_r(uint32_t tab, int d) {
+  const int e = tile_byte(tab, d);
+  return e == 0 ? 128 : e;
+}
+__host__ __device__ inline int tile_ext_c(uint32_t tab, int d) {
+  const int e = tile_byte(tab, d);
+  return e == 0 ? 256 : e;
+}
+// Extent of the last tile along a dimension whose other tiles have extent e:
+// the smallest multiple of 32 that covers the rem <= e remaining rows, so that
+// only the last tile is padded, by less than 32.
 __host__ __device__ inline int tail_ext(int rem, int e) {
   const int x = (rem + 31) / 32 * 32;
   return x < e ? x : e;
@@ -79,7 +88,7 @@ __host__ __device__ inline int tail_ext(int rem, int e) {
 __host__ __device__ inline bool tiles_valid(uint32_t tab) {
   for (int b = 0; b < 4; ++b) {
     const uint32_t e = (tab >> (8 * b)) & 0xffu;
-    if (e != 32 && e != 64 && e != 128) return false;
+    if (e != 0 && e != 32 && e != 64 && e != 128) return false;
   }
   return true;
 }

@@ -417,6 +417,22 @@ class HeffProblem:
         return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=TASK_DTYPE), ptr.cpu().numpy()
 
 
+def save_davidson_checkpoint(path, energy, psi, info):
+    """Write a Davidson state (energy, FP64 vector, counters) to ``path``
+    (numpy ``.npz``; no pickled objects) so that a later solve can resume
+    from the vector."""
+    np.savez(path, energy=np.float64(energy), psi=psi.detach().double().cpu().numpy(),
+             **{k: np.asarray(v) for k, v in info.items()})
+
+
+def load_davidson_checkpoint(path):
+    """``(energy, psi (CPU FP64 tensor), info)`` written by
+    :func:`save_davidson_checkpoint`."""
+    with np.load(path, allow_pickle=False) as f:
+        info = {k: f[k].item() for k in f.files if k not in ("energy", "psi")}
+        return float(f["energy"]), torch.from_numpy(f["psi"].copy()), info
+
+
 def _memcpy_d2d(dst, src_ptr, nbytes):
     hip = _hip()
     r = hip.hipMemcpyAsync(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), ctypes.c_size_t(nbytes),

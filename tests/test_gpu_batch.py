@@ -94,7 +94,7 @@ def test_batch_rejects_bad_arguments(batch):
         B.apply(psis, "f32", outs=[torch.empty_like(x) for x in psis], beta=0.5)
 
 
-TABLES = [0x80808080, 0x40404040, 0x20202020, 0x80404020, 0x20408080]
+TABLES = [0x80808080, 0x40404040, 0x20202020, 0x80404020, 0x20408080, 0x80804020, 0x00000000]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
@@ -122,7 +122,7 @@ def test_set_tiles_rejects_invalid(batch):
     with pytest.raises(TnsError):
         Hs[1].set_tiles(0x80804010)
     with pytest.raises(TnsError):
-        Hs[1].set_tiles(0)
+        Hs[1].set_tiles(0x00804030)
 
 
 def test_autotune_single_and_batch(batch):
@@ -131,7 +131,7 @@ def test_autotune_single_and_batch(batch):
     ref = Hs[0].apply(x, "f32")
     tab = Hs[0].autotune(x, "f32")
     say("autotuned single table %08x" % tab)
-    assert all(((tab >> (8 * b)) & 0xff) in (32, 64, 128) for b in range(4))
+    assert all(((tab >> (8 * b)) & 0xff) in (0, 32, 64, 128) for b in range(4))
     assert Hs[0].tiles == tab
     assert torch.equal(Hs[0].apply(x, "f32"), ref)
     psis = [to_dev(gaussian_psi(P, 50 + i), torch.float32) for i, P in enumerate(Ps)]

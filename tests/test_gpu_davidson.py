@@ -84,3 +84,36 @@ def test_small_gap_mixed_acceptance():
             assert err <= info["res_norm"] ** 2 / gap * 1.01 + 1e-12
             if tol_res <= 1e-6:
                 assert err <= 1e-8
+
+
+def test_checkpoint_resume(tmp_path):
+    """A solve cut short, written to a checkpoint and resumed from it reaches
+    the uninterrupted solve's energy in fewer products."""
+    from paper_2305_05581_amd.tns import HeffProblem, save_davidson_checkpoint, load_davidson_checkpoint
+    P = synthetic_problem(16, 16, 0, 96, 8, 24, 60, seed=5, gapped=True)
+    H = HeffProblem(P)
+    x0 = to_dev(gapped_guess(P, 1))
+    e_full, _, i_full = H.davidson(x0, tol_res=1e-8)
+    e_cut, x_cut, i_cut = H.davidson(x0, tol_res=1e-8, max_iter=6)
+    assert not i_cut["converged"]
+    path = str(tmp_path / "davidson.npz")
+    save_davidson_checkpoint(path, e_cut, x_cut, i_cut)
+    e_ck, x_ck, info_ck = load_davidson_checkpoint(path)
+    assert e_ck == e_cut and info_ck["iters"] == i_cut["iters"]
+    e_res, _, i_res = H.davidson(x_ck.to("cuda"), tol_res=1e-8)
+    say("checkpoint", e_full, e_res, i_full, i_cut, i_res)
+    assert i_res["converged"] and abs(e_res - e_full) < 1e-10
+    assert i_res["iters"] < i_full["iters"]
+
+
+def test_non_finite_operator_reported():
+    """A NaN in the operator values makes the device Davidson stop with
+    TNS_ERR_NUMERIC after its first iteration (every kernel runs to its end)."""
+    from paper_2305_05581_amd.tns import HeffProblem, TnsError
+    P = synthetic_problem(10, 10, 0, 24, 3, 8, 40, seed=77)
+    vals = torch.from_numpy(P.op_vals.copy()).to("cuda")
+    vals[int(P.blk_off[0])] = float("nan")
+    H = HeffProblem(P, vals64=vals)
+    with pytest.raises(TnsError) as e:
+        H.davidson(to_dev(gaussian_psi(P, 1)), tol_res=1e-8)
+    assert e.value.code == -6
