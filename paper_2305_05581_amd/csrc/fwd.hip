@@ -120,12 +120,11 @@ template <> struct FP<TNS_BF16X3> {
 
 // --- work queues --------------------------------------------------------------------
 // Phase A: panel items, phase B: the schedule's items; queue q of a phase is
-// items[qbase[q], qbase[q+1]).  FP32 / FP64 take every item as two units of
-// work (its first 128 columns and the rest, if any): MULT = 2.
-template <int P> constexpr int work_mult() { return P == TNS_BF16X3 ? 1 : 2; }
-// Thread 0: next work id of phase PH (own XCD queue first), -1 when drained:
-// item MULT id + unit.
-template <int PH, int MULT>
+// items[qbase[q], qbase[q+1]).  BF16X3 takes the lists built at the tile
+// table as given (up to 256 columns per item), FP32 / FP64 those built at its
+// narrow form (up to 128).
+// Thread 0: next item of phase PH (own XCD queue first), -1 when drained.
+template <int PH>
 __device__ inline int pop_work(const FwdArgs &g) {
   const int home = blockIdx.x % g.nq;
   const int64_t *qb = PH == 0 ? g.a_qbase : g.qbase;
@@ -134,7 +133,7 @@ __device__ inline int pop_work(const FwdArgs &g) {
     const int64_t b = qb[q], n = qb[q + 1] - b;
     if (n <= 0) continue;
     const int j = atomicAdd(g.queue + 8 * PH + q, 1);
-    if (j < MULT * n) return (int)(MULT * b + j);
+    if (j < n) return (int)(b + j);
   }
   return -1;
 }
@@ -666,26 +665,18 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
 }
 
 // Item dispatch: BF16X3 covers up to 256 columns per tile (16 TN per wave
-// over 4 waves, TN = ceil(tn / 2)); FP32 / FP64 run unit 0 (the first 128
-// columns) or unit 1 (the rest, nothing if none) of an item.
+// over 4 waves, TN = ceil(tn / 2)); FP32 / FP64 up to 128 (16 TN per wave over
+// 2 waves), which their item lists never exceed.
 template <int P, int KS>
 __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
-                                                                  int wk, int unit) {
-  Item it = load_item(g.items + wk);
+                                                                  int wk) {
+  const Item it = load_item(g.items + wk);
   const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
-  if constexpr (P == TNS_BF16X3) {
-    const int cw = (tn + 1) >> 1;
-#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode, 32 * tn)
-    TNS_TILE_SWITCH(tm, cw, TNS_CALL_B)
+  const int cw = P == TNS_BF16X3 ? (tn + 1) >> 1 : (tn < 4 ? tn : 4);
+  const int ncols = P == TNS_BF16X3 ? 32 * tn : 32 * cw;
+#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode, ncols)
+  TNS_TILE_SWITCH(tm, cw, TNS_CALL_B)
 #undef TNS_CALL_B
-  } else {
-    const int t = unit ? tn - 4 : (tn < 4 ? tn : 4);
-    if (t <= 0) return;
-    if (unit) it.c0 += 128;
-#define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode, 32 * t)
-    TNS_TILE_SWITCH(tm, t, TNS_CALL_B)
-#undef TNS_CALL_B
-  }
 }
 
 // --- phase A: row tiles of a panel as one stream of K steps ---------------------------
@@ -834,30 +825,20 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
       });
 }
 
-// Item dispatch as in phase B: BF16X3 up to 256 columns per tile, FP32 / FP64
-// unit 0 (the first 128 columns) or unit 1 (the rest) of an item.
+// Item dispatch as in phase B: BF16X3 up to 256 columns per tile, FP32 /
+// FP64 up to 128.
 template <int P, int KS>
 __device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
-                                                                  int wk, int unit) {
-  Item it = load_item(g.a_items + wk);
+                                                                  int wk) {
+  const Item it = load_item(g.a_items + wk);
   const int tn = (it.mode >> 16) & 0xff;
-  if constexpr (P == TNS_BF16X3) {
-    switch ((tn + 1) >> 1) {
-      case 1: ring_item_a_t<P, KS, 1>(g, rg, it, 32 * tn); break;
-      case 2: ring_item_a_t<P, KS, 2>(g, rg, it, 32 * tn); break;
-      case 3: ring_item_a_t<P, KS, 3>(g, rg, it, 32 * tn); break;
-      default: ring_item_a_t<P, KS, 4>(g, rg, it, 32 * tn); break;
-    }
-  } else {
-    const int t = unit ? tn - 4 : (tn < 4 ? tn : 4);
-    if (t <= 0) return;
-    if (unit) it.c0 += 128;
-    switch (t) {
-      case 1: ring_item_a_t<P, KS, 1>(g, rg, it, 32); break;
-      case 2: ring_item_a_t<P, KS, 2>(g, rg, it, 64); break;
-      case 3: ring_item_a_t<P, KS, 3>(g, rg, it, 96); break;
-      default: ring_item_a_t<P, KS, 4>(g, rg, it, 128); break;
-    }
+  const int cw = P == TNS_BF16X3 ? (tn + 1) >> 1 : (tn < 4 ? tn : 4);
+  const int ncols = P == TNS_BF16X3 ? 32 * tn : 32 * cw;
+  switch (cw) {
+    case 1: ring_item_a_t<P, KS, 1>(g, rg, it, ncols); break;
+    case 2: ring_item_a_t<P, KS, 2>(g, rg, it, ncols); break;
+    case 3: ring_item_a_t<P, KS, 3>(g, rg, it, ncols); break;
+    default: ring_item_a_t<P, KS, 4>(g, rg, it, ncols); break;
   }
 }
 
@@ -896,19 +877,18 @@ __global__ __launch_bounds__(gth<P>(), (Geo<P, PH>::WG)) void k_fwd(FwdArgs g) {
   __shared__ StageJ<P, KS, NS, 4> st4;
   Ring<P, KS, NS> rg{st0, st1, st2, st3, st4};
   int *s_work = reinterpret_cast<int *>(st0.b);  // the ring is idle between items
-  constexpr int MULT = work_mult<P>();
   for (;;) {
     ring_drain();  // the previous item's trailing (zero) loads have landed
     __syncthreads();
-    if (threadIdx.x == 0) *s_work = pop_work<PH, MULT>(g);
+    if (threadIdx.x == 0) *s_work = pop_work<PH>(g);
     __syncthreads();
     // uniform: the item's metadata then comes through scalar loads, which
     // leave the vector-memory count (ring loads in flight) alone
     const int wk = __builtin_amdgcn_readfirstlane(*s_work);
     __syncthreads();
     if (wk < 0) break;
-    if (PH == 0) ring_item_a<P, KS>(g, rg, wk / MULT, wk % MULT);
-    else ring_item_b<P, KS>(g, rg, wk / MULT, wk % MULT);
+    if (PH == 0) ring_item_a<P, KS>(g, rg, wk);
+    else ring_item_b<P, KS>(g, rg, wk);
   }
   ring_drain();
 }
@@ -1045,9 +1025,7 @@ __global__ void k_batch_cum(BatchArgs b) {
   c[b.n] = run;
 }
 
-// Thread 0: next (instance, work id) of phase ph, own XCD queue first; work
-// id = item MULT id + unit as in pop_work.
-template <int MULT>
+// Thread 0: next (instance, item) of phase ph, own XCD queue first.
 __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk) {
   const int home = blockIdx.x % b.nq;
   for (int k = 0; k < b.nq; ++k) {
@@ -1055,9 +1033,8 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
     const int64_t *c = b.cum + ((int64_t)ph * NQ_MAX + q) * (b.n + 1);
     const int64_t tot = c[b.n];
     if (tot <= 0) continue;
-    const int jm = atomicAdd(b.queue + 8 * ph + q, 1);
-    if (jm >= MULT * tot) continue;
-    const int j = jm / MULT;
+    const int j = atomicAdd(b.queue + 8 * ph + q, 1);
+    if (j >= tot) continue;
     int lo = 0, hi = b.n - 1;  // last instance with c[i] <= j
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -1065,7 +1042,7 @@ __device__ inline void pop_batch(const BatchArgs &b, int ph, int *inst, int *wk)
     }
     const int64_t loc = j - c[lo];
     *inst = lo;
-    *wk = MULT * (int)((ph == 0 ? b.tab[lo].g.a_qbase : b.tab[lo].g.qbase)[q] + loc) + jm % MULT;
+    *wk = (int)((ph == 0 ? b.tab[lo].g.a_qbase : b.tab[lo].g.qbase)[q] + loc);
     return;
   }
   *inst = -1;
@@ -1084,15 +1061,14 @@ __global__ __launch_bounds__(gth<P>(), (Geo<P, PH>::WG)) void k_fwd_batch(BatchA
   for (;;) {
     ring_drain();  // the previous item's trailing (zero) loads have landed
     __syncthreads();
-    if (threadIdx.x == 0) pop_batch<work_mult<P>()>(b, PH, &s_w[0], &s_w[1]);
+    if (threadIdx.x == 0) pop_batch(b, PH, &s_w[0], &s_w[1]);
     __syncthreads();
     const int inst = __builtin_amdgcn_readfirstlane(s_w[0]), wk = __builtin_amdgcn_readfirstlane(s_w[1]);
     __syncthreads();
     if (inst < 0) break;
     const FwdArgs g = load_words(&b.tab[inst].g);
-    constexpr int MULT = work_mult<P>();
-    if (PH == 0) ring_item_a<P, KS>(g, rg, wk / MULT, wk % MULT);
-    else ring_item_b<P, KS>(g, rg, wk / MULT, wk % MULT);
+    if (PH == 0) ring_item_a<P, KS>(g, rg, wk);
+    else ring_item_b<P, KS>(g, rg, wk);
   }
   ring_drain();
 }
@@ -1213,12 +1189,15 @@ static FwdArgs fwd_args(const Plan &p, const void *ops, char *w) {
   g.pp = pp; g.pt = pt;
   g.pp_off = p.pp_off; g.pt_off = p.pt_off;
   g.T = T; g.t_off = p.t_off;
-  g.items = S.items; g.nitems = S.nitems; g.idx = S.idx; g.grp_rows = S.grp_rows; g.grp_cols = S.grp_cols;
-  g.slot_off = S.slot_off; g.qbase = S.qbase; g.partial = part;
+  // FP32 / FP64: the lists at the narrow table when the table has 256-column entries
+  const bool nb = P != TNS_BF16X3 && tiles_wide(S.tiles), na = P != TNS_BF16X3 && tiles_wide(p.pa.tiles);
+  g.items = nb ? S.items_n : S.items; g.nitems = nb ? S.nitems_n : S.nitems;
+  g.idx = S.idx; g.grp_rows = S.grp_rows; g.grp_cols = S.grp_cols;
+  g.slot_off = S.slot_off; g.qbase = nb ? S.qbase_n : S.qbase; g.partial = part;
   g.queue = reinterpret_cast<int32_t *>(w); g.nq = S.nq;
   g.zero = w + 64;
   g.tiles = p.tiles;
-  g.a_items = p.pa.items; g.a_qbase = p.pa.qbase; g.a_tb = p.pa.tb; g.a_gch = p.pa.gch;
+  g.a_items = na ? p.pa.items_n : p.pa.items; g.a_qbase = na ? p.pa.qbase_n : p.pa.qbase; g.a_tb = p.pa.tb; g.a_gch = p.pa.gch;
   g.a_ch = p.pa.ch; g.a_idx = p.pa.idx;
   g.recs = reinterpret_cast<const ChunkRec *>(recs);
   g.segb = p.segb;

@@ -873,16 +873,24 @@ static void layout_sched(Carve &cv, Sched &S, int32_t ngroups, int64_t ntcap, in
   S.sort_tmp_bytes = radix_tmp_u64(S.items_cap);
   S.sort_tmp = cv.take<char>(S.sort_tmp_bytes + 256);
   S.qbase = cv.take<int64_t>(NQ_MAX + 1);
+  if (tiles) {  // room for the narrow list (a later table may have 256-column entries)
+    S.items_n = cv.take<Item>(S.items_cap);
+    S.qbase_n = cv.take<int64_t>(NQ_MAX + 1);
+  } else {
+    S.items_n = S.items;
+    S.qbase_n = S.qbase;
+  }
   S.scratch = cv.take<int64_t>(std::max<int64_t>(ng, chunks_cap) + 1);
   S.scalars = cv.take<int64_t>(8);
 }
 
 // Carves the phase-A panel arrays.
-static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int maxdim, int n_cu, int nq) {
+static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int maxdim, int n_cu, int nq,
+                          uint32_t tiles) {
   A.ngroups = ng;
   A.nq = nq;
   A.ntcap = ntcap;
-  A.tiles = TILES_DEFAULT;
+  A.tiles = tiles;
   // items: a panel's column tiles (smallest extent 32) plus one extra row
   // piece per PANEL_ITEMS_PER_CU share of the work
   A.items_cap = std::max<int64_t>(2 * (int64_t)PANEL_ITEMS_PER_CU * n_cu + (int64_t)ng * ((maxdim + 31) / 32) + 16, ng);
@@ -902,6 +910,8 @@ static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int m
   A.sort_tmp_bytes = std::max(radix_tmp_u64(A.items_cap), radix_tmp_i32(ntcap));
   A.sort_tmp = cv.take<char>(A.sort_tmp_bytes + 256);
   A.qbase = cv.take<int64_t>(NQ_MAX + 1);
+  A.items_n = cv.take<Item>(A.items_cap);
+  A.qbase_n = cv.take<int64_t>(NQ_MAX + 1);
   A.scratch = cv.take<int64_t>(std::max<int64_t>(std::max<int64_t>(ng, ntcap), A.items_cap) + 1);
   A.scalars = cv.take<int64_t>(8);
 }
@@ -946,7 +956,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   for (int s = 0; s < P->nS; ++s)
     ftiles += 2 * (int64_t)((P->dimL[P->psi_sec[4 * s]] + 31) / 32) * ((P->dimR[P->psi_sec[4 * s + 3]] + 31) / 32);
   layout_sched(cv, p.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
-  layout_panels(cv, p.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
+  layout_panels(cv, p.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd, TILES_DEFAULT);
   const int64_t bent = backward ? 3 * ntcap : 0;
   Adjoint &J = p.adj;
   if (backward) {
@@ -970,15 +980,16 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
     J.segb = cv.take<SegRec>(ntcap);
     J.n_vals = 0;
     for (int b = 0; b < P->nBlk; ++b) J.n_vals += (int64_t)P->blk_cols[b] * ld8(P->blk_rows[b]);
-    layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, TILES_DEFAULT, n_xcd, true);
-    layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd);
+    // the adjoint runs in FP32 / FP64 only: its lists are built narrow
+    layout_sched(cv, J.fwd, 2 * P->nS, ntcap, fchunks, ftiles, n_cu, GM, GN, tiles_narrow(TILES_DEFAULT), n_xcd,
+                 true);
+    layout_panels(cv, J.pa, 2 * P->nS, ntcap, maxdim, n_cu, n_xcd, tiles_narrow(TILES_DEFAULT));
   }
-  // counts that the sorts and item indices hold in 32 bits (item indices
-  // twice over: the products count column halves of wide items)
+  // counts that the sorts and item indices hold in 32 bits
   const int64_t caps[] = {bent, p.fwd.items_cap, p.bwd.items_cap, J.fwd.items_cap, p.pa.items_cap, J.pa.items_cap,
                           p.fwd.chunks_cap, p.bwd.chunks_cap};
   for (int64_t c : caps)
-    if (c >= INT32_MAX / 2) return 0;
+    if (c >= INT32_MAX) return 0;
   if (pl) *pl = p;
   return cv.off + 256;
 }
@@ -1012,9 +1023,10 @@ static tns_status finish_sched(const Plan &p, Sched &S, hipStream_t st) {
   return sched_items(S, st);
 }
 
-// Work items of a schedule whose chunks and slots are set: tiles per chunk,
-// longest first within each XCD queue, queue bounds and totals.
-static tns_status sched_items(Sched &S, hipStream_t st) {
+// One item list of a schedule whose chunks and slots are set, at the table
+// S.tiles into S.items / S.qbase: tiles per chunk, longest first within each
+// XCD queue, queue bounds and totals (S.scalars[1..3]).
+static tns_status sched_list(Sched &S, hipStream_t st) {
   const int B = 256;
   int64_t *item_n = reinterpret_cast<int64_t *>(S.keys_out);
   hipLaunchKernelGGL(k_chunk_sizes, dim3(nblk(S.chunks_cap, B)), dim3(B), 0, st, S, S.scratch, item_n);
@@ -1038,9 +1050,25 @@ static tns_status sched_items(Sched &S, hipStream_t st) {
   return TNS_OK;
 }
 
-// Work items of the phase-A panels for the current tile table, grouped by
-// panel in descending panel cost inside each XCD queue.
-static tns_status pan_items(const Plan &p, hipStream_t st) {
+// Work items of a schedule: the list at its table and, when the table has
+// 256-column entries, the list at the narrow form (items_n, qbase_n, totals
+// in scalars[5..7]).  Both cover the same chunks and partial slots.
+static tns_status sched_items(Sched &S, hipStream_t st) {
+  if (tiles_wide(S.tiles)) {
+    Sched W = S;
+    W.tiles = tiles_narrow(S.tiles);
+    W.items = S.items_n;
+    W.qbase = S.qbase_n;
+    W.scalars = S.scalars + 4;
+    const tns_status s = sched_list(W, st);
+    if (s != TNS_OK) return s;
+  }
+  return sched_list(S, st);
+}
+
+// Work items of the phase-A panels for the table p.pa.tiles into p.pa.items /
+// p.pa.qbase, grouped by panel in descending panel cost inside each XCD queue.
+static tns_status pan_list(const Plan &p, hipStream_t st) {
   const int B = 256;
   const Panels &A = p.pa;
   const int ng = A.ngroups;
@@ -1060,6 +1088,21 @@ static tns_status pan_items(const Plan &p, hipStream_t st) {
   hipLaunchKernelGGL(k_pan_gather, dim3(nblk(A.items_cap + 1, B)), dim3(B), 0, st, p);
   TNS_HIP(hipGetLastError());
   return TNS_OK;
+}
+
+// Panel items at the panels' table and, when it has 256-column entries, at
+// its narrow form (items_n, qbase_n, totals in scalars[4..6]).
+static tns_status pan_items(const Plan &p, hipStream_t st) {
+  if (tiles_wide(p.pa.tiles)) {
+    Plan q = p;
+    q.pa.tiles = tiles_narrow(p.pa.tiles);
+    q.pa.items = p.pa.items_n;
+    q.pa.qbase = p.pa.qbase_n;
+    q.pa.scalars = p.pa.scalars + 4;
+    const tns_status s = pan_list(q, st);
+    if (s != TNS_OK) return s;
+  }
+  return pan_list(p, st);
 }
 
 // Phase-A panels of a built task list: panel order of the tasks, chunks,
@@ -1099,6 +1142,18 @@ static void read_sched(Sched &S, const int64_t *h) {
   S.nchunks = h[1];
   S.nitems = h[2];
   S.partial_elems = h[3];
+  S.nitems_n = tiles_wide(S.tiles) ? h[6] : h[2];
+}
+
+static bool sched_fits(const Sched &S) {
+  return S.nchunks <= S.chunks_cap && S.nitems <= S.items_cap && S.nitems_n <= S.items_cap;
+}
+
+// Panel item counts (scalars[2], [6]) as read back from the device.
+static bool pan_counts(Panels &A, int64_t n, int64_t n_narrow) {
+  A.nitems = n;
+  A.nitems_n = tiles_wide(A.tiles) ? n_narrow : n;
+  return A.nitems <= A.items_cap && A.nitems_n <= A.items_cap;
 }
 
 Plan adjoint_plan(const Plan &p) {
@@ -1144,20 +1199,20 @@ static tns_status build_adjoint(Plan &p, const int64_t *boff, const int32_t *bld
   TNS_HIP(hipMemcpyAsync(h, q.fwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   read_sched(q.fwd, h);
-  if (q.fwd.nchunks > q.fwd.chunks_cap || q.fwd.nitems > q.fwd.items_cap) return TNS_ERR_WORKSPACE;
+  if (!sched_fits(q.fwd)) return TNS_ERR_WORKSPACE;
   s = build_panels(q, st);
   if (s != TNS_OK) return s;
   if (q.ntasks > 0) hipLaunchKernelGGL(k_segb, dim3(nblk(q.ntasks, B)), dim3(B), 0, st, q, q.ntasks);
   TNS_HIP(hipGetLastError());
-  int64_t ext[3];
+  int64_t ext[4];
   TNS_HIP(hipMemcpyAsync(ext, q.pa.scalars + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 1, q.pa.ch + q.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 2, q.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 3, q.pa.scalars + 6, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   q.pa.t_elems = ext[0];
   q.pa.nchunks = ext[1];
-  q.pa.nitems = ext[2];
-  if (q.pa.nitems > q.pa.items_cap) return TNS_ERR_WORKSPACE;
+  if (!pan_counts(q.pa, ext[2], ext[3])) return TNS_ERR_WORKSPACE;
   J.fwd = q.fwd;
   J.pa = q.pa;
   J.t_elems = ext[0];
@@ -1260,7 +1315,7 @@ tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const 
   TNS_HIP(hipStreamSynchronize(st));
   p.ntasks = nt32;
   read_sched(p.fwd, h);
-  if (p.fwd.nchunks > p.fwd.chunks_cap || p.fwd.nitems > p.fwd.items_cap) return TNS_ERR_WORKSPACE;
+  if (!sched_fits(p.fwd)) return TNS_ERR_WORKSPACE;
 
   // phase-A panels and the offsets of the forward intermediates
   s = build_panels(p, st);
@@ -1269,19 +1324,19 @@ tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const 
   TNS_HIP(hipGetLastError());
 
   if (!backward) {
-    int64_t ext[5];
+    int64_t ext[6];
     TNS_HIP(hipMemcpyAsync(ext, p.pa.scalars + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     TNS_HIP(hipMemcpyAsync(ext + 1, p.pp_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     TNS_HIP(hipMemcpyAsync(ext + 2, p.pt_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     TNS_HIP(hipMemcpyAsync(ext + 3, p.pa.ch + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     TNS_HIP(hipMemcpyAsync(ext + 4, p.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TNS_HIP(hipMemcpyAsync(ext + 5, p.pa.scalars + 6, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     TNS_HIP(hipStreamSynchronize(st));
     p.t_elems = p.pa.t_elems = ext[0];
     p.pp_elems = ext[1];
     p.pt_elems = ext[2];
     p.pa.nchunks = ext[3];
-    p.pa.nitems = ext[4];
-    if (p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
+    if (!pan_counts(p.pa, ext[4], ext[5])) return TNS_ERR_WORKSPACE;
     p.no_backward = 1;
   } else {
   // backward grouping: stable sort of (key, task) entries by key
@@ -1301,12 +1356,13 @@ tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const 
   s = finish_sched(p, p.bwd, st);
   if (s != TNS_OK) return s;
   TNS_HIP(hipMemcpyAsync(h, p.bwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
-  int64_t ext[5];
+  int64_t ext[6];
   TNS_HIP(hipMemcpyAsync(ext, p.pa.scalars + 3, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 1, p.pp_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 2, p.pt_off + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 3, p.pa.ch + p.ntasks, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipMemcpyAsync(ext + 4, p.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(ext + 5, p.pa.scalars + 6, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   read_sched(p.bwd, h);
   p.t_elems = ext[0];
@@ -1314,9 +1370,8 @@ tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const 
   p.pt_elems = ext[2];
   p.pa.t_elems = ext[0];
   p.pa.nchunks = ext[3];
-  p.pa.nitems = ext[4];
-  if (p.bwd.nchunks > p.bwd.chunks_cap || p.bwd.nitems > p.bwd.items_cap) return TNS_ERR_WORKSPACE;
-  if (p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
+  if (!sched_fits(p.bwd)) return TNS_ERR_WORKSPACE;
+  if (!pan_counts(p.pa, ext[4], ext[5])) return TNS_ERR_WORKSPACE;
 
   // adjoint task list and schedule (d psi of the backward)
   std::vector<int64_t> toff(std::max(1, P->nBlk));
@@ -1364,13 +1419,12 @@ extern "C" tns_status tns_set_tiles(tns_tasklist *tl, uint32_t tiles, hipStream_
   if (s != TNS_OK) return s;
   s = pan_items(p, st);
   if (s != TNS_OK) return s;
-  int64_t h[8], na = 0;
+  int64_t h[8], na[8];
   TNS_HIP(hipMemcpyAsync(h, p.fwd.scalars, sizeof(h), hipMemcpyDeviceToHost, st));
-  TNS_HIP(hipMemcpyAsync(&na, p.pa.scalars + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  TNS_HIP(hipMemcpyAsync(na, p.pa.scalars, sizeof(na), hipMemcpyDeviceToHost, st));
   TNS_HIP(hipStreamSynchronize(st));
   read_sched(p.fwd, h);
-  p.pa.nitems = na;
-  if (p.fwd.nitems > p.fwd.items_cap || p.pa.nitems > p.pa.items_cap) return TNS_ERR_WORKSPACE;
+  if (!pan_counts(p.pa, na[2], na[6]) || !sched_fits(p.fwd)) return TNS_ERR_WORKSPACE;
   tl->nitems = p.fwd.nitems;
   return TNS_OK;
 }

@@ -85,6 +85,22 @@ __host__ __device__ inline int tail_ext(int rem, int e) {
   const int x = (rem + 31) / 32 * 32;
   return x < e ? x : e;
 }
+// Whether a table has 256-column entries, and its narrow form (those entries
+// read as 128): the FP32 / FP64 kernels take at most 128 columns per tile, so
+// schedules built at a table with 256-column entries keep a second item list
+// at the narrow form for them.
+__host__ __device__ inline bool tiles_wide(uint32_t tab) {
+  if (tab == 0) return false;
+  for (int b = 0; b < 4; ++b)
+    if (((tab >> (8 * b)) & 0xffu) == 0) return true;
+  return false;
+}
+__host__ __device__ inline uint32_t tiles_narrow(uint32_t tab) {
+  uint32_t r = tab;
+  for (int b = 0; b < 4; ++b)
+    if (((tab >> (8 * b)) & 0xffu) == 0) r |= 0x80u << (8 * b);
+  return r;
+}
 __host__ __device__ inline bool tiles_valid(uint32_t tab) {
   for (int b = 0; b < 4; ++b) {
     const uint32_t e = (tab >> (8 * b)) & 0xffu;
@@ -131,8 +147,12 @@ struct Sched {
   void *sort_tmp;
   size_t sort_tmp_bytes;
   int64_t *qbase;       // [NQ_MAX + 1]: queue q = items[qbase[q], qbase[q+1])
+  // the same chunks' items at tiles_narrow(tiles), built when tiles_wide(tiles)
+  Item *items_n;        // [items_cap]
+  int64_t *qbase_n;     // [NQ_MAX + 1]
+  int64_t nitems_n;
   int64_t *scratch;     // [max(ngroups, chunks_cap) + 1]
-  int64_t *scalars;     // [8]
+  int64_t *scalars;     // [8]: 0 total cost, 1 chunks, 2 items, 3 partial elements; 5..7: 1..3 of the narrow list
 };
 
 // Phase-A panels.  Panel 2 s + c holds the tasks with input sector s and
@@ -178,8 +198,12 @@ struct Panels {
   void *sort_tmp;
   size_t sort_tmp_bytes;
   int64_t *qbase;      // [NQ_MAX + 1]: queue q = items[qbase[q], qbase[q+1])
+  // the panels' items at tiles_narrow(tiles), built when tiles_wide(tiles)
+  Item *items_n;       // [items_cap]
+  int64_t *qbase_n;    // [NQ_MAX + 1]
+  int64_t nitems_n;
   int64_t *scratch;    // [max(ngroups, ntcap, items_cap) + 1]
-  int64_t *scalars;    // [8]: total item cost, item target cost, items, intermediate elements
+  int64_t *scalars;    // [8]: total item cost, item target cost, items, intermediate elements; 4..6: 0..2 of the narrow list
 };
 
 // One segment of a phase-B work item (a task of its chunk), in the order of
