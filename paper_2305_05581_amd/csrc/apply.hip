@@ -48,12 +48,6 @@ template <> struct Prec<TNS_F32> {
   typedef f4 accv;
   static constexpr int S = KK + 2;
 };
-template <> struct Prec<TNS_BF16X3> {
-  typedef float elem;    // psi / sigma type
-  typedef float acc;
-  typedef f4 accv;
-  static constexpr int S = KK + 8;  // bf16 elements; 80-byte rows keep 16-byte alignment
-};
 
 struct ApplyArgs {
   const Item *items;
@@ -66,8 +60,8 @@ struct ApplyArgs {
   const int32_t *psi_sec, *dimL, *dimR;
   const int64_t *psi_off, *blk_off, *slot_off;
   const int32_t *blk_ld, *blk_rows, *blk_cols;
-  const void *ops;       // F64: double*, F32: float*, BF16X3: uint16 hi[n_vals] then lo[n_vals]
-  const void *psi;       // F64: double*, F32: float*, BF16X3: uint16 hi[psi_dim] then lo[psi_dim]
+  const void *ops;       // operator values (F64: double*, F32: float*)
+  const void *psi;       // psi in the same precision
   const void *grad;      // d loss / d sigma (backward modes), psi layout
   void *partial;         // acc type
   int64_t n_vals, psi_dim;
@@ -96,7 +90,7 @@ struct View {
   int32_t si, sk; // element (i, k) at p[i * si + k * sk]
   int32_t rows, cols;
   int32_t ident;  // identity operator: (i == k)
-  int32_t src;    // 0 = operator values, 1 = psi, 2 = grad sigma (loaders of the BF16 kernel)
+  int32_t src;    // 0 = operator values, 1 = psi, 2 = grad sigma
   int64_t off;    // element offset of (0, 0) in its array
 };
 
@@ -533,12 +527,9 @@ static inline unsigned nb(int64_t n, int b) {
 
 static size_t elem_bytes(tns_prec p) { return p == TNS_F64 ? 8 : 4; }
 
-// Workspace: [queue counter | partial slots | (BF16X3) psi hi, lo]
-static size_t apply_ws(const Sched &S, int64_t psi_dim, tns_prec prec) {
-  size_t b = 256;
-  b += align_up((size_t)std::max<int64_t>(S.partial_elems, 1) * elem_bytes(prec), 256);
-  if (prec == TNS_BF16X3) b += align_up((size_t)psi_dim * 2 * sizeof(uint16_t), 256);
-  return b;
+// Workspace of k_apply (FP64 / FP32): [queue counter | partial slots]
+static size_t apply_ws(const Sched &S, tns_prec prec) {
+  return 256 + align_up((size_t)std::max<int64_t>(S.partial_elems, 1) * elem_bytes(prec), 256);
 }
 
 template <class K>
@@ -625,7 +616,7 @@ __global__ __launch_bounds__(256) void k_transpose_blocks(const T *__restrict__ 
 // Backward workspace: [k_apply: queue counter | partial slots of the
 // operator-gradient schedule] [transposed operator values] [workspace of the
 // adjoint forward product].
-static size_t bwd_transposed_at(const Plan &p, tns_prec prec) { return apply_ws(p.bwd, p.psi_dim, prec); }
+static size_t bwd_transposed_at(const Plan &p, tns_prec prec) { return apply_ws(p.bwd, prec); }
 static size_t bwd_fwd_at(const Plan &p, tns_prec prec) {
   return bwd_transposed_at(p, prec) +
          align_up((size_t)std::max<int64_t>(p.adj.n_vals, 1) * elem_bytes(prec), 256);
