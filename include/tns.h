@@ -376,24 +376,43 @@ tns_status tns_renormalize(const tns_renorm_plan *plan, tns_prec prec, const dou
  * range from its first to the end of its last block.
  * tns_ttcache_sizes: host and device bytes of the plan (host only: the walk,
  * the epochs' problems and their validation); TNS_ERR_WORKSPACE when a left
- * and a right operator together exceed the cache.  tns_ttcache_build: builds
- * every epoch's task list into dev_ws (synchronises the stream); host_buf and
- * dev_ws must outlive the plan.  tns_apply_heff_streamed: sigma := H_eff psi
- * (FP64 or FP32; host_vals in that type, the problem's value layout), one
- * copy per load and one product per epoch, in order on `stream`.  The sum over
- * epochs runs in a fixed order (deterministic); it differs from
- * tns_apply_heff's order only by the grouping of terms. */
+ * and a right operator together exceed the cache, TNS_ERR_ARG for an unknown
+ * mode.  tns_ttcache_build: builds every epoch's task list into dev_ws
+ * (synchronises the stream); host_buf and dev_ws must outlive the plan; mode
+ * as given to tns_ttcache_sizes.
+ * Buffering (mode): when the walk needs more than one epoch and every term's
+ * two operators fit in half the cache, the plan may be double-buffered
+ * (halves = 1): the walk runs on half the cache, keeping nothing from one
+ * epoch to the next, and epochs alternate between the halves.  TNS_TT_DOUBLE
+ * takes the halves whenever they fit, TNS_TT_SINGLE never, TNS_TT_AUTO when
+ * the elements copied after the first epoch (the copies the halves hide)
+ * exceed 3 M per extra epoch (a product's fixed cost, measured at D = 1024 in
+ * FP64).
+ * tns_apply_heff_streamed: sigma := H_eff psi (FP64 or FP32; host_vals in
+ * that type, the problem's value layout), one copy per load and one product
+ * per epoch.  Single-buffered, all of it in order on `stream`;
+ * double-buffered, the copies run on a second stream of the device (created
+ * on first use, default priority, shared by all calls on the device), each
+ * epoch's copies after the earlier work on `stream` and after the product of
+ * two epochs before, which overlaps them with the previous epoch's product;
+ * the call's last product waits for every copy.  Calls that overlap in time
+ * on one device must be issued on one stream.  The sum over epochs runs in a
+ * fixed order (deterministic); it differs from tns_apply_heff's order only by
+ * the grouping of terms. */
+enum { TNS_TT_AUTO = 0, TNS_TT_SINGLE = 1, TNS_TT_DOUBLE = 2 };
 typedef struct {
   int64_t n_epochs, n_loads;
   int64_t loaded_elems;  /* operator elements copied per product                    */
   int64_t naive_elems;   /* elements a per-term load of both operators would copy   */
   int64_t ntasks, total_flops, cache_elems;
+  int64_t halves;        /* 1: double-buffered                                      */
   uint8_t opaque[256];
 } tns_ttcache_plan;
-tns_status tns_ttcache_sizes(const tns_problem *prob, int64_t cache_elems, size_t *host_bytes, size_t *dev_bytes,
-                             int64_t *n_epochs);
-tns_status tns_ttcache_build(const tns_problem *prob, int64_t cache_elems, void *host_buf, size_t host_bytes,
-                             void *dev_ws, size_t dev_bytes, tns_ttcache_plan *out, hipStream_t stream);
+tns_status tns_ttcache_sizes(const tns_problem *prob, int64_t cache_elems, int32_t mode, size_t *host_bytes,
+                             size_t *dev_bytes, int64_t *n_epochs);
+tns_status tns_ttcache_build(const tns_problem *prob, int64_t cache_elems, int32_t mode, void *host_buf,
+                             size_t host_bytes, void *dev_ws, size_t dev_bytes, tns_ttcache_plan *out,
+                             hipStream_t stream);
 size_t tns_ttcache_apply_workspace_bytes(const tns_ttcache_plan *plan, tns_prec prec);
 tns_status tns_apply_heff_streamed(const tns_ttcache_plan *plan, tns_prec prec, const void *host_vals, void *cache,
                                    const void *psi, void *sigma, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -28,9 +28,7 @@
 namespace tns {
 
 constexpr int KK = 32;    // K1 step of stage 1
-constexpr int KC = 32;    // column chunk of M (K of stage 2)
 constexpr int CMAX = 256; // output columns held in accumulators per pass
-constexpr int YG = 128;   // columns of Y staged in LDS at a time
 constexpr int NWG = 256;  // threads per workgroup (4 waves)
 
 // --- precision traits -------------------------------------------------------

@@ -156,6 +156,7 @@ __device__ inline int pop_work(const FwdArgs &g) {
 // (T, padded psi) hold zeros beyond K, so the k-tail of an operator row
 // always meets zeros.
 typedef __bf16 bfx4 __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 // KS: k-halves per stage of FP32 / FP64 (each half 4 k-vectors of 16 bytes
 // per row, one array of chunks per operand and half); BF16X3 uses KS = 1 and
@@ -692,7 +693,6 @@ __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs 
 template <int P>
 __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g, LoadSetT<P> &ls, int ch, int ch_end,
                                                                 int K) {
-  typedef typename FP<P>::E E;
   const int w = threadIdx.x >> 6;
   constexpr bool BF = P == TNS_BF16X3;
   constexpr int NU = 2;
@@ -719,7 +719,12 @@ __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g
 // acc[i][j] rows = T columns c0 + wn 16 TN + 16 i + .., columns = the rows of
 // chunk ch + 4 wm + j).  Row r of chunk c lies at tbase + (16 c + r) ldT;
 // rows beyond the chunk's task and columns at or beyond cend are not stored.
-// FP32 and BF16X3 write 4 consecutive columns per lane as one vector.
+// FP32 writes 4 consecutive columns per lane as one vector.  BF16X3: the
+// lanes l and l ^ 16 hold the two halves of one 8-column group (row starts
+// and cend are multiples of 8, so both store or neither); they trade 8 bytes
+// so that the even lane writes the group's 8 high halves and the odd one its
+// 8 low halves, each as one 16-byte store: a row's 16 columns are 64
+// contiguous bytes from 4 lanes.
 template <int P, int TN>
 __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[TN][4],
                                                                      int ch, int ch_end, int64_t tbase, int c0,
@@ -735,7 +740,29 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
       const int vr = cld(&r->vrows);
       const double alpha = cld(&r->alpha);
       const int64_t orow = tbase + ((int64_t)c * PCH + l16) * ldT;
-      if (l16 < vr) {
+      if constexpr (P == TNS_BF16X3) {
+#pragma unroll
+        for (int i = 0; i < TN; ++i) {
+          const int col = c0 + wn * 16 * TN + i * 16 + 4 * lg;
+          const f4 x = (float)alpha * acc[i][j];
+          const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+          const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
+                          (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
+          const uint64_t hb = __builtin_bit_cast(uint64_t, h), lb = __builtin_bit_cast(uint64_t, l);
+          const bool odd = lg & 1;
+          // the even lane takes its partner's high halves, the odd one its partner's low halves
+          const uint64_t got = __shfl_xor((unsigned long long)(odd ? hb : lb), 16);
+          if (l16 < vr && col < ldT && col < cend) {
+            u64x2 v;
+            v[0] = odd ? got : hb;
+            v[1] = odd ? lb : got;
+            // column col of the group: u16 index 2 (orow + col) is the start
+            // of the group's high halves (col = 0 mod 8) or of its low halves
+            // (col = 4 mod 8)
+            *gptr(reinterpret_cast<u64x2 *>(reinterpret_cast<uint16_t *>(g.T) + 2 * (orow + col))) = v;
+          }
+        }
+      } else if (l16 < vr) {
 #pragma unroll
         for (int i = 0; i < TN; ++i) {
           const int col0 = c0 + wn * 16 * TN + i * 16;
@@ -751,18 +778,7 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
             if (col < ldT && col < cend) {
               const f4 x = (float)alpha * acc[i][j];
               const int64_t o = orow + col;
-              if constexpr (P == TNS_F32) {
-                *gptr(reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o)) = x;
-              } else {
-                const bfx4 h = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
-                const bfx4 l = {(__bf16)(x[0] - (float)h[0]), (__bf16)(x[1] - (float)h[1]),
-                                (__bf16)(x[2] - (float)h[2]), (__bf16)(x[3] - (float)h[3])};
-                // four consecutive elements (o a multiple of 4): 8 bytes of
-                // high halves and, 16 bytes further, 8 bytes of low halves
-                uint16_t *Th = reinterpret_cast<uint16_t *>(g.T) + bfx_hi(o);
-                *gptr(reinterpret_cast<uint64_t *>(Th)) = __builtin_bit_cast(uint64_t, h);
-                *gptr(reinterpret_cast<uint64_t *>(Th + 8)) = __builtin_bit_cast(uint64_t, l);
-              }
+              *gptr(reinterpret_cast<f4 *>(reinterpret_cast<float *>(g.T) + o)) = x;
             }
           }
         }
@@ -777,7 +793,6 @@ template <int P, int KS, int TN>
 __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
                                                                     const Item &it, int ncols) {
   typedef typename FP<P>::A4 A4;
-  typedef typename FP<P>::E E;
   constexpr int BK = RingL<P, KS>::BK;
   constexpr int NL = P == TNS_BF16X3 ? 2 + TN : RingL<P, KS>::LOADS;
   const int cend = it.c0 + ncols;

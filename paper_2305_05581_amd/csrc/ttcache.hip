@@ -9,13 +9,30 @@
 // pending term runs as one product (tns_apply_heff, accumulating into sigma)
 // whose task list was built at plan time with the blocks' cache offsets, and
 // the space of the nodes already left is given back.
+//
+// When that walk needs more than one epoch and every term's two operators fit
+// in half the cache, the plan may double-buffer instead: the walk runs on half
+// the cache with nothing kept from one epoch to the next, epochs alternate
+// between the halves, and the copies of epoch k + 1 run on a second stream
+// while epoch k's product runs (they wait only for the product of epoch k - 1,
+// the last one that read their half).  That hides the copies after the first
+// epoch's but needs more, smaller products, each with a fixed cost (thinner
+// panels and task chunks, one more launch sequence); the plan takes the
+// halves when the copy they hide exceeds the extra epochs' cost, counted as
+// TT_EPOCH_ELEMS copied elements per epoch.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "kern.hpp"
 #include "tns_internal.hpp"
 
 namespace tns {
+
+// Fixed cost of one more epoch in elements of copy time: 0.43 ms per product
+// measured at D = 1024 (FP64, MI355X), the time of 3 M FP64 elements over the
+// 57 GB/s pinned host link.
+constexpr int64_t TT_EPOCH_ELEMS = 3000000;
 
 struct TtLoad {
   int64_t host_off, cache_off, elems;  // elements of the operator value arrays
@@ -30,6 +47,7 @@ struct TtEpoch {
 
 struct TtHeader {
   int64_t n_epochs, n_loads, cache_elems, psi_dim;
+  int64_t halves;  // 1: double-buffered (epoch k in half k mod 2)
   TtEpoch *epochs;
   TtLoad *loads;
   tns_tasklist *tls;  // one per epoch
@@ -72,9 +90,12 @@ static void op_extents(const tns_problem *P, std::vector<int64_t> &lo, std::vect
 // level-1 operator.  Every level-1 operator is thus copied once and every
 // level-2 operator at most once per parent (never more than a per-term copy),
 // operators still on the stack are reused across subtrees, and a cache that
-// holds everything copies each operator once and runs one product.  Returns
-// TNS_ERR_WORKSPACE when two operators of one term together exceed the cache.
-static tns_status tt_walk(const tns_problem *P, int64_t cap, int lead, std::vector<TtPlanEpoch> &epochs,
+// holds everything copies each operator once and runs one product.  With
+// carry false an epoch keeps nothing of the previous one (the level-1
+// operator is copied again), so that consecutive epochs may use separate
+// buffers.  Returns TNS_ERR_WORKSPACE when two operators of one term together
+// exceed the cache.
+static tns_status tt_walk(const tns_problem *P, int64_t cap, int lead, bool carry, std::vector<TtPlanEpoch> &epochs,
                           int64_t *naive, int64_t *loaded) {
   std::vector<int64_t> lo, hi;
   op_extents(P, lo, hi);
@@ -133,10 +154,10 @@ static tns_status tt_walk(const tns_problem *P, int64_t cap, int lead, std::vect
         bottom = bottom || l.cache_off == 0;
       }
       cur.loads.clear();
-      kept = o1 >= 0 && at[o1] == 0 && !bottom;  // a copy made before this epoch stays valid
+      kept = carry && o1 >= 0 && at[o1] == 0 && !bottom;  // a copy made before this epoch stays valid
     } else {
       flush();
-      kept = o1 >= 0 && at[o1] == 0;  // its copy at the bottom stays valid
+      kept = carry && o1 >= 0 && at[o1] == 0;  // its copy at the bottom stays valid
     }
     for (int x : on) at[x] = -1;
     on.clear();
@@ -230,26 +251,53 @@ static void tt_sub(const tns_problem *P, const TtPlanEpoch &e, int64_t cap, TtSu
   s.P.term_coef = s.tc.data();
 }
 
-// Blocks are read at element offsets that are multiples of 8: the cache keeps
-// each operator's first element at a multiple of 8 (sizes rounded up), so the
-// rebased offsets stay multiples of 8 when the host ones are.
-static tns_status tt_plan(const tns_problem *P, int64_t cap, std::vector<TtPlanEpoch> &epochs,
-                          std::vector<size_t> &ws, int64_t *naive, int64_t *loaded) {
-  int32_t nmax = 0, maxdim = 0;
-  tns_status s = validate_problem(P, &nmax, &maxdim);
-  if (s != TNS_OK) return s;
-  if (cap <= 0) return TNS_ERR_ARG;
-  // the tree is a choice: level 1 the left or the right operators; keep the
-  // one that copies fewer elements (left on a tie)
-  const int64_t c8 = (cap / 8) * 8;
+// The walk of the better tree: level 1 the left or the right operators,
+// whichever copies fewer elements (left on a tie).
+static tns_status tt_best_walk(const tns_problem *P, int64_t cap, bool carry, std::vector<TtPlanEpoch> &epochs,
+                               int64_t *naive, int64_t *loaded) {
   std::vector<TtPlanEpoch> alt;
   int64_t nv2 = 0, ld2 = 0;
-  s = tt_walk(P, c8, 0, epochs, naive, loaded);
-  const tns_status s2 = tt_walk(P, c8, 1, alt, &nv2, &ld2);
+  tns_status s = tt_walk(P, cap, 0, carry, epochs, naive, loaded);
+  const tns_status s2 = tt_walk(P, cap, 1, carry, alt, &nv2, &ld2);
   if (s2 == TNS_OK && (s != TNS_OK || ld2 < *loaded)) {
     epochs.swap(alt);
     *loaded = ld2;
     s = TNS_OK;
+  }
+  return s;
+}
+
+// Blocks are read at element offsets that are multiples of 8: the cache keeps
+// each operator's first element at a multiple of 8 (sizes rounded up), so the
+// rebased offsets stay multiples of 8 when the host ones are.
+static tns_status tt_plan(const tns_problem *P, int64_t cap, int32_t mode, std::vector<TtPlanEpoch> &epochs,
+                          std::vector<size_t> &ws, int64_t *naive, int64_t *loaded, bool *halves) {
+  int32_t nmax = 0, maxdim = 0;
+  tns_status s = validate_problem(P, &nmax, &maxdim);
+  if (s != TNS_OK) return s;
+  if (cap <= 0 || (mode != TNS_TT_AUTO && mode != TNS_TT_SINGLE && mode != TNS_TT_DOUBLE)) return TNS_ERR_ARG;
+  const int64_t c8 = (cap / 8) * 8;
+  s = tt_best_walk(P, c8, true, epochs, naive, loaded);
+  if (s != TNS_OK) return s;
+  *halves = false;
+  const int64_t h8 = c8 / 16 * 8;  // half the cache, a multiple of 8
+  if (mode != TNS_TT_SINGLE && epochs.size() > 1 && h8 > 0) {
+    std::vector<TtPlanEpoch> hv;
+    int64_t nv = 0, ld = 0;
+    int64_t first = 0;
+    const bool ok = tt_best_walk(P, h8, false, hv, &nv, &ld) == TNS_OK;
+    if (ok)
+      for (auto &l : hv[0].loads) first += l.elems;
+    const int64_t hidden = ld - first, extra = ((int64_t)hv.size() - (int64_t)epochs.size()) * TT_EPOCH_ELEMS;
+    if (ok && (mode == TNS_TT_DOUBLE || hidden > extra)) {
+      for (size_t k = 1; k < hv.size(); k += 2) {  // odd epochs in the upper half
+        for (auto &l : hv[k].loads) l.cache_off += h8;
+        for (auto &r : hv[k].resident) r.second += h8;
+      }
+      epochs.swap(hv);
+      *loaded = ld;
+      *halves = true;
+    }
   }
   if (s != TNS_OK) return s;
   ws.clear();
@@ -271,17 +319,51 @@ __global__ void k_tt_zero(T *p, int64_t n) {
   GRID_STRIDE(i, n) p[i] = T(0);
 }
 
+// Copy stream and events of double-buffered products, one set per device,
+// created on first use with that device current (default priority).  Every
+// call on a device shares them: calls that overlap in time on one device
+// must be issued on one stream.
+struct TtStreams {
+  hipStream_t copy = nullptr;
+  hipEvent_t start = nullptr, load[2] = {nullptr, nullptr}, prod[2] = {nullptr, nullptr};
+};
+constexpr int TT_MAX_DEVICES = 64;
+static std::mutex g_tt_mu;
+static TtStreams g_tt[TT_MAX_DEVICES];
+
+static tns_status tt_streams(hipStream_t st, TtStreams **out) {
+  int dev = -1, cur = -1;
+  TNS_HIP(hipStreamGetDevice(st, &dev));
+  TNS_HIP(hipGetDevice(&cur));
+  if (dev < 0 || dev >= TT_MAX_DEVICES) return TNS_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_tt_mu);
+  TtStreams &T = g_tt[dev];
+  if (!T.copy) {
+    if (dev != cur) TNS_HIP(hipSetDevice(dev));
+    TtStreams n;
+    hipError_t e = hipStreamCreateWithFlags(&n.copy, hipStreamNonBlocking);
+    hipEvent_t *evs[5] = {&n.start, &n.load[0], &n.load[1], &n.prod[0], &n.prod[1]};
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(evs[i], hipEventDisableTiming);
+    if (dev != cur) TNS_HIP(hipSetDevice(cur));
+    if (e != hipSuccess) return TNS_ERR_HIP;
+    T = n;
+  }
+  *out = &T;
+  return TNS_OK;
+}
+
 }  // namespace tns
 
 using namespace tns;
 
-extern "C" tns_status tns_ttcache_sizes(const tns_problem *P, int64_t cache_elems, size_t *host_bytes,
+extern "C" tns_status tns_ttcache_sizes(const tns_problem *P, int64_t cache_elems, int32_t mode, size_t *host_bytes,
                                         size_t *dev_bytes, int64_t *n_epochs) {
   if (!host_bytes || !dev_bytes) return TNS_ERR_ARG;
   std::vector<TtPlanEpoch> epochs;
   std::vector<size_t> ws;
   int64_t naive = 0, loaded = 0;
-  const tns_status s = tt_plan(P, cache_elems, epochs, ws, &naive, &loaded);
+  bool halves = false;
+  const tns_status s = tt_plan(P, cache_elems, mode, epochs, ws, &naive, &loaded, &halves);
   if (s != TNS_OK) return s;
   size_t nl = 0, db = 0;
   for (auto &e : epochs) nl += e.loads.size();
@@ -293,17 +375,19 @@ extern "C" tns_status tns_ttcache_sizes(const tns_problem *P, int64_t cache_elem
   return TNS_OK;
 }
 
-extern "C" tns_status tns_ttcache_build(const tns_problem *P, int64_t cache_elems, void *host_buf, size_t host_bytes,
-                                        void *dev_ws, size_t dev_bytes, tns_ttcache_plan *out, hipStream_t st) {
+extern "C" tns_status tns_ttcache_build(const tns_problem *P, int64_t cache_elems, int32_t mode, void *host_buf,
+                                        size_t host_bytes, void *dev_ws, size_t dev_bytes, tns_ttcache_plan *out,
+                                        hipStream_t st) {
   if (!host_buf || !dev_ws || !out) return TNS_ERR_ARG;
   std::vector<TtPlanEpoch> epochs;
   std::vector<size_t> ws;
   int64_t naive = 0, loaded = 0;
-  tns_status s = tt_plan(P, cache_elems, epochs, ws, &naive, &loaded);
+  bool halves = false;
+  tns_status s = tt_plan(P, cache_elems, mode, epochs, ws, &naive, &loaded, &halves);
   if (s != TNS_OK) return s;
   size_t hb = 0, db = 0;
   int64_t ne = 0;
-  s = tns_ttcache_sizes(P, cache_elems, &hb, &db, &ne);
+  s = tns_ttcache_sizes(P, cache_elems, mode, &hb, &db, &ne);
   if (s != TNS_OK) return s;
   if (host_bytes < hb || dev_bytes < db) return TNS_ERR_WORKSPACE;
   memset(out, 0, sizeof(*out));
@@ -320,6 +404,7 @@ extern "C" tns_status tns_ttcache_build(const tns_problem *P, int64_t cache_elem
   h.n_loads = (int64_t)nl;
   h.cache_elems = cache_elems;
   h.psi_dim = P->psi_off[P->nS];
+  h.halves = halves ? 1 : 0;
   int64_t li = 0, doff = 0, tasks = 0, flops = 0;
   char *dws = reinterpret_cast<char *>(dev_ws);
   for (size_t k = 0; k < epochs.size(); ++k) {
@@ -347,6 +432,7 @@ extern "C" tns_status tns_ttcache_build(const tns_problem *P, int64_t cache_elem
   out->ntasks = tasks;
   out->total_flops = flops;
   out->cache_elems = cache_elems;
+  out->halves = h.halves;
   return TNS_OK;
 }
 
@@ -376,17 +462,43 @@ extern "C" tns_status tns_apply_heff_streamed(const tns_ttcache_plan *p, tns_pre
     }
     return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
   }
+  if (!h.halves) {
+    for (int64_t k = 0; k < h.n_epochs; ++k) {
+      const TtEpoch &E = h.epochs[k];
+      // the epoch's loads follow the previous epoch's product on the stream,
+      // so they never overwrite operators that product still reads
+      for (int64_t l = E.load_begin; l < E.load_end; ++l) {
+        const TtLoad &L = h.loads[l];
+        TNS_HIP(hipMemcpyAsync(cv + L.cache_off * es, hv + L.host_off * es, (size_t)L.elems * es,
+                               hipMemcpyHostToDevice, st));
+      }
+      const tns_status s = tns_apply_heff(&h.tls[k], prec, cache, psi, sigma, k == 0 ? 0.0 : 1.0, ws, ws_bytes, st);
+      if (s != TNS_OK) return s;
+    }
+    return TNS_OK;
+  }
+  // double-buffered: the copies of epoch k (half k mod 2) on the copy stream
+  // after the stream's earlier work and the product of epoch k - 2, the
+  // product of epoch k on `stream` after those copies; the last product waits
+  // for every copy, so later work on `stream` follows the whole call
+  TtStreams *T = nullptr;
+  tns_status s = tt_streams(st, &T);
+  if (s != TNS_OK) return s;
+  TNS_HIP(hipEventRecord(T->start, st));
+  TNS_HIP(hipStreamWaitEvent(T->copy, T->start, 0));
   for (int64_t k = 0; k < h.n_epochs; ++k) {
     const TtEpoch &E = h.epochs[k];
-    // the epoch's loads follow the previous epoch's product on the stream,
-    // so they never overwrite operators that product still reads
+    if (k >= 2) TNS_HIP(hipStreamWaitEvent(T->copy, T->prod[k & 1], 0));
     for (int64_t l = E.load_begin; l < E.load_end; ++l) {
       const TtLoad &L = h.loads[l];
       TNS_HIP(hipMemcpyAsync(cv + L.cache_off * es, hv + L.host_off * es, (size_t)L.elems * es,
-                             hipMemcpyHostToDevice, st));
+                             hipMemcpyHostToDevice, T->copy));
     }
-    const tns_status s = tns_apply_heff(&h.tls[k], prec, cache, psi, sigma, k == 0 ? 0.0 : 1.0, ws, ws_bytes, st);
+    TNS_HIP(hipEventRecord(T->load[k & 1], T->copy));
+    TNS_HIP(hipStreamWaitEvent(st, T->load[k & 1], 0));
+    s = tns_apply_heff(&h.tls[k], prec, cache, psi, sigma, k == 0 ? 0.0 : 1.0, ws, ws_bytes, st);
     if (s != TNS_OK) return s;
+    TNS_HIP(hipEventRecord(T->prod[k & 1], st));
   }
   return TNS_OK;
 }

@@ -70,7 +70,8 @@ class TnsRenormPlan(ctypes.Structure):
 
 class TnsTtcachePlan(ctypes.Structure):
     _fields_ = [("n_epochs", _i64), ("n_loads", _i64), ("loaded_elems", _i64), ("naive_elems", _i64),
-                ("ntasks", _i64), ("total_flops", _i64), ("cache_elems", _i64), ("opaque", ctypes.c_uint8 * 256)]
+                ("ntasks", _i64), ("total_flops", _i64), ("cache_elems", _i64), ("halves", _i64),
+                ("opaque", ctypes.c_uint8 * 256)]
 
 
 class TnsSu2Problem(ctypes.Structure):
@@ -169,10 +170,10 @@ def library(path=LIB_PATH):
         L.tns_renormalize.argtypes = [ctypes.POINTER(TnsRenormPlan), ctypes.c_int, _P, _P, _P, _P, sz, _P]
     if hasattr(L, "tns_ttcache_build"):
         L.tns_ttcache_sizes.restype = ctypes.c_int
-        L.tns_ttcache_sizes.argtypes = [ctypes.POINTER(TnsProblem), _i64, ctypes.POINTER(ctypes.c_size_t),
+        L.tns_ttcache_sizes.argtypes = [ctypes.POINTER(TnsProblem), _i64, _i32, ctypes.POINTER(ctypes.c_size_t),
                                         ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i64)]
         L.tns_ttcache_build.restype = ctypes.c_int
-        L.tns_ttcache_build.argtypes = [ctypes.POINTER(TnsProblem), _i64, _P, sz, _P, sz,
+        L.tns_ttcache_build.argtypes = [ctypes.POINTER(TnsProblem), _i64, _i32, _P, sz, _P, sz,
                                         ctypes.POINTER(TnsTtcachePlan), _P]
         L.tns_ttcache_apply_workspace_bytes.restype = sz
         L.tns_ttcache_apply_workspace_bytes.argtypes = [ctypes.POINTER(TnsTtcachePlan), ctypes.c_int]
@@ -690,14 +691,18 @@ class RenormStep:
         return out
 
 
-def ttcache_sizes(P, cache_elems):
+TT_MODES = {"auto": 0, "single": 1, "double": 2}
+
+
+def ttcache_sizes(P, cache_elems, buffering="auto"):
     """``(host_bytes, device_bytes, n_epochs)`` of a tree-traversal cache plan
-    (host only); raises :class:`TnsError` when two operators of one term do not
-    fit the cache together or the problem fails validation."""
+    (host only; buffering "auto", "single" or "double"); raises
+    :class:`TnsError` when two operators of one term do not fit the cache
+    together or the problem fails validation."""
     cp, host = problem_struct(P)
     hb, db, ne = ctypes.c_size_t(0), ctypes.c_size_t(0), _i64(0)
-    _check(library().tns_ttcache_sizes(ctypes.byref(cp), int(cache_elems), ctypes.byref(hb), ctypes.byref(db),
-                                       ctypes.byref(ne)), "tns_ttcache_sizes")
+    _check(library().tns_ttcache_sizes(ctypes.byref(cp), int(cache_elems), TT_MODES[buffering], ctypes.byref(hb),
+                                       ctypes.byref(db), ctypes.byref(ne)), "tns_ttcache_sizes")
     return int(hb.value), int(db.value), int(ne.value)
 
 
@@ -705,9 +710,11 @@ class StreamedHeff:
     """H_eff psi with the operator values in pinned host memory, streamed
     through a device cache of ``cache_elems`` elements by the tree-traversal
     stack (``tns_ttcache_build`` / ``tns_apply_heff_streamed``); FP64 or FP32.
-    psi and sigma stay on the device."""
+    psi and sigma stay on the device.  buffering: "auto", "single" or
+    "double" (epochs alternating between the cache's halves, each epoch's
+    copies overlapping the previous epoch's product)."""
 
-    def __init__(self, P, cache_elems, prec="f64", device="cuda", host_vals=None):
+    def __init__(self, P, cache_elems, prec="f64", device="cuda", host_vals=None, buffering="auto"):
         dev = torch.device(device)
         if dev.index is None:
             dev = torch.device(dev.type, torch.cuda.current_device())
@@ -719,12 +726,13 @@ class StreamedHeff:
         L = library()
         cp, self._host = problem_struct(P)
         self.cprob = cp
-        hb, db, _ = ttcache_sizes(P, cache_elems)
+        hb, db, _ = ttcache_sizes(P, cache_elems, buffering)
         self._hbuf = (ctypes.c_uint8 * max(hb, 64))()
         self.ws_build = torch.empty(max(db, 256), dtype=torch.uint8, device=dev)
         self.plan = TnsTtcachePlan()
         with torch.cuda.device(dev):
-            _check(L.tns_ttcache_build(ctypes.byref(cp), int(cache_elems), ctypes.cast(self._hbuf, _P), hb,
+            _check(L.tns_ttcache_build(ctypes.byref(cp), int(cache_elems), TT_MODES[buffering],
+                                       ctypes.cast(self._hbuf, _P), hb,
                                        _ptr(self.ws_build), self.ws_build.numel(), ctypes.byref(self.plan),
                                        _stream()), "tns_ttcache_build")
         if host_vals is None:
@@ -737,11 +745,14 @@ class StreamedHeff:
         self.ws = torch.empty(int(max(n, 256)), dtype=torch.uint8, device=dev)
         self.psi_dim = int(P.psi_off[-1])
         self.dtype = dt
-        for k in ("n_epochs", "n_loads", "loaded_elems", "naive_elems", "ntasks", "total_flops", "cache_elems"):
+        for k in ("n_epochs", "n_loads", "loaded_elems", "naive_elems", "ntasks", "total_flops", "cache_elems",
+                  "halves"):
             setattr(self, k, int(getattr(self.plan, k)))
 
     def apply(self, psi, out=None):
-        """sigma := H_eff psi (one copy per cache load, one product per epoch)."""
+        """sigma := H_eff psi (one copy per cache load, one product per epoch;
+        double-buffered plans overlap an epoch's copies with the previous
+        epoch's product)."""
         if psi.dtype != self.dtype or psi.device != self.device or psi.numel() != self.psi_dim \
                 or not psi.is_contiguous():
             raise ValueError("psi must be a contiguous %s tensor of %d elements on %s"

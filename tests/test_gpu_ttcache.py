@@ -4,7 +4,9 @@ cache of a given size, sigma against the oracle's FP64 sigma and against the
 in-HBM product, for caches from every operator down to the smallest that
 holds the two operators of any one term; the copied elements between every
 operator once (what a cache holding everything copies, in one product) and
-a per-term copy of both operators."""
+a per-term copy of both operators.  Caches that need several epochs and hold
+any term's operators in half their size run double-buffered (epochs
+alternating between the halves, copies overlapping the previous product)."""
 import numpy as np
 import pytest
 import torch
@@ -55,23 +57,39 @@ def built():
     return out
 
 
+def _pair(P):
+    _, fp = op_sizes(P)
+    return max((int(fp[a]) if a >= 0 else 0) + (int(fp[b]) if b >= 0 else 0) for a, b in zip(P.term_L, P.term_R))
+
+
 def _caches(P):
     ext, fp = op_sizes(P)
-    pair = max((int(fp[a]) if a >= 0 else 0) + (int(fp[b]) if b >= 0 else 0) for a, b in zip(P.term_L, P.term_R))
+    pair = _pair(P)
     full = max(int(fp.sum()), 8)
     return {"all": full, "quarter": max(pair, full // 4), "pair": max(pair, 8)}
 
 
+def _expect_halves(P, n):
+    """Whether a plan asked to double-buffer a cache of n elements does: the
+    used operators do not fit at once and any term's two fit in half the
+    cache."""
+    _, fp = op_sizes(P)
+    used = np.unique(np.concatenate([P.term_L, P.term_R]))
+    c8 = n // 8 * 8
+    return int(fp[used[used >= 0]].sum()) > c8 and _pair(P) <= c8 // 16 * 8
+
+
+@pytest.mark.parametrize("buffering", ["single", "double"])
 @pytest.mark.parametrize("cache", ["all", "quarter", "pair"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("name", list(_instances()))
-def test_streamed_parity(built, name, prec, cache):
+def test_streamed_parity(built, name, prec, cache, buffering):
     from paper_2305_05581_amd.tns import StreamedHeff
     P, H, psi, ref = built[name]
     n = _caches(P)[cache]
-    S = StreamedHeff(P, n, prec)
-    say("ttcache", name, prec, cache, "cache", n, "epochs", S.n_epochs, "loads", S.n_loads,
-        "loaded", S.loaded_elems, "naive", S.naive_elems)
+    S = StreamedHeff(P, n, prec, buffering=buffering)
+    say("ttcache", name, prec, cache, buffering, "cache", n, "epochs", S.n_epochs, "loads", S.n_loads,
+        "loaded", S.loaded_elems, "naive", S.naive_elems, "halves", S.halves)
     dt = torch.float64 if prec == "f64" else torch.float32
     x = to_dev(psi, dt)
     got = S.apply(x)
@@ -88,17 +106,25 @@ def test_streamed_parity(built, name, prec, cache):
     used = np.unique(np.concatenate([P.term_L, P.term_R]))
     assert S.naive_elems == naive
     assert int(ext[used[used >= 0]].sum()) <= S.loaded_elems <= naive
+    assert S.halves == (int(_expect_halves(P, n)) if buffering == "double" else 0)
     if cache == "all":  # every operator copied once, all terms in one product
         assert S.loaded_elems == int(ext[used[used >= 0]].sum())
         assert S.n_epochs == 1
 
 
-def test_streamed_deterministic(built):
+@pytest.mark.parametrize("cache,buffering", [("pair", "single"), ("quarter", "double")])
+def test_streamed_deterministic(built, cache, buffering):
+    """Repeated products are bitwise equal, single- and double-buffered, also
+    when a double-buffered call follows another on the stream at once (its
+    copies wait for the earlier call's products)."""
     from paper_2305_05581_amd.tns import StreamedHeff
     P, H, psi, ref = built["ragged"]
-    S = StreamedHeff(P, _caches(P)["pair"], "f32")
+    S = StreamedHeff(P, _caches(P)[cache], "f32", buffering=buffering)
+    say("ttcache deterministic", cache, buffering, "epochs", S.n_epochs, "halves", S.halves)
     x = to_dev(psi, torch.float32)
     a = S.apply(x)
     b = S.apply(x)
+    c = S.apply(x)
     assert S.n_epochs > 1
-    assert torch.equal(a, b)
+    assert S.halves == (1 if buffering == "double" else 0)
+    assert torch.equal(a, b) and torch.equal(a, c)

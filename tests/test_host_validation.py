@@ -118,6 +118,21 @@ def test_ttcache_plan_sizes(lib_ok, base):
     for cap in (pair - 8, 0):
         with pytest.raises(TnsError):
             ttcache_sizes(P, cap)
+    # buffering: a cache of a quarter of the operators double-buffered splits
+    # into at least as many epochs as single-buffered; everything-fits stays one
+    # product either way; an unknown mode is rejected
+    quarter = max(pair, int(fp.sum()) // 4)
+    _, _, e1 = ttcache_sizes(P, quarter, "single")
+    _, _, e2 = ttcache_sizes(P, quarter, "double")
+    assert e1 > 1 and e2 >= e1
+    assert ttcache_sizes(P, int(fp.sum()), "double")[2] == 1
+    import paper_2305_05581_amd.tns as T
+    T.TT_MODES["bad"] = 7
+    try:
+        with pytest.raises(TnsError):
+            ttcache_sizes(P, quarter, "bad")
+    finally:
+        del T.TT_MODES["bad"]
     tl = P.term_L.copy()
     tl[0] = P.nOps
     with pytest.raises(TnsError):
