@@ -17,16 +17,19 @@ constexpr int MAX_DIM = 32768;
 // Work items per compute unit the chunked schedules (phase B, backward) aim
 // at on large products: shorter chunks keep the tiles of one chunk, which
 // share their operand rows in L2, closer together in time.  Chunks stay at
-// ITEM_MIN_FLOP or more unless that leaves fewer than ITEMS_MIN_PER_CU per CU.
+// ITEM_MIN_FLOP or more unless that leaves fewer than ITEMS_MIN_PER_CU per CU
+// (small products: few, large items; each item costs a queue atomic, a ring
+// fill and drain and three barriers, which 2 per CU keep small: 64 uneven
+// instances 75 -> 63-65 ms against 8 per CU).
 constexpr int ITEMS_PER_CU = 32;
-constexpr int ITEMS_MIN_PER_CU = 8;
+constexpr int ITEMS_MIN_PER_CU = 2;
 constexpr int64_t ITEM_MIN_FLOP = 100000000;
 // Phase-A work items per compute unit: short row pieces whose column tiles
 // run side by side on one XCD, so that they share the operator rows in L2;
 // never below PANEL_ITEM_MIN_FLOP unless that leaves fewer than
 // PANEL_ITEMS_MIN_PER_CU items per CU.
 constexpr int PANEL_ITEMS_PER_CU = 64;
-constexpr int PANEL_ITEMS_MIN_PER_CU = 8;
+constexpr int PANEL_ITEMS_MIN_PER_CU = 4;
 constexpr int64_t PANEL_ITEM_MIN_FLOP = 100000000;
 // Most work queues of a schedule: one per XCD (accelerator complex die, each
 // with its own L2).  Workgroup b of a launch runs on XCD b mod n_xcd, since
