@@ -444,8 +444,10 @@ __global__ __launch_bounds__(NWG) void k_apply(ApplyArgs a) {
 template <class T>
 __global__ void k_epilogue_psi(const int64_t *__restrict__ psi_off, int nS, int gps,
                                const int64_t *__restrict__ grp_chunk_base, const int64_t *__restrict__ slot_off,
-                               const T *__restrict__ part, T *__restrict__ out, int64_t psi_dim, int beta) {
-  GRID_STRIDE(e, psi_dim) {
+                               const T *__restrict__ part, T *__restrict__ out, int64_t psi_dim, int beta,
+                               int64_t e0) {
+  for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < psi_dim;
+       e += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = nS;  // s with psi_off[s] <= e < psi_off[s+1]
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -561,12 +563,14 @@ bool take_profile_events(hipEvent_t ev[3]) {
 
 tns_status launch_epilogue_psi(const Plan &p, bool f64, const void *part, void *sigma, int beta, hipStream_t st) {
   const Sched &S = p.fwd;
+  if (p.psi_dim <= p.epi_e0) return TNS_OK;
+  const unsigned g = nb(p.psi_dim - p.epi_e0, 256);
   if (f64)
-    hipLaunchKernelGGL(k_epilogue_psi<double>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 2,
-                       S.grp_chunk_base, S.slot_off, (const double *)part, (double *)sigma, p.psi_dim, beta);
+    hipLaunchKernelGGL(k_epilogue_psi<double>, dim3(g), dim3(256), 0, st, p.psi_off, p.nS, 2, S.grp_chunk_base,
+                       S.slot_off, (const double *)part, (double *)sigma, p.psi_dim, beta, p.epi_e0);
   else
-    hipLaunchKernelGGL(k_epilogue_psi<float>, dim3(nb(p.psi_dim, 256)), dim3(256), 0, st, p.psi_off, p.nS, 2,
-                       S.grp_chunk_base, S.slot_off, (const float *)part, (float *)sigma, p.psi_dim, beta);
+    hipLaunchKernelGGL(k_epilogue_psi<float>, dim3(g), dim3(256), 0, st, p.psi_off, p.nS, 2, S.grp_chunk_base,
+                       S.slot_off, (const float *)part, (float *)sigma, p.psi_dim, beta, p.epi_e0);
   return hipGetLastError() == hipSuccess ? TNS_OK : TNS_ERR_HIP;
 }
 

@@ -1225,8 +1225,8 @@ static tns_status fwd_launch(const Plan &p, const void *ops, const In *psi, void
   const Sched &S = p.fwd;
   const FwdArgs g = fwd_args<P>(p, ops, w);
   hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(32), 0, st, g.queue);
-  if (p.nS > 0)
-    hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.nS, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
+  if (p.pad_ns > 0)
+    hipLaunchKernelGGL((k_pad_psi<In, P>), dim3(p.pad_ns, 8), dim3(256), 0, st, psi, p.psi_off, p.psi_sec, p.dimL,
                        p.dimR, p.pp_off, p.pt_off, const_cast<void *>(g.pp), const_cast<void *>(g.pt));
   if (p.ntasks > 0) {
     hipLaunchKernelGGL(k_chunk_recs, dim3(nblocks(p.ntasks)), dim3(256), 0, st, g);

@@ -465,6 +465,11 @@ extern "C" tns_status tns_renorm_build(const tns_renorm_problem *R, void *ws, si
   s = build_plan(&P, (int32_t)h.dim.size(), h.maxdim, h.tasks.data(), h.ptr.data(), (int64_t)h.tasks.size(), false,
                  ws, pb, &out->tl, st);
   if (s != TNS_OK) return s;
+  // the tasks read only the input sectors and write only the output ones:
+  // pad the former, sum the partial slots of the latter
+  Plan &gp = plan_of(&out->tl);
+  gp.pad_ns = h.n_in;
+  gp.epi_e0 = h.psi_off[h.n_in];
   RnPlan &rp = rn_of(out);
   rp.n_in = h.n_in; rp.n_out = h.n_out; rp.n_g = (int32_t)h.g_rows.size(); rp.nQ = R->nQ;
   rp.out_elems = h.out_elems; rp.u_need = h.u_need; rp.in0 = 0;

@@ -927,6 +927,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   memset(&p, 0, sizeof(p));
   p.nL = P->nL; p.nR = P->nR; p.nS = P->nS; p.nOps = P->nOps; p.nBlk = P->nBlk; p.nTerms = P->nTerms;
   p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals; p.maxdim = maxdim; p.tiles = TILES_DEFAULT;
+  p.pad_ns = P->nS; p.epi_e0 = 0;
   p.psi_dim = P->psi_off[P->nS];
   const int64_t ntcap = std::max<int64_t>(1, ntasks_explicit >= 0 ? ntasks_explicit : (int64_t)P->nTerms * P->nS);
   p.qL = cv.take<int32_t>(2 * P->nL); p.dimL = cv.take<int32_t>(P->nL);

@@ -248,7 +248,13 @@ struct Plan {
   int32_t nL, nR, nS, nOps, nBlk, nTerms, nmax, n_cu;
   int32_t maxdim;        // largest sector dimension
   uint32_t tiles;        // forward tile table
-  int32_t no_backward, pad0_;  // 1: built without the backward's schedules
+  int32_t no_backward;   // 1: built without the backward's schedules
+  // sectors [0, pad_ns) are padded for phase A (the task inputs), sigma is
+  // written from element epi_e0 on (the task outputs): all of them for a
+  // product; the input blocks and the output blocks of a generic problem
+  // whose inputs and outputs are disjoint sector ranges (renormalisation)
+  int32_t pad_ns;
+  int64_t epi_e0;
   int64_t n_vals, psi_dim, ntasks;
   // copied tables
   int32_t *qL, *dimL, *qR, *dimR, *psi_sec;
