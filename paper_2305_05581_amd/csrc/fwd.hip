@@ -381,26 +381,27 @@ __device__ __attribute__((always_inline)) inline void frag_mma(const Frag<P, KS>
   }
 }
 
-// One stage of MFMA for a (32 TM) x (32 TN) tile; wave (wm, wn) owns rows
-// wm 16 TM + 16 i and columns wn 16 TN + 16 j.  SWAP: acc[i][j] holds the
-// transposed tile (rows = B rows wn 16 TN + 16 i, columns = A rows wm 16 TM + 16 j).
+// One stage of MFMA for a tile of WM x WN wave tiles (WN waves across the
+// columns, default wgn): wave (wm, wn) owns rows wm 16 TM + 16 i and columns
+// wn 16 TN + 16 j.  SWAP: acc[i][j] holds the transposed tile (rows = B rows
+// wn 16 TN + 16 i, columns = A rows wm 16 TM + 16 j).
 // The operand fragments of one stage for this wave's tile.
-template <int P, int KS, int TM, int TN> struct Frags {
+template <int P, int KS, int TM, int TN, int WN = wgn<P>()> struct Frags {
   Frag<P, KS> a[TM], b[TN];
 };
 
-template <int P, int KS, int TM, int TN>
-__device__ __attribute__((always_inline)) inline void ring_read(const Stage<P, KS> &st, Frags<P, KS, TM, TN> &f) {
+template <int P, int KS, int TM, int TN, int WN>
+__device__ __attribute__((always_inline)) inline void ring_read(const Stage<P, KS> &st, Frags<P, KS, TM, TN, WN> &f) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w / wgn<P>(), wn = w % wgn<P>(), l16 = lane & 15, g = lane >> 4;
+  const int wm = w / WN, wn = w % WN, l16 = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int i = 0; i < TM; ++i) f.a[i] = ring_frag<P, KS>(st, 0, wm * 16 * TM + 16 * i, l16, g);
 #pragma unroll
   for (int j = 0; j < TN; ++j) f.b[j] = ring_frag<P, KS>(st, 1, wn * 16 * TN + 16 * j, l16, g);
 }
 
-template <int P, int KS, int TM, int TN, bool SWAP, int AM, int AN>
-__device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS, TM, TN> &f,
+template <int P, int KS, int TM, int TN, bool SWAP, int WN, int AM, int AN>
+__device__ __attribute__((always_inline)) inline void ring_mma(const Frags<P, KS, TM, TN, WN> &f,
                                                                typename FP<P>::A4 (&acc)[AM][AN]) {
   if (SWAP) {
 #pragma unroll
@@ -526,14 +527,15 @@ __device__ __attribute__((always_inline)) inline void ring_run(Ring<P, KS, NS> &
 // TM, TN: 16-row / 16-column MFMA tiles per wave (a workgroup tile of
 // 32 TM rows x 16 TN wgn columns); ncols: the item's columns (the rest of the
 // tile reads zeros and stores nothing).
-template <int P, int KS, int TM, int TN>
+template <int P, int KS, int TM, int TN, int WN = wgn<P>()>
 __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
                                                                     const Item &it, int mode, int ncols) {
   typedef typename FP<P>::A4 A4;
   constexpr int BK = RingL<P, KS>::BK;
-  constexpr int NL = P == TNS_BF16X3 ? 2 + TN : RingL<P, KS>::LOADS;
+  constexpr int NB = (WN * TN + 3) / 4;  // BF16X3 chunks of B rows per wave
+  constexpr int NL = P == TNS_BF16X3 ? 2 + NB : RingL<P, KS>::LOADS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w / wgn<P>(), wn = w % wgn<P>(), l16 = lane & 15, lg = lane >> 4;
+  const int wm = w / WN, wn = w % WN, l16 = lane & 15, lg = lane >> 4;
   const int cend = it.c0 + ncols;
   // FP32: the MFMA accumulators take NS steps at a time and are then added
   // into a second set (two-level summation), so that the rounding error over
@@ -600,8 +602,8 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
     LA.ld = ld8(r.K); LA.rows = r.arows;
     LB.p = elem_ptr<P>(g.ops, r.b_off);
     LB.ld = r.bld; LB.rows = r.brows;
-    ls_mat<P, TN>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 32 * TM), lK);
-    ls_mat<P, TN>(LS, 2, LB, it.c0, min(LB.rows, cend), lK);
+    ls_mat<P, NB>(LS, 0, LA, it.p0, min(LA.rows, it.p0 + 16 * TM * (gth<P>() / 64 / WN)), lK);
+    ls_mat<P, NB>(LS, 2, LB, it.c0, min(LB.rows, cend), lK);
   };
   SegRec nxt;
   if (!ldone) {
@@ -613,12 +615,12 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
   } else {  // no products: the ring runs on the zero region only
     Mat Z;
     Z.p = g.zero; Z.ld = 0; Z.rows = 0;
-    ls_mat<P, TN>(LS, 0, Z, 0, 0, 0);
-    ls_mat<P, TN>(LS, 2, Z, 0, 0, 0);
+    ls_mat<P, NB>(LS, 0, Z, 0, 0, 0);
+    ls_mat<P, NB>(LS, 2, Z, 0, 0, 0);
   }
-  typedef Frags<P, KS, TM, TN> FR;
+  typedef Frags<P, KS, TM, TN, WN> FR;
   ring_run<P, KS, Geo<P, 1>::NS, Geo<P, 1>::PF, FR, NL>(
-      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS, TN>(st, LS, lj * BK, !ldone, g.zero); },
+      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS, NB>(st, LS, lj * BK, !ldone, g.zero); },
       [&]() -> int {
         if (ldone) return 0;
         if (++lj * BK >= lK) {
@@ -666,8 +668,9 @@ __device__ __attribute__((always_inline)) inline void ring_item_b_t(const FwdArg
 }
 
 // Item dispatch: BF16X3 covers up to 256 columns per tile (16 TN per wave
-// over 4 waves, TN = ceil(tn / 2)); FP32 / FP64 up to 128 (16 TN per wave over
-// 2 waves), which their item lists never exceed.
+// over 4 waves, TN = ceil(tn / 2); 1 or 3 column tiles over 64 or 128 rows on
+// 4 x 2 waves instead, 16 tn columns each); FP32 / FP64 up to 128 (16 TN per
+// wave over 2 waves), which their item lists never exceed.
 template <int P, int KS>
 __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs &g, Ring<P, KS, Geo<P, 1>::NS> &rg,
                                                                   int wk) {
@@ -675,6 +678,19 @@ __device__ __attribute__((always_inline)) inline void ring_item_b(const FwdArgs 
   const int mode = it.mode & 0xff, tm = (it.mode >> 8) & 0xff, tn = (it.mode >> 16) & 0xff;
   const int cw = P == TNS_BF16X3 ? (tn + 1) >> 1 : (tn < 4 ? tn : 4);
   const int ncols = P == TNS_BF16X3 ? 32 * tn : 32 * cw;
+  if constexpr (P == TNS_BF16X3) {
+    // 32 or 96 columns over 64 or 128 rows: 4 x 2 waves (no padding columns)
+    if ((tn == 1 || tn == 3) && (tm == 2 || tm == 4)) {
+      if (tm == 2) {
+        if (tn == 1) ring_item_b_t<P, KS, 1, 1, 2>(g, rg, it, mode, ncols);
+        else ring_item_b_t<P, KS, 1, 3, 2>(g, rg, it, mode, ncols);
+      } else {
+        if (tn == 1) ring_item_b_t<P, KS, 2, 1, 2>(g, rg, it, mode, ncols);
+        else ring_item_b_t<P, KS, 2, 3, 2>(g, rg, it, mode, ncols);
+      }
+      return;
+    }
+  }
 #define TNS_CALL_B(a, b) ring_item_b_t<P, KS, a, b>(g, rg, it, mode, ncols)
   TNS_TILE_SWITCH(tm, cw, TNS_CALL_B)
 #undef TNS_CALL_B
@@ -717,7 +733,7 @@ __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g
 
 // Epilogue of a stacked T tile starting at chunk ch (swapped accumulator:
 // acc[i][j] rows = T columns c0 + wn 16 TN + 16 i + .., columns = the rows of
-// chunk ch + 4 wm + j).  Row r of chunk c lies at tbase + (16 c + r) ldT;
+// chunk ch + TM wm + j; WN waves across the columns).  Row r of chunk c lies at tbase + (16 c + r) ldT;
 // rows beyond the chunk's task and columns at or beyond cend are not stored.
 // FP32 writes 4 consecutive columns per lane as one vector.  BF16X3: the
 // lanes l and l ^ 16 hold the two halves of one 8-column group (row starts
@@ -725,16 +741,16 @@ __device__ __attribute__((always_inline)) inline void ls_chunks(const FwdArgs &g
 // so that the even lane writes the group's 8 high halves and the odd one its
 // 8 low halves, each as one 16-byte store: a row's 16 columns are 64
 // contiguous bytes from 4 lanes.
-template <int P, int TN>
-__device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[TN][4],
+template <int P, int TN, int TM, int WN>
+__device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdArgs &g, typename FP<P>::A4 (&acc)[TN][TM],
                                                                      int ch, int ch_end, int64_t tbase, int c0,
                                                                      int cend, int ldT) {
   typedef typename FP<P>::A4 A4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = w / wgn<P>(), wn = w % wgn<P>(), l16 = lane & 15, lg = lane >> 4;
+  const int wm = w / WN, wn = w % WN, l16 = lane & 15, lg = lane >> 4;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = __builtin_amdgcn_readfirstlane(ch + 4 * wm + j);
+  for (int j = 0; j < TM; ++j) {
+    const int c = __builtin_amdgcn_readfirstlane(ch + TM * wm + j);
     if (c < ch_end) {
       const ChunkRec *r = g.recs + c;
       const int vr = cld(&r->vrows);
@@ -789,12 +805,16 @@ __device__ __attribute__((always_inline)) inline void ring_store_stk(const FwdAr
   }
 }
 
-template <int P, int KS, int TN>
+// WN waves across the columns (the rest across the 128 rows, TM MFMA row
+// tiles each); BF16X3 loads NB chunks of B rows per wave.
+template <int P, int KS, int TN, int WN = wgn<P>()>
 __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
                                                                     const Item &it, int ncols) {
   typedef typename FP<P>::A4 A4;
   constexpr int BK = RingL<P, KS>::BK;
-  constexpr int NL = P == TNS_BF16X3 ? 2 + TN : RingL<P, KS>::LOADS;
+  constexpr int TM = 8 * WN * 64 / gth<P>();
+  constexpr int NB = (WN * TN + 3) / 4;
+  constexpr int NL = P == TNS_BF16X3 ? 2 + NB : RingL<P, KS>::LOADS;
   const int cend = it.c0 + ncols;
   const int G = it.grp, sec = G >> 1, cls = G & 1;
   const int m = cld(&g.dimL[cld(&g.psi_sec[4 * sec])]), n = cld(&g.dimR[cld(&g.psi_sec[4 * sec + 3])]);
@@ -814,15 +834,17 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
   bool ldone = false;
   LoadSetT<P> LS;
   ls_chunks<P>(g, LS, lch, ch_end, K);
-  ls_mat<P, TN>(LS, 2, B, it.c0, min(B.rows, cend), K);
-  A4 acc[TN][4];
+  ls_mat<P, NB>(LS, 2, B, it.c0, min(B.rows, cend), K);
+  A4 acc[TN][TM];
 #pragma unroll
   for (int i = 0; i < TN; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = vzero<A4>();
-  typedef Frags<P, KS, 4, TN> FR;
-  ring_run<P, KS, Geo<P, 0>::NS, Geo<P, 0>::PF, FR, NL>(
-      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS, TN>(st, LS, lk0, !ldone, g.zero); },
+    for (int j = 0; j < TM; ++j) acc[i][j] = vzero<A4>();
+  typedef Frags<P, KS, TM, TN, WN> FR;
+  // the prefetch's second fragment set of the widest 4 x 2 tiles would spill
+  constexpr bool PF = Geo<P, 0>::PF && !(WN == 2 && TN >= 5);
+  ring_run<P, KS, Geo<P, 0>::NS, PF, FR, NL>(
+      rg, [&](Stage<P, KS> &st) { ring_issue<P, KS, NB>(st, LS, lk0, !ldone, g.zero); },
       [&]() -> int {
         if (ldone) return 0;
         if ((lk0 += BK) < K) return 1;
@@ -831,29 +853,43 @@ __device__ __attribute__((always_inline)) inline void ring_item_a_t(const FwdArg
         else ldone = true;
         return 1;
       },
-      [&](const FR &f, auto) { ring_mma<P, KS, 4, TN, true>(f, acc); },
+      [&](const FR &f, auto) { ring_mma<P, KS, TM, TN, true>(f, acc); },
       [&]() {
         if ((ck0 += BK) < K) return;
         ck0 = 0;
-        ring_store_stk<P, TN>(g, acc, cch, ch_end, tbase, it.c0, cend, ldT);
+        ring_store_stk<P, TN, TM, WN>(g, acc, cch, ch_end, tbase, it.c0, cend, ldT);
         cch += PTILE_CH;
       });
 }
 
-// Item dispatch as in phase B: BF16X3 up to 256 columns per tile, FP32 /
-// FP64 up to 128.
+// Item dispatch: FP32 / FP64 up to 128 columns per tile (2 x 2 waves).
+// BF16X3 up to 256: an even number tn of 32-column tiles runs on 2 x 4 waves
+// of 16 tn / 2 columns each, an odd one on 4 x 2 waves of 16 tn columns each
+// (both without padding columns).
 template <int P, int KS>
 __device__ __attribute__((always_inline)) inline void ring_item_a(const FwdArgs &g, Ring<P, KS, Geo<P, 0>::NS> &rg,
                                                                   int wk) {
   const Item it = load_item(g.a_items + wk);
   const int tn = (it.mode >> 16) & 0xff;
-  const int cw = P == TNS_BF16X3 ? (tn + 1) >> 1 : (tn < 4 ? tn : 4);
-  const int ncols = P == TNS_BF16X3 ? 32 * tn : 32 * cw;
-  switch (cw) {
-    case 1: ring_item_a_t<P, KS, 1>(g, rg, it, ncols); break;
-    case 2: ring_item_a_t<P, KS, 2>(g, rg, it, ncols); break;
-    case 3: ring_item_a_t<P, KS, 3>(g, rg, it, ncols); break;
-    default: ring_item_a_t<P, KS, 4>(g, rg, it, ncols); break;
+  if constexpr (P == TNS_BF16X3) {
+    const int ncols = 32 * tn;
+    switch (tn) {
+      case 1: ring_item_a_t<P, KS, 1, 2>(g, rg, it, ncols); break;
+      case 2: ring_item_a_t<P, KS, 1, 4>(g, rg, it, ncols); break;
+      case 3: ring_item_a_t<P, KS, 3, 2>(g, rg, it, ncols); break;
+      case 4: ring_item_a_t<P, KS, 2, 4>(g, rg, it, ncols); break;
+      case 5: case 6: ring_item_a_t<P, KS, 3, 4>(g, rg, it, ncols); break;
+      default: ring_item_a_t<P, KS, 4, 4>(g, rg, it, ncols); break;
+    }
+  } else {
+    const int cw = tn < 4 ? tn : 4;
+    const int ncols = 32 * cw;
+    switch (cw) {
+      case 1: ring_item_a_t<P, KS, 1>(g, rg, it, ncols); break;
+      case 2: ring_item_a_t<P, KS, 2>(g, rg, it, ncols); break;
+      case 3: ring_item_a_t<P, KS, 3>(g, rg, it, ncols); break;
+      default: ring_item_a_t<P, KS, 4>(g, rg, it, ncols); break;
+    }
   }
 }
 
