@@ -916,9 +916,62 @@ static void layout_panels(Carve &cv, Panels &A, int32_t ng, int64_t ntcap, int m
   A.scalars = cv.take<int64_t>(8);
 }
 
+// Number of tasks of a validated problem, counted on the host with the
+// enumeration rule of k_tasks (for an output sector and a term at most one
+// input sector: the left block ending in the sector's left block sector, the
+// site states the monomials map onto the sector's, the right block likewise,
+// and that input sector present), so that the task arrays are sized exactly.
+static int64_t host_task_count(const tns_problem *P, int32_t nmax) {
+  std::vector<int32_t> psi_index((size_t)P->nL * 16, -1);
+  for (int s = 0; s < P->nS; ++s) {
+    const int32_t *e = P->psi_sec + 4 * s;
+    psi_index[((size_t)e[0] * 4 + e[1]) * 4 + e[2]] = s;
+  }
+  std::vector<int32_t> bo((size_t)std::max(1, P->nOps) * nmax, -1);
+  for (int b = 0; b < P->nBlk; ++b) bo[(size_t)P->blk_op[b] * nmax + P->blk_out[b]] = b;
+  // site state reached from state s by monomial m (-1: none), per monomial
+  int8_t src[16][4];
+  for (int m = 0; m < 16; ++m)
+    for (int t = 0; t < 4; ++t) {
+      src[m][t] = -1;
+      for (int u = 0; u < 4; ++u) {
+        int v;
+        if (mono_apply(m, u, &v) == t) src[m][t] = (int8_t)u;
+      }
+    }
+  // terms whose two monomials reach the site states (ta, tb), per (ta, tb)
+  std::vector<int32_t> site_terms[16];
+  for (int k = 0; k < P->nTerms; ++k)
+    for (int t = 0; t < 16; ++t)
+      if (src[P->term_ma[k]][t >> 2] >= 0 && src[P->term_mb[k]][t & 3] >= 0) site_terms[t].push_back(k);
+  int64_t n = 0;
+  for (int so = 0; so < P->nS; ++so) {
+    const int jL = P->psi_sec[4 * so], ta = P->psi_sec[4 * so + 1], tb = P->psi_sec[4 * so + 2];
+    const int jR = P->psi_sec[4 * so + 3];
+    for (const int32_t k : site_terms[ta * 4 + tb]) {
+      const int oL = P->term_L[k], oR = P->term_R[k];
+      int iL = jL, iR = jR;
+      if (oL >= 0) {
+        const int lb = bo[(size_t)oL * nmax + jL];
+        if (lb < 0) continue;
+        iL = P->blk_in[lb];
+      }
+      if (oR >= 0) {
+        const int rb = bo[(size_t)oR * nmax + jR];
+        if (rb < 0) continue;
+        iR = P->blk_in[rb];
+      }
+      const int si = psi_index[((size_t)iL * 4 + src[P->term_ma[k]][ta]) * 4 + src[P->term_mb[k]][tb]];
+      if (si < 0 || P->psi_sec[4 * si + 3] != iR) continue;
+      ++n;
+    }
+  }
+  return n;
+}
+
 // Lays out (or, with base == nullptr, sizes) the build workspace.
-// ntasks_explicit >= 0: a task table given by the caller (that many tasks)
-// instead of one enumerated from the terms.
+// ntasks_explicit >= 0: the number of tasks (of a table given by the caller,
+// or the host count of the enumerated one); else counted here.
 // backward: also the backward's schedules and the adjoint plan.
 static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_cu, int n_xcd, char *base,
                      Plan *pl, int64_t ntasks_explicit = -1, bool backward = true) {
@@ -929,7 +982,7 @@ static size_t layout(const tns_problem *P, int32_t nmax, int32_t maxdim, int n_c
   p.nmax = nmax; p.n_cu = n_cu; p.n_vals = P->n_vals; p.maxdim = maxdim; p.tiles = TILES_DEFAULT;
   p.pad_ns = P->nS; p.epi_e0 = 0;
   p.psi_dim = P->psi_off[P->nS];
-  const int64_t ntcap = std::max<int64_t>(1, ntasks_explicit >= 0 ? ntasks_explicit : (int64_t)P->nTerms * P->nS);
+  const int64_t ntcap = std::max<int64_t>(1, ntasks_explicit >= 0 ? ntasks_explicit : host_task_count(P, nmax));
   p.qL = cv.take<int32_t>(2 * P->nL); p.dimL = cv.take<int32_t>(P->nL);
   p.qR = cv.take<int32_t>(2 * P->nR); p.dimR = cv.take<int32_t>(P->nR);
   p.psi_sec = cv.take<int32_t>(4 * (size_t)std::max(1, P->nS)); p.psi_off = cv.take<int64_t>(P->nS + 1);
@@ -1249,7 +1302,7 @@ tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const 
                       const int32_t *xptr, int64_t nx, bool backward, void *ws, size_t ws_bytes, tns_tasklist *out,
                       hipStream_t st) {
   const int n_cu = device_cu_count(), n_xcd = device_xcd_count();
-  const int64_t ntx = xtasks ? nx : -1;
+  const int64_t ntx = xtasks ? nx : host_task_count(P, nmax);
   const size_t need = layout(P, nmax, maxdim, n_cu, n_xcd, nullptr, nullptr, ntx, backward);
   if (need == 0) return TNS_ERR_SHAPE;  // schedule counts beyond 32-bit indices
   if (ws_bytes < need) return TNS_ERR_WORKSPACE;
@@ -1298,6 +1351,12 @@ tns_status build_plan(const tns_problem *P, int32_t nmax, int32_t maxdim, const 
     if (P->nS > 0) {
       hipLaunchKernelGGL(k_tasks<false>, dim3(wblk), dim3(256), 0, st, p);
       hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, p.scan_tmp, p.scan_tmp, (int64_t)P->nS);
+      // the task arrays are sized for the host's count of the same rule;
+      // the device's count must equal it before the fill writes them
+      int64_t total = 0;
+      TNS_HIP(hipMemcpyAsync(&total, p.scan_tmp + P->nS, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      TNS_HIP(hipStreamSynchronize(st));
+      if (total != ntx) return TNS_ERR_WORKSPACE;
     } else {
       hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(1), 0, st, p.scan_tmp, (int64_t)1, (int64_t)0);
     }
