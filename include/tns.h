@@ -137,7 +137,10 @@ typedef struct {
 
 /* Bytes of device workspace tns_build_tasklist needs for this problem (host
  * only, no device call except a query of the device's compute-unit count).
- * Returns 0 when the problem fails host validation. */
+ * The per-task arrays are sized for the exact task count, which the host
+ * counts with the device enumeration's rule (Eq. (2): a task per term and
+ * output sector whose operator blocks, site monomials and input sector all
+ * exist).  Returns 0 when the problem fails host validation. */
 size_t tns_tasklist_workspace_bytes(const tns_problem *prob);
 
 /* Levels 1-2 of Section III.A.1 on the device: validates the problem on the
@@ -149,7 +152,9 @@ size_t tns_tasklist_workspace_bytes(const tns_problem *prob);
  * and for its backward, including the adjoint task list (every task with its
  * sectors swapped and its blocks transposed, sorted by the new output sector)
  * that the backward's d psi runs as a forward product.  Synchronises the
- * stream four times to read counts.
+ * stream a few times to read counts back (the first checks the device's
+ * task count against the host count the workspace was sized for:
+ * TNS_ERR_WORKSPACE if they differ).
  * `ws` must stay untouched while `out` is in use. */
 tns_status tns_build_tasklist(const tns_problem *prob, void *ws, size_t ws_bytes,
                               tns_tasklist *out, hipStream_t stream);
