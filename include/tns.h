@@ -143,6 +143,14 @@ typedef struct {
  * exist).  Returns 0 when the problem fails host validation. */
 size_t tns_tasklist_workspace_bytes(const tns_problem *prob);
 
+/* Number of tasks of Eq. (2) the problem yields (Section III.A.1, level 2),
+ * counted on the host with the rule tns_build_tasklist enumerates by: one
+ * task per (term, output sector) whose left block, site monomials, right
+ * block and input sector all exist.  Host only, no device call; `ntasks` is
+ * a host pointer.  Validation errors as tns_build_tasklist; TNS_ERR_ARG for
+ * a null `ntasks`. */
+tns_status tns_count_tasks(const tns_problem *prob, int64_t *ntasks);
+
 /* Levels 1-2 of Section III.A.1 on the device: validates the problem on the
  * host (shapes, ranges, quantum-number conservation of every block and every
  * term), copies the tables into `ws`, enumerates every (term, input sector)

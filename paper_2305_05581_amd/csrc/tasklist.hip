@@ -1285,6 +1285,15 @@ size_t tns::plan_workspace(const tns_problem *P, int32_t nmax, int32_t maxdim, i
   return layout(P, nmax, maxdim, device_cu_count(), device_xcd_count(), nullptr, nullptr, nx_explicit, backward);
 }
 
+extern "C" tns_status tns_count_tasks(const tns_problem *prob, int64_t *ntasks) {
+  if (!ntasks) return TNS_ERR_ARG;
+  int32_t nmax = 0, maxdim = 0;
+  const tns_status s = validate(prob, &nmax, &maxdim);
+  if (s != TNS_OK) return s;
+  *ntasks = host_task_count(prob, nmax);
+  return TNS_OK;
+}
+
 extern "C" size_t tns_tasklist_workspace_bytes(const tns_problem *prob) {
   int32_t nmax = 0, maxdim = 0;
   if (validate(prob, &nmax, &maxdim) != TNS_OK) return 0;

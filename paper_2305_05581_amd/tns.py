@@ -87,7 +87,7 @@ class TnsSu2Plan(ctypes.Structure):
                 ("tl", TnsTasklist)]
 
 
-EXPORTS = ("tns_tasklist_workspace_bytes", "tns_build_tasklist", "tns_apply_workspace_bytes",
+EXPORTS = ("tns_tasklist_workspace_bytes", "tns_count_tasks", "tns_build_tasklist", "tns_apply_workspace_bytes",
            "tns_prepare_operands", "tns_apply_heff", "tns_backward_workspace_bytes", "tns_apply_heff_backward",
            "tns_davidson_workspace_bytes", "tns_davidson", "tns_status_string")
 
@@ -105,6 +105,8 @@ def library(path=LIB_PATH):
     sz = ctypes.c_size_t
     L.tns_tasklist_workspace_bytes.restype = sz
     L.tns_tasklist_workspace_bytes.argtypes = [ctypes.POINTER(TnsProblem)]
+    L.tns_count_tasks.restype = ctypes.c_int
+    L.tns_count_tasks.argtypes = [ctypes.POINTER(TnsProblem), ctypes.POINTER(ctypes.c_int64)]
     L.tns_build_tasklist.restype = ctypes.c_int
     L.tns_build_tasklist.argtypes = [ctypes.POINTER(TnsProblem), _P, sz, ctypes.POINTER(TnsTasklist), _P]
     L.tns_apply_workspace_bytes.restype = sz
@@ -239,6 +241,14 @@ def problem_struct(P, n_vals=None):
         host[name] = a
         setattr(cp, name, a.ctypes.data_as(ctypes.c_void_p) if a.size else None)
     return cp, host
+
+
+def count_tasks(P):
+    """Task count of a problem by the library's host rule (no device call)."""
+    cp, host = problem_struct(P)
+    n = ctypes.c_int64(-1)
+    _check(library().tns_count_tasks(ctypes.byref(cp), ctypes.byref(n)), "tns_count_tasks")
+    return int(n.value)
 
 
 def tasklist_workspace_bytes(P):

@@ -137,3 +137,26 @@ def test_ttcache_plan_sizes(lib_ok, base):
     tl[0] = P.nOps
     with pytest.raises(TnsError):
         ttcache_sizes(_with(P, term_L=tl), int(fp.sum()))
+
+
+@pytest.mark.parametrize("seed,gapped", [(7, False), (11, True), (23, False)])
+def test_host_task_count_matches_oracle(lib_ok, seed, gapped):
+    """The library's host task count (which sizes the build workspace and
+    which the device enumeration must reproduce) equals the length of the
+    oracle's task table of Eq. (2)."""
+    from paper_2305_05581_amd.tns import count_tasks
+    from oracle import heff as oheff
+    P = synthetic_problem(12, 12, 0, 48, 4, 12, 40, seed=seed, gapped=gapped)
+    tasks, _ = oheff.task_table(P)
+    assert len(tasks) > 0
+    assert count_tasks(P) == len(tasks)
+
+
+def test_host_task_count_degenerate_and_rejected(lib_ok, base):
+    from paper_2305_05581_amd.tns import TnsError, count_tasks
+    empty = _with(base, term_L=np.zeros(0, np.int32), term_ma=np.zeros(0, np.int32),
+                  term_mb=np.zeros(0, np.int32), term_R=np.zeros(0, np.int32), term_coef=np.zeros(0))
+    assert count_tasks(empty) == 0
+    bad = _with(base, term_ma=np.full_like(np.asarray(base.term_ma), 16))
+    with pytest.raises(TnsError):
+        count_tasks(bad)
